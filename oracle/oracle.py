@@ -1,0 +1,189 @@
+"""ctypes wrapper of the plain CPU FP64 oracle (npg_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  It shares no
+code with the GPU path; both consume the same seeded inputs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "npg_oracle.c")
+LIB = os.path.join(HERE, "libnpg_oracle.so")
+
+OK, E_ARG, E_RANGE, E_CAPACITY = 0, -1, -2, -3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        sig = {
+            "or_boundaries": (None, [I, P, P]),
+            "or_bin_dirs": (I, [P, I64, I, I, P]),
+            "or_splat": (I, [P, P, P, P, I64, I, I, P, P, I]),
+            "or_normalize_input": (None, [P, I64, I, I, P]),
+            "or_net_forward": (I, [P, C.c_size_t, P, I64, I, I, P]),
+            "or_conv2d": (None, [P, P, I, I, I, P, I, I, P]),
+            "or_build_cdf": (I, [P, I64, I, I, P, P, P, P]),
+            "or_sample": (I, [P, P, P, I64, I, I, P, P, I64, P, P, P]),
+            "or_eval_pdf": (I, [P, I64, I, I, P, P, I64, P]),
+            "or_build_tree": (I, [P, I64, C.c_uint32, I, P, P, P, P, P, I64, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def boundaries(W: int):
+    ex = np.empty(W, np.float32)
+    ey = np.empty(W, np.float32)
+    lib().or_boundaries(W, _p(ex), _p(ey))
+    return ex, ey
+
+
+def bin_dirs(dirs, H: int, W: int):
+    dirs = _c(dirs, np.float32)
+    out = np.empty(dirs.shape[0], np.int32)
+    rc = lib().or_bin_dirs(_p(dirs), dirs.shape[0], H, W, _p(out))
+    return rc, out
+
+
+def splat(dirs, w, leaf_off, H, W, perm=None, energy=None, count=None, accumulate=False,
+          want_count=True):
+    dirs = _c(dirs, np.float32)
+    w = _c(w, np.uint32)
+    leaf_off = _c(leaf_off, np.uint32)
+    L = leaf_off.shape[0] - 1
+    if energy is None:
+        energy = np.zeros((L, H, W), np.uint64)
+    if count is None and want_count:
+        count = np.zeros((L, H, W), np.uint32)
+    perm = None if perm is None else _c(perm, np.uint32)
+    rc = lib().or_splat(_p(dirs), _p(w), _p(perm), _p(leaf_off), L, H, W, _p(energy),
+                        _p(count), int(bool(accumulate)))
+    return rc, energy, count
+
+
+def normalize_input(energy):
+    energy = _c(energy, np.uint64)
+    L, H, W = energy.shape
+    x = np.empty((L, H, W), np.float64)
+    lib().or_normalize_input(_p(energy), L, H, W, _p(x))
+    return x
+
+
+def net_forward(model: bytes, x):
+    x = _c(x, np.float64)
+    L, H, W = x.shape
+    s = np.empty((L, H, W), np.float64)
+    buf = np.frombuffer(model, dtype=np.uint8)
+    rc = lib().or_net_forward(_p(buf), len(model), _p(x), L, H, W, _p(s))
+    return rc, s
+
+
+def conv2d(w, b, x):
+    """One conv layer: w [co,ci,k,k] f32, b [co] f32 or None, x [ci,H,W] f64."""
+    w = _c(w, np.float32)
+    co, ci, k, _ = w.shape
+    x = _c(x, np.float64)
+    _, H, W = x.shape
+    out = np.empty((co, H, W), np.float64)
+    bb = None if b is None else _c(b, np.float32)
+    lib().or_conv2d(_p(w), _p(bb), co, ci, k, _p(x), H, W, _p(out))
+    return out
+
+
+def build_cdf(s):
+    s = _c(s, np.float64)
+    L, H, W = s.shape
+    pdf = np.empty((L, H, W), np.float32)
+    marg = np.empty((L, H + 1), np.float32)
+    cond = np.empty((L, H, W + 1), np.float32)
+    total = np.empty(L, np.float64)
+    rc = lib().or_build_cdf(_p(s), L, H, W, _p(pdf), _p(marg), _p(cond), _p(total))
+    return rc, pdf, marg, cond, total
+
+
+def sample(pdf, marg, cond, leaf, u):
+    pdf = _c(pdf, np.float32)
+    marg = _c(marg, np.float32)
+    cond = _c(cond, np.float32)
+    L, H, W = pdf.shape
+    leaf = _c(leaf, np.uint32)
+    u = _c(u, np.float32)
+    n = leaf.shape[0]
+    d = np.empty((n, 3), np.float64)
+    p = np.empty(n, np.float32)
+    b = np.empty(n, np.uint32)
+    rc = lib().or_sample(_p(pdf), _p(marg), _p(cond), L, H, W, _p(leaf), _p(u), n, _p(d), _p(p), _p(b))
+    return rc, d, p, b
+
+
+def eval_pdf(pdf, leaf, dirs):
+    pdf = _c(pdf, np.float32)
+    L, H, W = pdf.shape
+    leaf = _c(leaf, np.uint32)
+    dirs = _c(dirs, np.float32)
+    n = leaf.shape[0]
+    out = np.empty(n, np.float32)
+    rc = lib().or_eval_pdf(_p(pdf), L, H, W, _p(leaf), _p(dirs), n, _p(out))
+    return rc, out
+
+
+def build_tree(pos, T: int = 8192, Dmax: int = 6, max_leaves: int | None = None):
+    pos = _c(pos, np.float32)
+    n = pos.shape[0]
+    if max_leaves is None:
+        max_leaves = max(1, n)
+    perm = np.empty(max(n, 1), np.uint32)
+    leaf_of = np.empty(max(n, 1), np.uint32)
+    off = np.zeros(max_leaves + 1, np.uint32)
+    key = np.zeros(max_leaves, np.uint64)
+    depth = np.zeros(max_leaves, np.uint8)
+    nl = C.c_int64(0)
+    rc = lib().or_build_tree(_p(pos), n, T, Dmax, _p(perm), _p(leaf_of), _p(off), _p(key),
+                             _p(depth), max_leaves, C.addressof(nl))
+    L = min(nl.value, max_leaves)
+    return rc, dict(perm=perm[:n], leaf_of=leaf_of[:n], leaf_off=off[:L + 1], key=key[:L],
+                    depth=depth[:L], n_leaves=nl.value)
+
+
+def pipeline(batch, want_tables=True):
+    """The full oracle chain on a leaf batch: splat -> normalise -> net -> CDF."""
+    rc, E, P = splat(batch.dirs, batch.w, batch.leaf_off, batch.H, batch.W)
+    assert rc == OK
+    x = normalize_input(E)
+    rc, s = net_forward(batch.model, x)
+    assert rc == OK
+    rc, pdf, marg, cond, total = build_cdf(s)
+    return dict(energy=E, count=P, x=x, s=s, pdf=pdf, marg=marg, cond=cond, total=total)

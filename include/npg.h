@@ -1,0 +1,249 @@
+/*
+ * npg.h -- C-ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of photon-driven neural path guiding (Zhu et al., "Photon-Driven
+ * Neural Path Guiding", arXiv 2010.01775):
+ *
+ *   photons -> leaves of an adaptive spatial hierarchy   npg_build_hierarchy
+ *   -> per-leaf 2D directional histograms                npg_splat_histograms
+ *   -> raw sampling map (normalised energy)              npg_normalize_input
+ *   -> CNN reconstruction of a sampling density          npg_reconstruct_density
+ *   -> pdf + marginal/conditional CDF tables             npg_build_cdf
+ *   -> guided direction sampling / pdf evaluation        npg_sample_dirs, npg_eval_pdf
+ *
+ * Conventions (all entry points):
+ *  - Pointers whose names end in _dev are device pointers OWNED BY THE CALLER
+ *    (for instance memory of torch tensors).  The library never frees or
+ *    reallocates them.  It allocates only its own scratch space and model
+ *    weights, charged against the context's HBM budget.
+ *  - Every call takes the caller's stream (a hipStream_t passed as void*,
+ *    NULL = the default stream), only enqueues work and returns without
+ *    waiting, except where a call says it synchronises.  Calls on one context
+ *    must be issued from one host thread at a time and, when they share the
+ *    context's scratch space, in one stream order (use one context per
+ *    concurrently used stream).
+ *  - Return value: NPG_OK (0) or a negative code.  Argument errors (null
+ *    pointers, sizes out of range) are detected on the host before anything
+ *    is enqueued.  Data-dependent errors (a direction that is not finite, a
+ *    position outside the unit box, a leaf id >= L, a uniform outside [0,1))
+ *    are raised by the kernels into a device error word; the offending
+ *    outputs are written as documented per call, and npg_sync_status reports
+ *    and clears the word.  npg_last_error returns a message for the last
+ *    failing call.
+ *  - Map sizes H (rows, z) and W (columns, azimuth) are powers of two in
+ *    [4, 1024].  Per-leaf maps are stored row-major [leaf][z row][phi column].
+ */
+#ifndef NPG_H
+#define NPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NPG_OK 0
+#define NPG_E_ARG -1      /* invalid argument (null pointer, bad size, bad model)   */
+#define NPG_E_RANGE -2    /* data-dependent input out of range (see each call)      */
+#define NPG_E_CAPACITY -3 /* more leaves than the caller's capacity                 */
+#define NPG_E_BUDGET -4   /* scratch space would exceed the context's HBM budget    */
+#define NPG_E_HIP -5      /* a HIP runtime call failed                              */
+
+typedef struct npg_ctx npg_ctx;
+typedef struct npg_model npg_model;
+
+/* Arithmetic of the network's convolutions.  Inputs, normalisation, the
+ * per-leaf totals and the CDF prefixes are FP64/FP32 in every mode. */
+typedef enum {
+  NPG_FP32 = 0, /* FP32 operands, FP32 accumulation                         */
+  NPG_BF16 = 1, /* BF16 activations and weights, FP32 accumulation          */
+  NPG_FP8 = 2   /* FP8 e4m3 (OCP) with static per-layer scales, FP32 accum.  */
+} npg_precision;
+
+/* Device pointers of a batch of per-leaf CDF tables (as written by
+ * npg_build_cdf).  pdf [L][H][W] (1/sr), marg [L][H+1], cond [L][H][W+1],
+ * total [L] (FP64 sum of the density, may be NULL for sampling). */
+typedef struct {
+  const float *pdf_dev;
+  const float *marg_dev;
+  const float *cond_dev;
+  const double *total_dev;
+  uint32_t L;
+  int32_t H;
+  int32_t W;
+} npg_tables;
+
+/* Octree parameters (Sec. 7.1 "Voxel subdivision": split a voxel while its
+ * photon count exceeds a threshold, recursively, with a depth cap). */
+typedef struct {
+  uint32_t split_count; /* a cell splits iff its count > split_count ...      */
+  int32_t max_depth;    /* ... and its depth < max_depth; 0 <= max_depth <= 8  */
+} npg_hier_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * scratch space and model weights the library itself allocates on that
+ * device (0 = no bound).  *out is set on success. */
+int npg_create(npg_ctx **out, int device, uint64_t hbm_budget_bytes);
+
+/* Waits for nothing; frees the context's scratch space.  The caller must
+ * have synchronised every stream it used with the context. */
+void npg_destroy(npg_ctx *ctx);
+
+/* Message of the last failing call on ctx ("" if none).  Valid until the
+ * next call on ctx. */
+const char *npg_last_error(const npg_ctx *ctx);
+
+/* Synchronises `stream`, then returns NPG_E_RANGE if any kernel launched
+ * with ctx flagged a data-dependent error since the previous check (and
+ * clears the flag), NPG_E_HIP if the stream reports a fault, else NPG_OK. */
+int npg_sync_status(npg_ctx *ctx, void *stream);
+
+/* Bytes of device memory the library currently holds for ctx (scratch) and
+ * the high-water mark. */
+void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak);
+
+/* ------------------------------------------------------------------ model */
+
+/* Loads a network from an NPGW v1 weight file held in host memory:
+ *   'NPGW' | u32 version = 1 | u32 arch | u32 levels | u32 n_layers |
+ *   per layer: u32 cout, u32 cin, u32 k, f32 w[cout][cin][k][k], f32 b[cout]
+ * (little endian).  arch 1 = chain of 3x3 convolutions, ReLU between them,
+ * softplus after the last, 1 input and 1 output channel.  arch 2 = U-Net
+ * with `levels` resolution levels: encoder level d = two 3x3 conv + ReLU on
+ * the 2x2-average-pooled output of level d-1; decoder level d = two 3x3
+ * conv + ReLU on [nearest x2 upsample of level d+1, skip of level d];
+ * head = 1x1 conv to one channel + softplus (the compact U-Net of Sec. 6.1,
+ * whose published figure and weights are not available, so the file's
+ * weights are stand-ins).  Zero padding.  The host buffer is not retained.
+ * Weights are repacked on the device for FP32 and BF16; FP8 needs
+ * npg_model_calibrate_fp8 first.  NPG_E_ARG for a malformed file. */
+int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_bytes, npg_model **out);
+void npg_model_free(npg_model *model);
+
+/* Sets the static FP8 scales of a model from a calibration batch: per-layer
+ * weight scales from the weight amax, activation scales from the amax of
+ * every layer input over the given energy maps (run in FP32).  Synchronises
+ * `stream`.  Scales stay fixed afterwards, so a leaf's FP8 result does not
+ * depend on the other leaves of a batch. */
+int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *model, const uint64_t *energy_dev,
+                            uint32_t L, int H, int W, void *stream);
+
+/* ------------------------------------------------------------- hot path */
+
+/* Assigns photons to the leaves of an adaptive octree over the unit box
+ * (Sec. 7.1 "Voxel subdivision"; Algorithm 1, subdivision step).  The root
+ * [0,1)^3 has depth 0; a cell splits into its 8 midpoint octants iff its
+ * photon count > split_count and its depth < max_depth.  Leaves are the
+ * unsplit cells holding at least one photon, numbered in ascending Morton
+ * order (x in the lowest bit of each bit triple).
+ *   pos_dev        [n][3] float32 positions, each coordinate in [0, 1)
+ *   perm_dev       [n] out: photon indices grouped by leaf; within a leaf in
+ *                  input order (stable), so leaf l owns perm[off[l]..off[l+1])
+ *   leaf_of_dev    [n] out: leaf id of each photon (input order); may be NULL
+ *   leaf_off_dev   [max_leaves+1] out: CSR offsets into perm
+ *   leaf_key_dev   [max_leaves] out: Morton code of the leaf cell's lowest
+ *                  corner on the 2^21 lattice (63 bits); may be NULL
+ *   leaf_depth_dev [max_leaves] out: depth of the leaf cell; may be NULL
+ *   n_leaves_out   host out: number of leaves L
+ * Synchronises `stream` (L is read back).  A position outside [0,1)^3 or
+ * not finite returns NPG_E_RANGE (outputs unspecified).  L > max_leaves
+ * returns NPG_E_CAPACITY with *n_leaves_out = L (nothing past max_leaves
+ * is written).  n <= 2^32 - 1. */
+int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n, const npg_hier_params *params,
+                        uint32_t *perm_dev, uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,
+                        uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev, uint32_t max_leaves,
+                        uint32_t *n_leaves_out, void *stream);
+
+/* Bins photons into per-leaf energy and count maps (Eq. "photon": the
+ * energy of bin k of voxel j is the sum of the energies of the voxel's
+ * photons whose direction falls in bin k; plus the photon count per bin,
+ * an input channel of Sec. 6).  Direction -> bin is the exact equal-area
+ * rule: row iz = #{b in 1..H-1 : z >= -1 + 2b/H}; column = azimuth sector
+ * bounded by the rays e_b = Rot90^q(RN32(cos t), RN32(sin t)),
+ * t = 2 pi r / W, b = q W/4 + r, tested with exact FP64 cross products
+ * (x = y = 0 -> column 0).  Directions need not be normalised.
+ *   dir_dev      [N][3] float32 directions;  w_dev [N] uint32 photon energy
+ *                in fixed point (units of 2^-16; any value)
+ *   perm_dev     NULL: leaf l owns photons leaf_off[l]..leaf_off[l+1]-1;
+ *                else it owns photons perm[leaf_off[l]..leaf_off[l+1]-1]
+ *   leaf_off_dev [L+1] CSR offsets (non-decreasing)
+ *   energy_dev   [L][H][W] uint64 out (exact integer sums)
+ *   count_dev    [L][H][W] uint32 out, or NULL
+ *   accumulate   0: overwrite the maps; 1: add to them (progressive
+ *                accumulation over iterations, Sec. 5)
+ * Integer sums make the result independent of photon order and chunking.
+ * A non-finite direction flags NPG_E_RANGE and the photon is skipped. */
+int npg_splat_histograms(npg_ctx *ctx, const float *dir_dev, const uint32_t *w_dev,
+                         const uint32_t *perm_dev, const uint32_t *leaf_off_dev, uint32_t L,
+                         int H, int W, uint64_t *energy_dev, uint32_t *count_dev, int accumulate,
+                         void *stream);
+
+/* Raw sampling map fed to the network (Sec. 7.2: the accumulated energy
+ * map is normalised): x = H*W*E / sum(E) computed in FP64 and stored as
+ * float32 (mean 1); an all-zero leaf gives a zero map.
+ *   energy_dev [L][H][W] uint64;  x_dev [L][H][W] float32 out. */
+int npg_normalize_input(npg_ctx *ctx, const uint64_t *energy_dev, uint32_t L, int H, int W,
+                        float *x_dev, void *stream);
+
+/* Reconstructs the sampling density of every leaf with the network
+ * (Sec. 6: S_d = F(S_e); the raw map S_e is the normalised energy map as in
+ * npg_normalize_input, computed on the fly).
+ *   energy_dev  [L][H][W] uint64;  count_dev: reserved for the count input
+ *               channels of the paper's five-channel network, may be NULL
+ *   density_dev [L][H][W] float32 out, softplus output (>= 0)
+ * A U-Net needs H and W divisible by 2^(levels-1).  Leaves are processed
+ * in chunks that fit the context's budget; NPG_E_BUDGET if not even one
+ * leaf fits.  NPG_E_ARG for NPG_FP8 on an uncalibrated model. */
+int npg_reconstruct_density(npg_ctx *ctx, const npg_model *model, const uint64_t *energy_dev,
+                            const uint32_t *count_dev, uint32_t L, int H, int W,
+                            npg_precision precision, float *density_dev, void *stream);
+
+/* Sampling pdf and CDF tables of each leaf (Eq. "energy_target": the guide
+ * pdf is proportional to the map value over the bin's solid angle; Sec. 7.3:
+ * a CDF from a cumulative sum over pixels, sampled like an environment map).
+ *   p_k = s_k / S, S = sum_k s_k in FP64;  pdf_k = p_k H W / (4 pi)  [1/sr]
+ *   marg: M_0 = 0, M_i = sum_{i'<i} sum_j p_{i',j}, M_H = 1
+ *   cond: C_{i,0} = 0, C_{i,j} = sum_{j'<j} p_{i,j'} / m_i, C_{i,W} = 1,
+ *         a row with m_i = 0 gets C_{i,j} = j/W
+ * Prefixes in FP64, stored as float32.
+ *   density_dev [L][H][W] float32 (>= 0);  pdf_dev [L][H][W] out;
+ *   marg_dev [L][H+1] out;  cond_dev [L][H][W+1] out;  total_dev [L] out
+ *   (FP64 S; may be NULL)
+ * A leaf whose density has a negative or non-finite value or sums to zero
+ * flags NPG_E_RANGE; its tables are written as NaN and its total as 0. */
+int npg_build_cdf(npg_ctx *ctx, const float *density_dev, uint32_t L, int H, int W, float *pdf_dev,
+                  float *marg_dev, float *cond_dev, double *total_dev, void *stream);
+
+/* Guided direction sampling (Algorithm 1, guided-sampling step): for query
+ * q with leaf l and uniforms (u1, u2) in [0,1):
+ *   row i = max{i in [0,H-1] : M_i <= u1}, column j = max{j : C_{i,j} <= u2},
+ *   t1 = (u1 - M_i)/(M_{i+1} - M_i), t2 likewise (clamped to [0,1)),
+ *   z = -1 + 2(i + t1)/H, phi = 2 pi (j + t2)/W,
+ *   dir = (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi, z), pdf = pdf[l][i][j].
+ *   leaf_dev [n] uint32;  u_dev [n][2] float32
+ *   dir_out_dev [n][3] float32 out;  pdf_out_dev [n] float32 out;
+ *   bin_out_dev [n] uint32 out (i*W + j) or NULL
+ * leaf >= L or a uniform outside [0,1) flags NPG_E_RANGE; that query's
+ * direction and pdf are NaN and its bin 0xffffffff. */
+int npg_sample_dirs(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf_dev,
+                    const float *u_dev, uint64_t n, float *dir_out_dev, float *pdf_out_dev,
+                    uint32_t *bin_out_dev, void *stream);
+
+/* pdf of directions under their leaf's map: pdf[l][bin(dir)], with the bin
+ * rule of npg_splat_histograms (the guide term of the one-sample MIS pdf,
+ * Eq. "mis_coef").
+ *   leaf_dev [n];  dir_dev [n][3] float32;  pdf_out_dev [n] float32 out
+ * leaf >= L or a non-finite direction flags NPG_E_RANGE; pdf 0 there. */
+int npg_eval_pdf(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf_dev,
+                 const float *dir_dev, uint64_t n, float *pdf_out_dev, void *stream);
+
+/* The float32 boundary rays of a W-column map, (x, y) pairs for b = 0..W-1,
+ * as the kernels use them (host memory out, 2*W floats). */
+int npg_bin_boundaries(int W, float *xy_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NPG_H */

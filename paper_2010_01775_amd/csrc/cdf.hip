@@ -1,0 +1,145 @@
+// pdf and marginal/conditional CDF tables of each leaf's density.
+//
+// One workgroup (4 wavefronts) per leaf.  Every sum and prefix is formed in
+// binary64 and only the stored tables are rounded to float32:
+//   S = sum s;  p = s / S;  pdf = p*H*W/(4 pi)
+//   row mass m_i = sum_j p_ij, marginal M_i = sum_{i'<i} m_i' (M_H = 1)
+//   conditional C_ij = sum_{j'<j} p_ij' / m_i (C_iW = 1; j/W if m_i = 0)
+// A row is scanned by one wavefront: each lane takes a contiguous segment,
+// scans it serially, and a wavefront-wide exclusive scan of the segment
+// totals gives each lane its offset.
+#include <math.h>
+
+#include "npg_internal.h"
+
+namespace {
+
+constexpr int CDF_THREADS = 256;
+constexpr double FOUR_PI = 4.0 * M_PI;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// exclusive prefix over the 64 lanes
+__device__ __forceinline__ double wave_excl_scan(double v, int lane) {
+  double incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  return incl - v;
+}
+
+__global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restrict__ dens, int H, int W,
+                                                          float *__restrict__ pdf, float *__restrict__ marg,
+                                                          float *__restrict__ cond, double *__restrict__ total,
+                                                          uint32_t *err) {
+  extern __shared__ double rowmass[];  // [H]
+  __shared__ double red[4];
+  __shared__ int bad_s;
+  const int leaf = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t HW = (size_t)H * W;
+  const float *s = dens + leaf * HW;
+  if (tid == 0) bad_s = 0;
+  __syncthreads();
+  // total S
+  double acc = 0.0;
+  int bad = 0;
+  for (size_t k = tid; k < HW; k += CDF_THREADS) {
+    const float v = s[k];
+    if (!(v >= 0.0f) || !isfinite(v)) bad = 1;
+    acc += (double)v;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) red[wave] = acc;
+  if (bad) atomicOr(&bad_s, 1);
+  __syncthreads();
+  const double S = red[0] + red[1] + red[2] + red[3];
+  float *pl = pdf + leaf * HW;
+  float *ml = marg + (size_t)leaf * (H + 1);
+  float *cl = cond + (size_t)leaf * H * (W + 1);
+  if (bad_s || !(S > 0.0) || !isfinite(S)) {
+    const float qnan = __int_as_float(0x7fc00000);
+    for (size_t k = tid; k < HW; k += CDF_THREADS) pdf[leaf * HW + k] = qnan;
+    for (int k = tid; k <= H; k += CDF_THREADS) ml[k] = qnan;
+    for (size_t k = tid; k < (size_t)H * (W + 1); k += CDF_THREADS) cl[k] = qnan;
+    if (tid == 0) {
+      if (total) total[leaf] = 0.0;
+      raise_err(err, ERR_RANGE);
+    }
+    return;
+  }
+  const double pdf_scale = (double)HW;
+  // rows: one wavefront per row
+  const int seg = (W + 63) / 64;  // elements per lane
+  for (int i = wave; i < H; i += 4) {
+    const float *srow = s + (size_t)i * W;
+    const int j0 = lane * seg;
+    double part = 0.0;
+    for (int t = 0; t < seg; ++t) {
+      const int j = j0 + t;
+      if (j < W) {
+        const double p = (double)srow[j] / S;
+        pl[(size_t)i * W + j] = (float)(p * pdf_scale / FOUR_PI);
+        part += p;
+      }
+    }
+    const double m = wave_sum(part);
+    const double before = wave_excl_scan(part, lane);
+    float *crow = cl + (size_t)i * (W + 1);
+    if (m > 0.0) {
+      double c = before;
+      for (int t = 0; t < seg; ++t) {
+        const int j = j0 + t;
+        if (j < W) {
+          crow[j] = (float)(c / m);
+          c += (double)srow[j] / S;
+        }
+      }
+    } else {
+      for (int t = 0; t < seg; ++t) {
+        const int j = j0 + t;
+        if (j < W) crow[j] = (float)((double)j / (double)W);
+      }
+    }
+    if (lane == 0) {
+      crow[W] = 1.0f;
+      rowmass[i] = m;
+    }
+  }
+  __syncthreads();
+  // marginal over rows (wavefront 0)
+  if (wave == 0) {
+    const int rseg = (H + 63) / 64;
+    const int i0 = lane * rseg;
+    double part = 0.0;
+    for (int t = 0; t < rseg; ++t)
+      if (i0 + t < H) part += rowmass[i0 + t];
+    double c = wave_excl_scan(part, lane);
+    for (int t = 0; t < rseg; ++t) {
+      const int i = i0 + t;
+      if (i < H) {
+        ml[i] = (float)c;
+        c += rowmass[i];
+      }
+    }
+    if (lane == 0) {
+      ml[H] = 1.0f;
+      if (total) total[leaf] = S;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_build_cdf(const float *density, uint32_t L, int H, int W, float *pdf, float *marg,
+                            float *cond, double *total, uint32_t *err, hipStream_t s) {
+  hipLaunchKernelGGL(cdf_kernel, dim3(L), dim3(CDF_THREADS), sizeof(double) * H, s, density, H, W, pdf,
+                     marg, cond, total, err);
+  return hipGetLastError();
+}

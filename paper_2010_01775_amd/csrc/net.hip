@@ -1,0 +1,802 @@
+// Network evaluation: weight-file loading and repacking, the convolution
+// kernels, and the per-chunk CNN / U-Net schedule.
+//
+// Activations are channel-last per leaf, [leaf][y][x][c].  3x3 convolutions
+// with at least 16 output channels run as implicit GEMMs on the matrix cores
+// (v_mfma_f32_16x16x4f32 for FP32, v_mfma_f32_16x16x32_bf16 for BF16):
+//   M = output pixels of a tile, N = output channels, K = 9 taps x input
+//   channels.
+// A workgroup (4 wavefronts) owns a tile of 64*MW pixels (rows of one leaf)
+// and all output channels.  For each chunk of KC input channels it stages
+// the tile's input patch with a one-pixel halo in LDS, plus the chunk's
+// weights, and the nine taps read shifted windows of the patch, so each
+// input element is fetched from memory once per chunk.  The 2x2 average pool
+// (encoder) and the nearest upsample + skip concatenation (decoder) are
+// folded into the patch loads; bias and ReLU into the epilogue; the 1x1 head
+// and softplus into the epilogue of the last decoder convolution.  The first
+// layer (one input channel) and any layer the tiling does not fit run as a
+// direct convolution; the first layer computes the normalised input map
+// from the energy map on the fly.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "npg_internal.h"
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ model
+struct LayerDev {
+  int cout = 0, cin = 0, k = 0;
+  float *w = nullptr;          // OIHW float32
+  float *b = nullptr;          // [cout]
+  float *pk32 = nullptr;       // [chunk][tap][kc16][cout]
+  uint16_t *pk16 = nullptr;    // [chunk][tap][cout][kc32] (bf16 bits)
+};
+
+struct npg_model {
+  npg_ctx *ctx = nullptr;
+  int arch = 0, levels = 0;
+  std::vector<LayerDev> layer;
+  std::vector<std::vector<float>> host_w, host_b;
+  void *blob = nullptr;  // one device allocation holding every array
+  size_t blob_bytes = 0;
+  bool fp8_ready = false;
+};
+
+namespace {
+
+uint32_t rd32(const unsigned char *p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+uint16_t f32_to_bf16_host(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+constexpr int KC32 = 16;  // input channels per chunk, FP32 path
+constexpr int KC16 = 32;  // input channels per chunk, BF16 path
+
+}  // namespace
+
+// Parses the NPGW v1 file and checks the declared topology.
+static int parse_model(npg_ctx *ctx, const unsigned char *buf, size_t len, npg_model *m) {
+  if (len < 20 || memcmp(buf, "NPGW", 4) != 0 || rd32(buf + 4) != 1)
+    return npg_fail(ctx, NPG_E_ARG, "model: not an NPGW v1 file");
+  m->arch = (int)rd32(buf + 8);
+  m->levels = (int)rd32(buf + 12);
+  const int n = (int)rd32(buf + 16);
+  if (n <= 0 || n > 256) return npg_fail(ctx, NPG_E_ARG, "model: bad layer count %d", n);
+  size_t o = 20;
+  m->layer.resize(n);
+  m->host_w.resize(n);
+  m->host_b.resize(n);
+  for (int i = 0; i < n; ++i) {
+    if (o + 12 > len) return npg_fail(ctx, NPG_E_ARG, "model: truncated");
+    LayerDev &y = m->layer[i];
+    y.cout = (int)rd32(buf + o);
+    y.cin = (int)rd32(buf + o + 4);
+    y.k = (int)rd32(buf + o + 8);
+    o += 12;
+    if (y.cout <= 0 || y.cin <= 0 || y.cout > 4096 || y.cin > 4096 || (y.k != 1 && y.k != 3))
+      return npg_fail(ctx, NPG_E_ARG, "model: bad layer %d shape", i);
+    const size_t nw = (size_t)y.cout * y.cin * y.k * y.k;
+    if (o + 4 * (nw + y.cout) > len) return npg_fail(ctx, NPG_E_ARG, "model: truncated weights");
+    m->host_w[i].resize(nw);
+    m->host_b[i].resize(y.cout);
+    memcpy(m->host_w[i].data(), buf + o, 4 * nw);
+    o += 4 * nw;
+    memcpy(m->host_b[i].data(), buf + o, 4 * (size_t)y.cout);
+    o += 4 * (size_t)y.cout;
+  }
+  if (o != len) return npg_fail(ctx, NPG_E_ARG, "model: %zu trailing bytes", len - o);
+  if (m->arch == 1) {
+    int c = 1;
+    for (int i = 0; i < n; ++i) {
+      if (m->layer[i].cin != c || m->layer[i].k != 3) return npg_fail(ctx, NPG_E_ARG, "model: CNN layer %d", i);
+      c = m->layer[i].cout;
+    }
+    if (c != 1) return npg_fail(ctx, NPG_E_ARG, "model: CNN must end with one channel");
+  } else if (m->arch == 2) {
+    const int D = m->levels;
+    if (D < 1 || D > 10 || n != 4 * D - 1) return npg_fail(ctx, NPG_E_ARG, "model: U-Net layer count");
+    int prev = 1;
+    for (int d = 0; d < D; ++d) {
+      const LayerDev &a = m->layer[2 * d], &b = m->layer[2 * d + 1];
+      if (a.cin != prev || a.k != 3 || b.cin != a.cout || b.cout != a.cout || b.k != 3)
+        return npg_fail(ctx, NPG_E_ARG, "model: U-Net encoder level %d", d);
+      prev = a.cout;
+    }
+    int li = 2 * D;
+    for (int d = D - 2; d >= 0; --d) {
+      const int cd = m->layer[2 * d].cout, cu = m->layer[2 * (d + 1)].cout;
+      const LayerDev &a = m->layer[li], &b = m->layer[li + 1];
+      if (a.cin != cu + cd || a.cout != cd || a.k != 3 || b.cin != cd || b.cout != cd || b.k != 3)
+        return npg_fail(ctx, NPG_E_ARG, "model: U-Net decoder level %d", d);
+      li += 2;
+    }
+    const LayerDev &h = m->layer[li];
+    if (h.k != 1 || h.cout != 1 || h.cin != m->layer[0].cout)
+      return npg_fail(ctx, NPG_E_ARG, "model: U-Net head");
+  } else {
+    return npg_fail(ctx, NPG_E_ARG, "model: unknown arch %d", m->arch);
+  }
+  return NPG_OK;
+}
+
+extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_bytes, npg_model **out) {
+  if (!ctx || !out) return NPG_E_ARG;
+  *out = nullptr;
+  if (!host_bytes) return npg_fail(ctx, NPG_E_ARG, "model: null buffer");
+  npg_model *m = new npg_model();
+  m->ctx = ctx;
+  int rc = parse_model(ctx, static_cast<const unsigned char *>(host_bytes), n_bytes, m);
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  // host-side repacking into one blob
+  std::vector<char> blob;
+  struct Off { size_t w, b, p32, p16; };
+  std::vector<Off> offs(m->layer.size());
+  auto put = [&](const void *src, size_t bytes) {
+    size_t at = npg_align(blob.size());
+    blob.resize(at + npg_align(bytes));
+    memcpy(blob.data() + at, src, bytes);
+    return at;
+  };
+  for (size_t i = 0; i < m->layer.size(); ++i) {
+    const LayerDev &y = m->layer[i];
+    const std::vector<float> &w = m->host_w[i];
+    offs[i].w = put(w.data(), 4 * w.size());
+    offs[i].b = put(m->host_b[i].data(), 4 * (size_t)y.cout);
+    offs[i].p32 = offs[i].p16 = (size_t)-1;
+    if (y.k == 3) {
+      const int nch32 = (y.cin + KC32 - 1) / KC32, nch16 = (y.cin + KC16 - 1) / KC16;
+      std::vector<float> p32((size_t)nch32 * 9 * KC32 * y.cout, 0.0f);
+      std::vector<uint16_t> p16((size_t)nch16 * 9 * y.cout * KC16, 0);
+      for (int co = 0; co < y.cout; ++co)
+        for (int ci = 0; ci < y.cin; ++ci)
+          for (int t = 0; t < 9; ++t) {
+            const float v = w[((size_t)co * y.cin + ci) * 9 + t];
+            const int c32 = ci / KC32, k32 = ci % KC32;
+            p32[(((size_t)c32 * 9 + t) * KC32 + k32) * y.cout + co] = v;
+            const int c16 = ci / KC16, k16 = ci % KC16;
+            p16[(((size_t)c16 * 9 + t) * y.cout + co) * KC16 + k16] = f32_to_bf16_host(v);
+          }
+      offs[i].p32 = put(p32.data(), 4 * p32.size());
+      offs[i].p16 = put(p16.data(), 2 * p16.size());
+    }
+  }
+  rc = npg_set_device(ctx);
+  if (!rc) rc = npg_device_alloc(ctx, blob.size(), &m->blob);
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  m->blob_bytes = blob.size();
+  if (hipMemcpy(m->blob, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    npg_device_free(ctx, m->blob, m->blob_bytes);
+    delete m;
+    return npg_fail(ctx, NPG_E_HIP, "model: upload failed");
+  }
+  char *base = static_cast<char *>(m->blob);
+  for (size_t i = 0; i < m->layer.size(); ++i) {
+    LayerDev &y = m->layer[i];
+    y.w = reinterpret_cast<float *>(base + offs[i].w);
+    y.b = reinterpret_cast<float *>(base + offs[i].b);
+    if (offs[i].p32 != (size_t)-1) {
+      y.pk32 = reinterpret_cast<float *>(base + offs[i].p32);
+      y.pk16 = reinterpret_cast<uint16_t *>(base + offs[i].p16);
+    }
+  }
+  *out = m;
+  return NPG_OK;
+}
+
+extern "C" void npg_model_free(npg_model *m) {
+  if (!m) return;
+  if (m->ctx) {
+    (void)hipSetDevice(m->ctx->device);
+    npg_device_free(m->ctx, m->blob, m->blob_bytes);
+  }
+  delete m;
+}
+
+// ------------------------------------------------------------- kernels
+namespace {
+
+enum SrcMode : int { SRC_PLAIN = 0, SRC_POOL = 1, SRC_UPCAT = 2, SRC_ENERGY = 3 };
+enum Act : int { ACT_RELU = 0, ACT_SOFTPLUS = 1 };
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+
+template <class T> __device__ __forceinline__ float to_f(T v);
+template <> __device__ __forceinline__ float to_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_f<uint16_t>(uint16_t v) { return bf2f(v); }
+template <class T> __device__ __forceinline__ T from_f(float v);
+template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ uint16_t from_f<uint16_t>(float v) { return f2bf(v); }
+
+// Source tensors of one convolution's (virtual) input.
+struct Src {
+  int mode;
+  const void *s0;      // PLAIN: [L][H][W][C0]; POOL: [L][2H][2W][C0]; UPCAT: [L][H/2][W/2][C0];
+                       // ENERGY: uint64 [L][H][W]
+  const void *s1;      // UPCAT: skip [L][H][W][C1]
+  const double *tot;   // ENERGY: per-leaf energy totals
+  int C0, C1;
+};
+
+// One input element (leaf, y, x, c) as float; (y, x) inside the map.
+template <class T>
+__device__ __forceinline__ float src_at(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+  switch (s.mode) {
+    case SRC_ENERGY: {
+      const double t = s.tot[leaf];
+      const uint64_t e = static_cast<const uint64_t *>(s.s0)[((size_t)leaf * H + y) * W + x];
+      return t > 0.0 ? (float)((double)(H * W) * (double)e / t) : 0.0f;
+    }
+    case SRC_POOL: {
+      const T *p = static_cast<const T *>(s.s0);
+      const int W2 = 2 * W;
+      const size_t b = (((size_t)leaf * 2 * H + 2 * y) * W2 + 2 * x) * s.C0 + c;
+      return (to_f<T>(p[b]) + to_f<T>(p[b + s.C0]) + to_f<T>(p[b + (size_t)W2 * s.C0]) +
+              to_f<T>(p[b + (size_t)W2 * s.C0 + s.C0])) * 0.25f;
+    }
+    case SRC_UPCAT:
+      if (c < s.C0)
+        return to_f<T>(static_cast<const T *>(s.s0)[(((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c]);
+      return to_f<T>(static_cast<const T *>(s.s1)[(((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0)]);
+    default:
+      return to_f<T>(static_cast<const T *>(s.s0)[(((size_t)leaf * H + y) * W + x) * s.C0 + c]);
+  }
+}
+
+// Direct convolution, one thread per output pixel, FP32 arithmetic.
+// out: T [L][H][W][Cout] (ACT_RELU) or float [L][H][W] (ACT_SOFTPLUS, Cout 1).
+template <class T>
+__global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *__restrict__ w,
+                                                          const float *__restrict__ bias, int Cin, int Cout,
+                                                          int k, int H, int W, size_t npix, int act,
+                                                          void *out) {
+  const size_t pix = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (pix >= npix) return;
+  const int HW = H * W;
+  const int leaf = (int)(pix / HW);
+  const int rem = (int)(pix - (size_t)leaf * HW);
+  const int y = rem / W, x = rem - y * W;
+  const int r = k / 2;
+  for (int co0 = 0; co0 < Cout; co0 += 16) {
+    const int nco = min(16, Cout - co0);
+    float acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = j < nco ? bias[co0 + j] : 0.0f;
+    for (int ci = 0; ci < Cin; ++ci)
+      for (int ky = 0; ky < k; ++ky) {
+        const int sy = y + ky - r;
+        if (sy < 0 || sy >= H) continue;
+        for (int kx = 0; kx < k; ++kx) {
+          const int sx = x + kx - r;
+          if (sx < 0 || sx >= W) continue;
+          const float v = src_at<T>(src, leaf, sy, sx, ci, H, W);
+          const float *wp = w + ((size_t)co0 * Cin + ci) * k * k + ky * k + kx;
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (j < nco) acc[j] = fmaf(wp[(size_t)j * Cin * k * k], v, acc[j]);
+        }
+      }
+    if (act == ACT_SOFTPLUS) {
+      static_cast<float *>(out)[pix] = softplus_f(acc[0]);
+    } else {
+      T *o = static_cast<T *>(out) + pix * Cout + co0;
+      for (int j = 0; j < nco; ++j) o[j] = from_f<T>(fmaxf(acc[j], 0.0f));
+    }
+  }
+}
+
+// ---------------------------------------------------------- MFMA conv
+struct F32P {
+  using T = float;
+  static constexpr int KC = KC32, VEC = 4, PSTR = KC + 4;
+};
+struct BF16P {
+  using T = uint16_t;
+  static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8;
+};
+
+struct ConvArgs {
+  Src src;
+  int Cin, Cout, H, W, TW, TR, nchunk;
+  int tiles_x, tiles_per_leaf;
+  const void *wpk;
+  const float *bias;
+  const float *head_w;   // non-null: fuse the 1x1 head + softplus (Cout == 16)
+  float head_b;
+  void *out;
+};
+
+// 16 bytes of VEC channels starting at c, as raw bits.
+template <class P>
+__device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+  using T = typename P::T;
+  constexpr int VEC = P::VEC;
+  uint4 z = make_uint4(0, 0, 0, 0);
+  if (s.mode == SRC_PLAIN) {
+    if (c >= s.C0) return z;
+    return *reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) +
+                                            (((size_t)leaf * H + y) * W + x) * s.C0 + c);
+  }
+  if (s.mode == SRC_UPCAT) {
+    if (c < s.C0)
+      return *reinterpret_cast<const uint4 *>(
+          static_cast<const T *>(s.s0) + (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c);
+    if (c - s.C0 < s.C1)
+      return *reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s1) +
+                                              (((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0));
+    return z;
+  }
+  // SRC_POOL
+  if (c >= s.C0) return z;
+  const int W2 = 2 * W;
+  const T *p = static_cast<const T *>(s.s0) + (((size_t)leaf * 2 * H + 2 * y) * W2 + 2 * x) * s.C0 + c;
+  const size_t dr = (size_t)W2 * s.C0;
+  const uint4 a = *reinterpret_cast<const uint4 *>(p);
+  const uint4 b = *reinterpret_cast<const uint4 *>(p + s.C0);
+  const uint4 cc = *reinterpret_cast<const uint4 *>(p + dr);
+  const uint4 d = *reinterpret_cast<const uint4 *>(p + dr + s.C0);
+  const T *ta = reinterpret_cast<const T *>(&a), *tb = reinterpret_cast<const T *>(&b);
+  const T *tc = reinterpret_cast<const T *>(&cc), *td = reinterpret_cast<const T *>(&d);
+  uint4 r;
+  T *tr = reinterpret_cast<T *>(&r);
+#pragma unroll
+  for (int i = 0; i < VEC; ++i)
+    tr[i] = from_f<T>((to_f<T>(ta[i]) + to_f<T>(tb[i]) + to_f<T>(tc[i]) + to_f<T>(td[i])) * 0.25f);
+  return r;
+}
+
+template <class P, int MW, int NW>
+__global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
+  using T = typename P::T;
+  constexpr int KC = P::KC, VEC = P::VEC, PSTR = P::PSTR, G = KC / VEC;
+  constexpr int BN = 16 * NW;
+  constexpr bool IS_F32 = sizeof(T) == 4;
+  // FP32 B tile: [tap][kc][BNP], row stride chosen so the four k-rows a
+  // fragment read touches fall in different LDS banks.
+  constexpr int BNP = BN + ((16 - BN) & 63);
+  constexpr int KCP = KC + 8;  // BF16 B tile: [tap][n][KCP]
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int TW = a.TW, TR = a.TR, PW = TW + 2, PH = TR + 2;
+  T *patch = reinterpret_cast<T *>(smem);
+  const size_t patch_bytes = npg_align((size_t)PH * PW * PSTR * sizeof(T), 16);
+  T *wl = reinterpret_cast<T *>(smem + patch_bytes);
+
+  const int tile = blockIdx.x;
+  const int leaf = tile / a.tiles_per_leaf;
+  const int t = tile - leaf * a.tiles_per_leaf;
+  const int ty0 = (t / a.tiles_x) * TR, tx0 = (t - (t / a.tiles_x) * a.tiles_x) * TW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  int bp[MW];
+#pragma unroll
+  for (int mi = 0; mi < MW; ++mi) {
+    const int m = wave * 16 * MW + mi * 16 + lr;
+    bp[mi] = (m / TW) * PW + (m % TW);
+  }
+  f32x4 acc[MW][NW];
+#pragma unroll
+  for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int H = a.H, W = a.W;
+  for (int ch = 0; ch < a.nchunk; ++ch) {
+    const int c0 = ch * KC;
+    // input patch with halo
+    const int items = PH * PW * G;
+    for (int it = tid; it < items; it += 256) {
+      const int pp = it / G, g = it - pp * G;
+      const int py = pp / PW, px = pp - py * PW;
+      const int y = ty0 - 1 + py, x = tx0 - 1 + px;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (y >= 0 && y < H && x >= 0 && x < W) v = load_vec<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
+      *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v;
+    }
+    // weights of this chunk
+    const T *wg = static_cast<const T *>(a.wpk) + (size_t)ch * 9 * KC * BN;
+    if (IS_F32) {
+      constexpr int R4 = BN / 4;  // float4 per row
+      for (int it = tid; it < 9 * KC * R4; it += 256) {
+        const int row = it / R4, c4 = it - row * R4;
+        *reinterpret_cast<uint4 *>(wl + row * BNP + c4 * 4) =
+            *reinterpret_cast<const uint4 *>(wg + (size_t)row * BN + c4 * 4);
+      }
+    } else {
+      constexpr int R8 = KC / 8;  // 8 bf16 per row piece
+      for (int it = tid; it < 9 * BN * R8; it += 256) {
+        const int row = it / R8, c8 = it - row * R8;
+        *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * 8) =
+            *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * 8);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int toff = (tap / 3) * PW + (tap % 3);
+      if constexpr (IS_F32) {
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+          float av[MW], bv[NW];
+#pragma unroll
+          for (int mi = 0; mi < MW; ++mi)
+            av[mi] = reinterpret_cast<const float *>(patch)[(bp[mi] + toff) * PSTR + ks * 4 + lg];
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni)
+            bv[ni] = reinterpret_cast<const float *>(wl)[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
+#pragma unroll
+          for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NW; ++ni)
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+        }
+      } else {
+        bf16x8 av[MW], bv[NW];
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+          av[mi] = *reinterpret_cast<const bf16x8 *>(patch + (bp[mi] + toff) * PSTR + lg * 8);
+#pragma unroll
+        for (int ni = 0; ni < NW; ++ni)
+          bv[ni] = *reinterpret_cast<const bf16x8 *>(wl + (tap * BN + ni * 16 + lr) * KCP + lg * 8);
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: bias + ReLU (+ head)
+  if (a.head_w) {
+    const float bn = a.bias[lr];
+    const float hw = a.head_w[lr];
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = fmaxf(acc[mi][0][r] + bn, 0.0f) * hw;
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if (lr == r) {
+          const int m = wave * 16 * MW + mi * 16 + lg * 4 + r;
+          const int y = ty0 + m / TW, x = tx0 + m % TW;
+          static_cast<float *>(a.out)[((size_t)leaf * H + y) * W + x] = softplus_f(v + a.head_b);
+        }
+      }
+    return;
+  }
+  T *out = static_cast<T *>(a.out);
+#pragma unroll
+  for (int ni = 0; ni < NW; ++ni) {
+    const int n = ni * 16 + lr;
+    const float bn = a.bias[n];
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = wave * 16 * MW + mi * 16 + lg * 4 + r;
+        const int y = ty0 + m / TW, x = tx0 + m % TW;
+        out[(((size_t)leaf * H + y) * W + x) * a.Cout + n] = from_f<T>(fmaxf(acc[mi][ni][r] + bn, 0.0f));
+      }
+  }
+}
+
+// Tiling of a layer: returns false if the MFMA kernel does not fit it.
+struct Tiling {
+  int MW, NW, TW, TR;
+};
+
+bool pick_tiling(int Cout, int H, int W, Tiling *t) {
+  if (Cout % 16 || Cout > 128) return false;
+  const int NW = Cout / 16;
+  int MW = 4;
+  while (MW > 1 && (MW * NW > 16 || 64 * MW > H * W)) MW >>= 1;
+  if (64 * MW > H * W) return false;
+  const int BM = 64 * MW;
+  const int TW = std::min(W, BM);
+  const int TR = BM / TW;
+  if (TR > H || TW * TR != BM) return false;
+  t->MW = MW;
+  t->NW = NW;
+  t->TW = TW;
+  t->TR = TR;
+  return true;
+}
+
+template <class P>
+size_t conv_lds_bytes(const Tiling &t) {
+  using T = typename P::T;
+  const int BN = 16 * t.NW;
+  const size_t patch = npg_align((size_t)(t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
+  size_t wts;
+  if (sizeof(T) == 4) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(T);
+  else wts = (size_t)9 * BN * (P::KC + 8) * sizeof(T);
+  return patch + wts;
+}
+
+template <class P, int MW, int NW>
+hipError_t launch_mfma_t(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW>), dim3(tiles), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_mfma(const ConvArgs &a, const Tiling &t, unsigned tiles, hipStream_t s) {
+  const size_t lds = conv_lds_bytes<P>(t);
+  switch (t.NW * 10 + t.MW) {
+    case 11: return launch_mfma_t<P, 1, 1>(a, lds, tiles, s);
+    case 12: return launch_mfma_t<P, 2, 1>(a, lds, tiles, s);
+    case 14: return launch_mfma_t<P, 4, 1>(a, lds, tiles, s);
+    case 21: return launch_mfma_t<P, 1, 2>(a, lds, tiles, s);
+    case 22: return launch_mfma_t<P, 2, 2>(a, lds, tiles, s);
+    case 24: return launch_mfma_t<P, 4, 2>(a, lds, tiles, s);
+    case 41: return launch_mfma_t<P, 1, 4>(a, lds, tiles, s);
+    case 42: return launch_mfma_t<P, 2, 4>(a, lds, tiles, s);
+    case 44: return launch_mfma_t<P, 4, 4>(a, lds, tiles, s);
+    case 81: return launch_mfma_t<P, 1, 8>(a, lds, tiles, s);
+    case 82: return launch_mfma_t<P, 2, 8>(a, lds, tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- runner
+namespace {
+
+struct Runner {
+  npg_ctx *ctx;
+  const npg_model *m;
+  npg_precision prec;
+  hipStream_t s;
+  size_t esz;  // bytes per activation element
+  int force_direct = 0;
+
+  // One 3x3 conv (+ReLU) or the last layer (+head / softplus).
+  int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
+           int act) {
+    Tiling t;
+    const bool mfma_ok = !force_direct && y.k == 3 && src.mode != SRC_ENERGY && act == ACT_RELU &&
+                         (y.cin % 8 == 0) && pick_tiling(y.cout, H, W, &t) && (!head || y.cout == 16);
+    if (mfma_ok) {
+      ConvArgs a;
+      a.src = src;
+      a.Cin = y.cin;
+      a.Cout = y.cout;
+      a.H = H;
+      a.W = W;
+      a.TW = t.TW;
+      a.TR = t.TR;
+      a.tiles_x = W / t.TW;
+      a.tiles_per_leaf = (H / t.TR) * a.tiles_x;
+      a.bias = y.b;
+      a.head_w = head ? head->w : nullptr;
+      a.head_b = head ? m->host_b[&*head - &m->layer[0]][0] : 0.0f;
+      a.out = out;
+      const unsigned tiles = (unsigned)Lc * a.tiles_per_leaf;
+      hipError_t e;
+      if (prec == NPG_FP32) {
+        a.nchunk = (y.cin + KC32 - 1) / KC32;
+        a.wpk = y.pk32;
+        e = launch_mfma<F32P>(a, t, tiles, s);
+      } else {
+        a.nchunk = (y.cin + KC16 - 1) / KC16;
+        a.wpk = y.pk16;
+        e = launch_mfma<BF16P>(a, t, tiles, s);
+      }
+      if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "conv launch: %s", hipGetErrorString(e));
+      return NPG_OK;
+    }
+    // direct path; a fused head becomes a separate 1x1 direct layer
+    const size_t npix = (size_t)Lc * H * W;
+    void *dst = out;
+    if (head) {
+      // intermediate activation is written into the head's output region's
+      // companion buffer provided by the caller through `out` of this call:
+      return npg_fail(ctx, NPG_E_ARG, "internal: head fusion without MFMA tiling");
+    }
+    const unsigned blocks = (unsigned)((npix + 255) / 256);
+    if (prec == NPG_FP32)
+      hipLaunchKernelGGL(conv_direct_kernel<float>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
+                         y.cout, y.k, H, W, npix, act, dst);
+    else
+      hipLaunchKernelGGL(conv_direct_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b,
+                         y.cin, y.cout, y.k, H, W, npix, act, dst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "direct conv launch: %s", hipGetErrorString(e));
+    return NPG_OK;
+  }
+};
+
+Src plain(const void *p, int C) { return Src{SRC_PLAIN, p, nullptr, nullptr, C, 0}; }
+Src pooled(const void *p, int C) { return Src{SRC_POOL, p, nullptr, nullptr, C, 0}; }
+Src upcat(const void *lo, int Cu, const void *skip, int Cs) { return Src{SRC_UPCAT, lo, skip, nullptr, Cu, Cs}; }
+
+}  // namespace
+
+extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
+                                       const uint32_t *count_dev, uint32_t L, int H, int W,
+                                       npg_precision precision, float *density_dev, void *stream) {
+  (void)count_dev;
+  if (!ctx) return NPG_E_ARG;
+  if (!m) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null model");
+  if (!pow2_in(H, 4, 1024) || !pow2_in(W, 4, 1024))
+    return npg_fail(ctx, NPG_E_ARG, "reconstruct: bad H=%d W=%d", H, W);
+  if (precision != NPG_FP32 && precision != NPG_BF16 && precision != NPG_FP8)
+    return npg_fail(ctx, NPG_E_ARG, "reconstruct: bad precision %d", (int)precision);
+  if (precision == NPG_FP8 && !m->fp8_ready)
+    return npg_fail(ctx, NPG_E_ARG, "reconstruct: FP8 needs npg_model_calibrate_fp8 first");
+  if (precision == NPG_FP8) return npg_fail(ctx, NPG_E_ARG, "reconstruct: FP8 not available");
+  if (m->arch == 2) {
+    const int f = 1 << (m->levels - 1);
+    if (H % f || W % f || H / f < 1 || W / f < 1)
+      return npg_fail(ctx, NPG_E_ARG, "reconstruct: %dx%d not divisible by 2^%d", H, W, m->levels - 1);
+  }
+  if (L == 0) return NPG_OK;
+  if (!energy_dev || !density_dev) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null pointer");
+  int rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Runner R{ctx, m, precision, s, precision == NPG_FP32 ? (size_t)4 : (size_t)2};
+  if (const char *e = getenv("NPG_FORCE_DIRECT")) R.force_direct = atoi(e);
+  const size_t HW = (size_t)H * W;
+
+  // activation bytes per leaf
+  size_t per_leaf = 0;
+  std::vector<size_t> skip_elems;
+  size_t tmp_elems = 0;
+  if (m->arch == 1) {
+    for (const LayerDev &y : m->layer) tmp_elems = std::max(tmp_elems, (size_t)y.cout * HW);
+    per_leaf = 2 * npg_align(tmp_elems * R.esz, 64);
+  } else {
+    const int D = m->levels;
+    for (int d = 0; d < D; ++d) {
+      const size_t e = (size_t)m->layer[2 * d].cout * (HW >> (2 * d));
+      tmp_elems = std::max(tmp_elems, e);
+      if (d < D - 1) skip_elems.push_back(e);
+    }
+    for (size_t e : skip_elems) per_leaf += npg_align(e * R.esz, 64);
+    per_leaf += 2 * npg_align(tmp_elems * R.esz, 64);
+  }
+  size_t chunk = 1024;
+  if (const char *e = getenv("NPG_CHUNK_LEAVES")) chunk = std::max(1, atoi(e));
+  chunk = std::min<size_t>(chunk, L);
+  const size_t fixed = npg_align(sizeof(double) * L) + (16u << 20);
+  if (ctx->budget) {
+    const uint64_t others = ctx->held - ctx->scratch_bytes;
+    const uint64_t avail = ctx->budget > others ? ctx->budget - others : 0;
+    if (avail < fixed + per_leaf) return npg_fail(ctx, NPG_E_BUDGET, "reconstruct: budget too small for one leaf");
+    chunk = std::min<size_t>(chunk, (avail - fixed) / per_leaf);
+  }
+  void *scr = nullptr;
+  rc = npg_scratch(ctx, fixed + chunk * per_leaf, s, &scr);
+  if (rc) return rc;
+  Carver cv(scr);
+  double *tot = cv.take<double>(L);
+  std::vector<char *> skip;
+  for (size_t e : skip_elems) skip.push_back(cv.take<char>(chunk * e * R.esz));
+  char *tA = cv.take<char>(chunk * tmp_elems * R.esz);
+  char *tB = cv.take<char>(chunk * tmp_elems * R.esz);
+  NPG_HIP_CHECK(ctx, launch_leaf_scale(energy_dev, L, (int)HW, tot, s));
+
+  for (size_t l0 = 0; l0 < L; l0 += chunk) {
+    const int Lc = (int)std::min<size_t>(chunk, L - l0);
+    const Src in{SRC_ENERGY, energy_dev + l0 * HW, nullptr, tot + l0, 0, 0};
+    float *dens = density_dev + l0 * HW;
+    if (m->arch == 1) {
+      const int n = (int)m->layer.size();
+      Src cur = in;
+      char *bufs[2] = {tA, tB};
+      for (int i = 0; i < n; ++i) {
+        const LayerDev &y = m->layer[i];
+        const bool last = i == n - 1;
+        void *dst = last ? (void *)dens : (void *)bufs[i & 1];
+        rc = R.conv(y, cur, Lc, H, W, dst, nullptr, last ? ACT_SOFTPLUS : ACT_RELU);
+        if (rc) return rc;
+        cur = plain(dst, y.cout);
+      }
+      continue;
+    }
+    const int D = m->levels;
+    // encoder
+    int h = H, w = W;
+    const void *prev = nullptr;
+    int prevC = 0;
+    for (int d = 0; d < D; ++d) {
+      const LayerDev &la = m->layer[2 * d], &lb = m->layer[2 * d + 1];
+      Src sa = in;
+      if (d > 0) {
+        h /= 2;
+        w /= 2;
+        sa = pooled(prev, prevC);
+      }
+      rc = R.conv(la, sa, Lc, h, w, tA, nullptr, ACT_RELU);
+      if (rc) return rc;
+      void *ob = d < D - 1 ? (void *)skip[d] : (void *)tB;
+      rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, ob, nullptr, ACT_RELU);
+      if (rc) return rc;
+      prev = ob;
+      prevC = lb.cout;
+    }
+    // decoder
+    int li = 2 * D;
+    for (int d = D - 2; d >= 0; --d) {
+      const LayerDev &la = m->layer[li], &lb = m->layer[li + 1];
+      li += 2;
+      h *= 2;
+      w *= 2;
+      const int cs = m->layer[2 * d].cout;
+      rc = R.conv(la, upcat(prev, prevC, skip[d], cs), Lc, h, w, tA, nullptr, ACT_RELU);
+      if (rc) return rc;
+      if (d == 0) {
+        const LayerDev &hd = m->layer[li];
+        Tiling t;
+        const bool fuse = !R.force_direct && pick_tiling(lb.cout, h, w, &t) && lb.cout == 16 && lb.cin % 8 == 0;
+        if (fuse) {
+          rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, dens, &hd, ACT_RELU);
+          if (rc) return rc;
+        } else {
+          rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, tB, nullptr, ACT_RELU);
+          if (rc) return rc;
+          rc = R.conv(hd, plain(tB, lb.cout), Lc, h, w, dens, nullptr, ACT_SOFTPLUS);
+          if (rc) return rc;
+        }
+      } else {
+        rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, tB, nullptr, ACT_RELU);
+        if (rc) return rc;
+        prev = tB;
+        prevC = lb.cout;
+      }
+    }
+    if (D == 1) {
+      const LayerDev &hd = m->layer[2];
+      rc = R.conv(hd, plain(prev, prevC), Lc, H, W, dens, nullptr, ACT_SOFTPLUS);
+      if (rc) return rc;
+    }
+  }
+  return NPG_OK;
+}
+
+extern "C" int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *model, const uint64_t *energy_dev,
+                                       uint32_t L, int H, int W, void *stream) {
+  (void)model; (void)energy_dev; (void)L; (void)H; (void)W; (void)stream;
+  if (!ctx) return NPG_E_ARG;
+  return npg_fail(ctx, NPG_E_ARG, "calibrate_fp8: FP8 path not built yet");
+}

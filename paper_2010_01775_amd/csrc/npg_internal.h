@@ -1,0 +1,174 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/npg.h"
+
+// ---------------------------------------------------------------- context
+struct npg_ctx {
+  int device = 0;
+  uint64_t budget = 0;        // 0 = unbounded
+  uint64_t held = 0;          // bytes the library holds (scratch + models)
+  uint64_t peak = 0;
+  uint32_t *err_dev = nullptr;  // device error word (bit 0: range error)
+  float2 *bnd_dev = nullptr;    // boundary-ray table, 256 entries (see bnd_ray)
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  hipStream_t scratch_stream = nullptr;  // stream that last used the scratch
+  std::string last_error;
+};
+
+// Error bits raised by kernels into ctx->err_dev.
+enum : uint32_t { ERR_RANGE = 1u };
+
+int npg_fail(npg_ctx *ctx, int code, const char *fmt, ...);
+#define NPG_HIP_CHECK(ctx, expr)                                                     \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return npg_fail((ctx), NPG_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+// Scratch arena: one device buffer per context, grown on demand within the
+// budget.  Growing waits for the stream that last used the old buffer.
+int npg_scratch(npg_ctx *ctx, size_t bytes, hipStream_t stream, void **out);
+int npg_device_alloc(npg_ctx *ctx, size_t bytes, void **out);
+void npg_device_free(npg_ctx *ctx, void *p, size_t bytes);
+int npg_set_device(npg_ctx *ctx);
+
+__host__ __device__ static inline size_t npg_align(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Carves consecutive 256-byte aligned pieces out of one scratch buffer.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <class T>
+  T *take(size_t count) {
+    T *p = reinterpret_cast<T *>(base + off);
+    off += npg_align(count * sizeof(T));
+    return p;
+  }
+};
+
+static inline bool pow2_in(int v, int lo, int hi) {
+  return v >= lo && v <= hi && (v & (v - 1)) == 0;
+}
+
+// ---------------------------------------------------------------- bin rule
+// Boundary rays of the azimuth sectors.  The context holds the table
+// tab[m] = (RN32(cos t), RN32(sin t)), t = fl64(2*pi*m)/1024, m = 0..255: the
+// first quadrant of a 1024-column map.  A W-column map uses ray r*(1024/W)
+// for its r-th ray (the binary64 angles coincide exactly because W is a power
+// of two), rotated by q*90 degrees for quadrant q.  Kernels stage the W/4
+// rays they need into LDS with load_quarter and index them with bnd_ray.
+void npg_host_boundaries(float2 out[256]);
+
+__device__ __forceinline__ void load_quarter(const float2 *__restrict__ tab1024, int W, float2 *q) {
+  for (int r = threadIdx.x; r < (W >> 2); r += blockDim.x) q[r] = tab1024[r * (1024 / W)];
+}
+
+__device__ __forceinline__ float2 bnd_ray(const float2 *q4, int b, int W) {
+  const int Q = W >> 2;
+  const int q = b / Q;
+  const int r = b - q * Q;
+  const float2 e = q4[r];
+  switch (q) {
+    case 0: return make_float2(e.x, e.y);
+    case 1: return make_float2(-e.y, e.x);
+    case 2: return make_float2(-e.x, -e.y);
+    default: return make_float2(e.y, -e.x);
+  }
+}
+
+// Sign test of cross(e, v) = e.x*y - e.y*x.  Both products of float32
+// operands are exact in binary64, so the sign of their rounded difference is
+// the sign of the exact value.
+__device__ __forceinline__ bool left_of(float2 e, float x, float y) {
+  const double a = (double)e.x * (double)y;
+  const double b = (double)e.y * (double)x;
+  return a - b >= 0.0;
+}
+
+// Azimuth sector of (x, y): the b with cross(e_b, v) >= 0 > cross(e_{b+1}, v).
+// A float32 atan2 estimate lands within one sector of the answer; the exact
+// tests then settle it.  A bisection over all sectors backs up the
+// (never observed) case of a farther estimate.
+__device__ __forceinline__ int phi_sector(const float2 *q4, float x, float y, int W) {
+  if (x == 0.0f && y == 0.0f) return 0;
+  const float k = (float)W * 0.15915494309189535f;  // W / (2 pi)
+  float f = atan2f(y, x) * k;
+  if (f < 0.0f) f += (float)W;
+  int b = (int)f;
+  b = b < 0 ? 0 : (b >= W ? W - 1 : b);
+  const int mask = W - 1;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    if (!left_of(bnd_ray(q4, b, W), x, y)) {
+      b = (b - 1) & mask;
+    } else if (left_of(bnd_ray(q4, (b + 1) & mask, W), x, y)) {
+      b = (b + 1) & mask;
+    } else {
+      return b;
+    }
+  }
+  // Quadrant from the axis rays (exact), then bisection on the half-plane
+  // test inside it: left_of(e_b) is true for b <= answer, false after.
+  int q;
+  if (y >= 0.0f && x > 0.0f) q = 0;
+  else if (x <= 0.0f && y > 0.0f) q = 1;
+  else if (y <= 0.0f && x < 0.0f) q = 2;
+  else q = 3;
+  int lo = q * (W >> 2), hi = lo + (W >> 2) - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (left_of(bnd_ray(q4, mid, W), x, y)) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Row of z: #{b in 1..H-1 : z >= -1 + 2b/H}.  The boundaries are exact in
+// float32 (H is a power of two <= 1024), so two corrections of a float
+// estimate give the exact count.
+__device__ __forceinline__ int z_row(float z, int H) {
+  float t = (z + 1.0f) * (0.5f * (float)H);
+  int iz = (int)floorf(fminf(fmaxf(t, 0.0f), (float)(H - 1)));
+  const float hh = 0.5f * (float)H;
+  if (iz > 0 && z < -1.0f + (float)iz / hh) --iz;
+  if (iz > 0 && z < -1.0f + (float)iz / hh) --iz;
+  if (iz < H - 1 && z >= -1.0f + (float)(iz + 1) / hh) ++iz;
+  if (iz < H - 1 && z >= -1.0f + (float)(iz + 1) / hh) ++iz;
+  return iz;
+}
+
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+  return isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+__device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
+  atomicOr(err, bit);
+}
+
+// ---------------------------------------------------------------- launchers
+// Each returns a hipError_t from the launch.
+hipError_t launch_splat(const float2 *bnd, const float *dir, const uint32_t *w, const uint32_t *perm,
+                        const uint32_t *off, uint32_t L, int H, int W, uint64_t *energy,
+                        uint32_t *count, int accumulate, uint32_t *err, hipStream_t s);
+hipError_t launch_leaf_scale(const uint64_t *energy, uint32_t L, int HW, double *scale,
+                             hipStream_t s);
+hipError_t launch_apply_scale(const uint64_t *energy, const double *scale, uint32_t L, int HW,
+                              float *x, hipStream_t s);
+hipError_t launch_build_cdf(const float *density, uint32_t L, int H, int W, float *pdf,
+                            float *marg, float *cond, double *total, uint32_t *err,
+                            hipStream_t s);
+hipError_t launch_sample(const npg_tables &t, const uint32_t *leaf, const float *u, uint64_t n,
+                         float *dir, float *pdf, uint32_t *bin, uint32_t *err, hipStream_t s);
+hipError_t launch_eval(const float2 *bnd, const npg_tables &t, const uint32_t *leaf, const float *dir, uint64_t n,
+                       float *pdf, uint32_t *err, hipStream_t s);

@@ -1,0 +1,289 @@
+"""Python binding of libnpg.so (the C-ABI in include/npg.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+torch tensors provide device memory and the current stream.  Importing this
+module does not need a GPU; loading the library does, and fails loudly if the
+library has not been built (``python -m paper_2010_01775_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnpg.so")
+
+OK, E_ARG, E_RANGE, E_CAPACITY, E_BUDGET, E_HIP = 0, -1, -2, -3, -4, -5
+FP32, BF16, FP8 = 0, 1, 2
+PRECISION = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
+
+SYMBOLS = [
+    "npg_create", "npg_destroy", "npg_last_error", "npg_sync_status", "npg_memory_usage",
+    "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
+    "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
+    "npg_reconstruct_density", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
+    "npg_bin_boundaries",
+]
+
+
+class NpgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"npg error {code}: {msg}")
+        self.code = code
+
+
+class Tables(C.Structure):
+    _fields_ = [("pdf_dev", C.c_void_p), ("marg_dev", C.c_void_p), ("cond_dev", C.c_void_p),
+                ("total_dev", C.c_void_p), ("L", C.c_uint32), ("H", C.c_int32), ("W", C.c_int32)]
+
+
+class HierParams(C.Structure):
+    _fields_ = [("split_count", C.c_uint32), ("max_depth", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnpg.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libnpg.so not built at {path}; run python -m paper_2010_01775_amd.build")
+    lib = C.CDLL(path)
+    P, I, U32, U64, SZ = C.c_void_p, C.c_int, C.c_uint32, C.c_uint64, C.c_size_t
+    sig = {
+        "npg_create": (I, [C.POINTER(P), I, U64]),
+        "npg_destroy": (None, [P]),
+        "npg_last_error": (C.c_char_p, [P]),
+        "npg_sync_status": (I, [P, P]),
+        "npg_memory_usage": (None, [P, C.POINTER(U64), C.POINTER(U64)]),
+        "npg_model_load": (I, [P, P, SZ, C.POINTER(P)]),
+        "npg_model_free": (None, [P]),
+        "npg_model_calibrate_fp8": (I, [P, P, P, U32, I, I, P]),
+        "npg_build_hierarchy": (I, [P, P, U64, C.POINTER(HierParams), P, P, P, P, P, U32,
+                                    C.POINTER(U32), P]),
+        "npg_splat_histograms": (I, [P, P, P, P, P, U32, I, I, P, P, I, P]),
+        "npg_normalize_input": (I, [P, P, U32, I, I, P, P]),
+        "npg_reconstruct_density": (I, [P, P, P, P, U32, I, I, I, P, P]),
+        "npg_build_cdf": (I, [P, P, U32, I, I, P, P, P, P, P]),
+        "npg_sample_dirs": (I, [P, C.POINTER(Tables), P, P, U64, P, P, P, P]),
+        "npg_eval_pdf": (I, [P, C.POINTER(Tables), P, P, U64, P, P]),
+        "npg_bin_boundaries": (I, [I, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _dev(t, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Context:
+    """An npg context on one device with an HBM budget for library scratch."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.npg_create(C.byref(h), device, hbm_budget_bytes)
+        if rc:
+            raise NpgError(rc, "npg_create failed")
+        self.h = h
+
+    def check(self, rc: int):
+        if rc:
+            raise NpgError(rc, self.lib.npg_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.npg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.npg_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def memory_usage(self):
+        cur, peak = C.c_uint64(), C.c_uint64()
+        self.lib.npg_memory_usage(self.h, C.byref(cur), C.byref(peak))
+        return cur.value, peak.value
+
+
+def sync_status(ctx: Context, stream=None) -> int:
+    """Synchronise and return the data-dependent error status (0 or E_RANGE)."""
+    return ctx.lib.npg_sync_status(ctx.h, _stream(stream))
+
+
+class Model:
+    def __init__(self, ctx: Context, weight_file: bytes):
+        self.ctx = ctx
+        buf = C.create_string_buffer(weight_file, len(weight_file))
+        h = C.c_void_p()
+        ctx.check(ctx.lib.npg_model_load(ctx.h, buf, len(weight_file), C.byref(h)))
+        self.h = h
+
+    def calibrate_fp8(self, energy, stream=None):
+        L, H, W = energy.shape
+        self.ctx.check(self.ctx.lib.npg_model_calibrate_fp8(self.ctx.h, self.h, _ptr(energy), L, H, W,
+                                                            _stream(stream)))
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.npg_model_free(self.h)
+            self.h = None
+
+
+def model_load(ctx: Context, weight_file: bytes) -> Model:
+    return Model(ctx, weight_file)
+
+
+@dataclass
+class CdfTables:
+    pdf: torch.Tensor
+    marg: torch.Tensor
+    cond: torch.Tensor
+    total: torch.Tensor
+
+    def c(self) -> Tables:
+        L, H, W = self.pdf.shape
+        return Tables(self.pdf.data_ptr(), self.marg.data_ptr(), self.cond.data_ptr(),
+                      self.total.data_ptr() if self.total is not None else None, L, H, W)
+
+
+def build_hierarchy(ctx: Context, pos, split_count: int = 8192, max_depth: int = 6,
+                    max_leaves: int | None = None, want_leaf_of: bool = True, stream=None):
+    """Octree leaves of the photon positions; returns a dict of device tensors."""
+    _dev(pos, torch.float32, "pos")
+    n = pos.shape[0]
+    dev = pos.device
+    if max_leaves is None:
+        max_leaves = max(1, min(n, 8 ** max_depth))
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    leaf_of = torch.empty(n, dtype=torch.int32, device=dev) if want_leaf_of else None
+    off = torch.empty(max_leaves + 1, dtype=torch.int32, device=dev)
+    key = torch.empty(max_leaves, dtype=torch.int64, device=dev)
+    depth = torch.empty(max_leaves, dtype=torch.uint8, device=dev)
+    nl = C.c_uint32(0)
+    prm = HierParams(split_count, max_depth)
+    rc = ctx.lib.npg_build_hierarchy(ctx.h, _ptr(pos), n, C.byref(prm), _ptr(perm), _ptr(leaf_of),
+                                     _ptr(off), _ptr(key), _ptr(depth), max_leaves, C.byref(nl),
+                                     _stream(stream))
+    ctx.check(rc)
+    L = nl.value
+    return dict(perm=perm, leaf_of=leaf_of, leaf_off=off[:L + 1], key=key[:L], depth=depth[:L],
+                n_leaves=L)
+
+
+def splat_histograms(ctx: Context, dirs, w, leaf_off, H: int, W: int, perm=None, energy=None,
+                     count=None, accumulate: bool = False, want_count: bool = True, stream=None):
+    _dev(dirs, torch.float32, "dirs")
+    _dev(w, torch.int32, "w (uint32 bits in int32)")
+    _dev(leaf_off, torch.int32, "leaf_off")
+    L = leaf_off.shape[0] - 1
+    dev = dirs.device
+    if energy is None:
+        energy = torch.empty((L, H, W), dtype=torch.int64, device=dev)
+    if count is None and want_count:
+        count = torch.empty((L, H, W), dtype=torch.int32, device=dev)
+    ctx.check(ctx.lib.npg_splat_histograms(ctx.h, _ptr(dirs), _ptr(w), _ptr(perm), _ptr(leaf_off), L,
+                                           H, W, _ptr(energy), _ptr(count), int(bool(accumulate)),
+                                           _stream(stream)))
+    return energy, count
+
+
+def normalize_input(ctx: Context, energy, x=None, stream=None):
+    L, H, W = energy.shape
+    if x is None:
+        x = torch.empty((L, H, W), dtype=torch.float32, device=energy.device)
+    ctx.check(ctx.lib.npg_normalize_input(ctx.h, _ptr(energy), L, H, W, _ptr(x), _stream(stream)))
+    return x
+
+
+def reconstruct_density(ctx: Context, model: Model, energy, precision="fp32", count=None,
+                        density=None, stream=None):
+    L, H, W = energy.shape
+    if density is None:
+        density = torch.empty((L, H, W), dtype=torch.float32, device=energy.device)
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.lib.npg_reconstruct_density(ctx.h, model.h, _ptr(energy), _ptr(count), L, H, W, p,
+                                              _ptr(density), _stream(stream)))
+    return density
+
+
+def build_cdf(ctx: Context, density, out: CdfTables | None = None, stream=None) -> CdfTables:
+    L, H, W = density.shape
+    dev = density.device
+    if out is None:
+        out = CdfTables(torch.empty((L, H, W), dtype=torch.float32, device=dev),
+                        torch.empty((L, H + 1), dtype=torch.float32, device=dev),
+                        torch.empty((L, H, W + 1), dtype=torch.float32, device=dev),
+                        torch.empty(L, dtype=torch.float64, device=dev))
+    ctx.check(ctx.lib.npg_build_cdf(ctx.h, _ptr(density), L, H, W, _ptr(out.pdf), _ptr(out.marg),
+                                    _ptr(out.cond), _ptr(out.total), _stream(stream)))
+    return out
+
+
+def sample_dirs(ctx: Context, tables: CdfTables, leaf, u, want_bin: bool = True, out=None,
+                stream=None):
+    n = leaf.shape[0]
+    dev = leaf.device
+    if out is None:
+        out = (torch.empty((n, 3), dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.int32, device=dev) if want_bin else None)
+    d, p, b = out
+    t = tables.c()
+    ctx.check(ctx.lib.npg_sample_dirs(ctx.h, C.byref(t), _ptr(leaf), _ptr(u), n, _ptr(d), _ptr(p),
+                                      _ptr(b), _stream(stream)))
+    return d, p, b
+
+
+def eval_pdf(ctx: Context, tables: CdfTables, leaf, dirs, out=None, stream=None):
+    n = leaf.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=leaf.device)
+    t = tables.c()
+    ctx.check(ctx.lib.npg_eval_pdf(ctx.h, C.byref(t), _ptr(leaf), _ptr(dirs), n, _ptr(out),
+                                   _stream(stream)))
+    return out
+
+
+def bin_boundaries(W: int):
+    import numpy as np
+    out = np.empty(2 * W, np.float32)
+    rc = load_library().npg_bin_boundaries(W, out.ctypes.data)
+    if rc:
+        raise NpgError(rc, "bad W")
+    return out.reshape(W, 2)

@@ -17,3 +17,19 @@ def orc():
     from oracle import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def npg():
+    from paper_2010_01775_amd import npg as _npg
+    _npg.load_library()
+    return _npg
+
+
+@pytest.fixture(scope="session")
+def ctx(npg):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    c = npg.Context(0)
+    yield c
+    c.close()

@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every entry point include/npg.h
+declares; host-only helpers agree with the oracle.  No GPU work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "npg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(npg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_hot_path():
+    names = _declared()
+    for n in ("npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
+              "npg_reconstruct_density", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(npg):
+    lib = npg.load_library()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert sorted(npg.SYMBOLS) == _declared()
+
+
+def test_boundary_table_matches_oracle(npg, orc):
+    for W in (4, 8, 16, 32, 64, 128, 256, 512, 1024):
+        got = npg.bin_boundaries(W)
+        ex, ey = orc.boundaries(W)
+        assert np.array_equal(got[:, 0], ex) and np.array_equal(got[:, 1], ey), W
+
+
+def test_bad_width_rejected(npg):
+    with pytest.raises(npg.NpgError):
+        npg.bin_boundaries(12)
+
+
+def test_no_oracle_in_product():
+    """The product package never imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_2010_01775_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                for pat in (r"import\s+oracle", r"from\s+oracle", r"npg_oracle", r"\bor_(splat|build_cdf|sample|eval_pdf|net_forward|build_tree|bin_dirs)\b"):
+                    assert not re.search(pat, txt), (os.path.join(dp, f), pat)

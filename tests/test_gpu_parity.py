@@ -1,0 +1,404 @@
+"""GPU parity: every hot-path call through the C-ABI against the FP64 oracle
+on the same seeded inputs.
+
+Bars: bit-exact for histograms (energy, counts), the normalised input, bin
+indices and pdf lookups; pdfs from the FP32 network within 1e-5 relative of
+the oracle; CDF tables within one float32 rounding of the oracle's; sampled
+directions within 2e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2010_01775_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def t32(a):
+    """numpy uint32/int32 -> device int32 tensor (same bits)."""
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(DEV)
+
+
+def t64(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(DEV)
+
+
+def tf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def ragged_batch(seed, counts, H, W):
+    rng = synth.rng_for(seed)
+    L = len(counts)
+    n = int(sum(counts))
+    mus = synth.unit_vectors(rng, 2 * L + 2).reshape(-1, 2, 3)
+    dirs = np.concatenate([synth.two_lobe_mixture(rng, c, mus[i, 0], mus[i, 1]) if c else
+                           np.zeros((0, 3), np.float32) for i, c in enumerate(counts)])
+    w = synth.photon_weights(rng, n)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.uint32)
+    return dirs, w, off
+
+
+# ------------------------------------------------------------------ splat
+@pytest.mark.parametrize("H,W,counts", [
+    (32, 32, [4096]),
+    (64, 64, [4096] * 7 + [0, 1, 3, 700, 40000]),      # ragged, empty, > one drain round
+    (4, 4, [100, 0, 5000]),
+    (16, 64, [2000, 300]),
+    (128, 128, [0, 20, 90000, 1753, 8192]),            # 16384 bins: 128 KiB of LDS
+    (256, 256, [3000, 10]),                            # two row bands
+    (1024, 4, [5000]),
+])
+def test_splat_bit_exact(ctx, npg, orc, H, W, counts):
+    dirs, w, off = ragged_batch(sum(counts) + H, counts, H, W)
+    rc, e_ref, c_ref = orc.splat(dirs, w, off, H, W)
+    assert rc == 0
+    e, c = npg.splat_histograms(ctx, tf(dirs), t32(w), t32(off), H, W)
+    assert npg.sync_status(ctx) == 0
+    assert np.array_equal(u64(e), e_ref)
+    assert np.array_equal(u32(c), c_ref)
+
+
+def test_splat_perm_accumulate_and_huge_weights(ctx, npg, orc):
+    H = W = 64
+    counts = [3000, 0, 50000, 17]
+    dirs, w, off = ragged_batch(77, counts, H, W)
+    w[::7] = 0xFFFFFFFF                      # maximal weights stress the packed words
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(len(w)).astype(np.uint32)
+    rc, e_ref, c_ref = orc.splat(dirs, w, off, H, W, perm=perm)
+    rc, e_ref, c_ref = orc.splat(dirs, w, off, H, W, perm=perm, energy=e_ref, count=c_ref, accumulate=True)
+    e, c = npg.splat_histograms(ctx, tf(dirs), t32(w), t32(off), H, W, perm=t32(perm))
+    e, c = npg.splat_histograms(ctx, tf(dirs), t32(w), t32(off), H, W, perm=t32(perm), energy=e, count=c,
+                                accumulate=True)
+    assert npg.sync_status(ctx) == 0
+    assert np.array_equal(u64(e), e_ref) and np.array_equal(u32(c), c_ref)
+    # mass conservation with huge weights
+    assert int(u64(e).sum(dtype=np.uint64)) == 2 * int(w.astype(np.uint64).sum())
+
+
+def test_splat_adversarial_directions(ctx, npg, orc):
+    """Directions on boundary rays, poles, row boundaries, signed zeros."""
+    H, W = 32, 64
+    ex, ey = orc.boundaries(W)
+    zb = (-1 + 2 * np.arange(H) / H).astype(np.float32)
+    rows = [np.stack([ex, ey, np.zeros(W, np.float32)], 1),
+            np.stack([ex * 3, ey * 3, np.full(W, 0.25, np.float32)], 1),
+            np.stack([np.ones(H), np.zeros(H), zb], 1),
+            np.stack([np.ones(H), np.zeros(H), np.nextafter(zb, np.float32(-2))], 1),
+            np.array([[0, 0, 1], [0, 0, -1], [-0.0, 0.0, 0.5], [0.0, -0.0, -0.5], [-0.0, -0.0, 0]]),
+            np.array([[1, -1e-30, 0], [-1, -1e-30, 0], [-1, 1e-30, 0], [1e-30, 1, 0.1]])]
+    a = np.nextafter(np.arctan2(ey, ex).astype(np.float64), 10)
+    rows.append(np.stack([np.cos(a + 1e-7), np.sin(a + 1e-7), np.zeros(W)], 1))
+    rows.append(np.stack([np.cos(a - 1e-7), np.sin(a - 1e-7), np.zeros(W)], 1))
+    dirs = np.concatenate(rows).astype(np.float32)
+    n = dirs.shape[0]
+    w = np.arange(1, n + 1, dtype=np.uint32)
+    off = np.array([0, n], np.uint32)
+    rc, e_ref, c_ref = orc.splat(dirs, w, off, H, W)
+    e, c = npg.splat_histograms(ctx, tf(dirs), t32(w), t32(off), H, W)
+    assert np.array_equal(u64(e), e_ref) and np.array_equal(u32(c), c_ref)
+    # and the per-direction bins through eval_pdf on a one-hot-per-bin pdf
+    pdf = np.arange(H * W, dtype=np.float32).reshape(1, H, W)
+    tabs = npg.CdfTables(tf(pdf), tf(np.zeros((1, H + 1))), tf(np.zeros((1, H, W + 1))), None)
+    got = npg.eval_pdf(ctx, tabs, t32(np.zeros(n, np.uint32)), tf(dirs)).cpu().numpy()
+    rc, b = orc.bin_dirs(dirs, H, W)
+    assert np.array_equal(got.astype(np.int64), b)
+
+
+def test_splat_uniform_random_bins_match(ctx, npg, orc):
+    """Two million uniform directions at W = 1024: every bin decision agrees."""
+    rng = synth.rng_for(21)
+    n = 2_000_000
+    dirs = synth.to_f32_dirs(synth.unit_vectors(rng, n))
+    H = W = 1024
+    rc, b_ref = orc.bin_dirs(dirs, H, W)
+    pdf = np.arange(H * W, dtype=np.float32).reshape(1, H, W)
+    tabs = npg.CdfTables(tf(pdf), tf(np.zeros((1, H + 1))), tf(np.zeros((1, H, W + 1))), None)
+    got = npg.eval_pdf(ctx, tabs, t32(np.zeros(n, np.uint32)), tf(dirs)).cpu().numpy()
+    assert np.array_equal(got.astype(np.int64), b_ref)
+
+
+def test_splat_nonfinite_flags_range(ctx, npg, orc):
+    dirs = np.array([[1, 0, 0], [np.nan, 0, 0], [0, 1, 0]], np.float32)
+    w = np.array([3, 4, 5], np.uint32)
+    off = np.array([0, 3], np.uint32)
+    e, c = npg.splat_histograms(ctx, tf(dirs), t32(w), t32(off), 8, 8)
+    assert npg.sync_status(ctx) == npg.E_RANGE
+    assert npg.sync_status(ctx) == 0          # cleared
+    rc, e_ref, c_ref = orc.splat(dirs, w, off, 8, 8)
+    assert np.array_equal(u64(e), e_ref)
+
+
+def test_splat_bad_args(ctx, npg):
+    d = torch.zeros((1, 3), device=DEV)
+    w = torch.zeros(1, dtype=torch.int32, device=DEV)
+    off = torch.tensor([0, 1], dtype=torch.int32, device=DEV)
+    for H, W in ((6, 8), (8, 2048), (0, 8)):
+        with pytest.raises(npg.NpgError) as ei:
+            npg.splat_histograms(ctx, d, w, off, H, W, energy=torch.zeros(1, dtype=torch.int64, device=DEV),
+                                 want_count=False)
+        assert ei.value.code == npg.E_ARG
+
+
+# -------------------------------------------------------------- normalise
+def test_normalize_bit_exact(ctx, npg, orc):
+    counts = [4096, 0, 33, 90000]
+    dirs, w, off = ragged_batch(5, counts, 64, 64)
+    rc, e_ref, _ = orc.splat(dirs, w, off, 64, 64)
+    e_ref[1, 3, 3] = 0
+    x_ref = orc.normalize_input(e_ref)
+    x = npg.normalize_input(ctx, t64(e_ref)).cpu().numpy()
+    assert np.array_equal(x, x_ref.astype(np.float32))
+
+
+# ---------------------------------------------------------------- network
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def _pdf_from_density(s):
+    s = s.astype(np.float64)
+    L, H, W = s.shape
+    return s / s.reshape(L, -1).sum(1)[:, None, None] * H * W / (4 * math.pi)
+
+
+def test_cnn_fp32_parity(ctx, npg, orc):
+    b = synth.single_leaf()
+    rc, e, _ = orc.splat(b.dirs, b.w, b.leaf_off, b.H, b.W)
+    rc, s_ref = orc.net_forward(b.model, orc.normalize_input(e))
+    m = npg.Model(ctx, b.model)
+    s = npg.reconstruct_density(ctx, m, t64(e), "fp32").cpu().numpy()
+    assert np.max(_rel(s, s_ref)) < 1e-5
+    assert np.max(_rel(_pdf_from_density(s), _pdf_from_density(s_ref))) < 1e-5
+    m.free()
+
+
+@pytest.mark.parametrize("H,W,L,bias", [(64, 64, 5, False), (64, 64, 3, True), (128, 128, 2, True),
+                                        (32, 64, 3, True), (16, 16, 4, True)])
+def test_unet_fp32_parity(ctx, npg, orc, H, W, L, bias):
+    model = synth.unet_model(31 + H, random_bias=bias)
+    counts = [4096] * (L - 1) + [700]
+    dirs, w, off = ragged_batch(H + L, counts, H, W)
+    rc, e, _ = orc.splat(dirs, w, off, H, W)
+    rc, s_ref = orc.net_forward(model, orc.normalize_input(e))
+    assert rc == 0
+    m = npg.Model(ctx, model)
+    s = npg.reconstruct_density(ctx, m, t64(e), "fp32").cpu().numpy()
+    p, p_ref = _pdf_from_density(s), _pdf_from_density(s_ref)
+    rel = _rel(p, p_ref)
+    assert np.max(rel) < 1e-5, (np.max(rel), np.unravel_index(np.argmax(rel), rel.shape))
+    m.free()
+
+
+def test_unet_direct_path_parity(ctx, npg, orc, monkeypatch):
+    """The direct-convolution fallback computes the same network."""
+    model = synth.unet_model(5, random_bias=True)
+    dirs, w, off = ragged_batch(9, [3000, 2000], 32, 32)
+    rc, e, _ = orc.splat(dirs, w, off, 32, 32)
+    rc, s_ref = orc.net_forward(model, orc.normalize_input(e))
+    monkeypatch.setenv("NPG_FORCE_DIRECT", "1")
+    m = npg.Model(ctx, model)
+    s = npg.reconstruct_density(ctx, m, t64(e), "fp32").cpu().numpy()
+    assert np.max(_rel(s, s_ref)) < 1e-5
+    m.free()
+
+
+def test_unet_chunking_invariant(ctx, npg, monkeypatch):
+    """Results do not depend on how leaves are chunked."""
+    model = synth.unet_model(8)
+    b = synth.uniform_batch(seed=12, L=10, per_leaf=1000, H=64, W=64, n_queries=8, model=model)
+    e, _ = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), 64, 64)
+    m = npg.Model(ctx, model)
+    s1 = npg.reconstruct_density(ctx, m, e, "fp32").cpu()
+    monkeypatch.setenv("NPG_CHUNK_LEAVES", "3")
+    s2 = npg.reconstruct_density(ctx, m, e, "fp32").cpu()
+    s3 = npg.reconstruct_density(ctx, m, e[4:7].contiguous(), "fp32").cpu()
+    assert torch.equal(s1, s2) and torch.equal(s1[4:7], s3)
+    m.free()
+
+
+def test_unet_bf16_error_stated(ctx, npg, orc):
+    """BF16 conv: per-leaf L1 and KL of the pdf against the FP64 oracle."""
+    model = synth.unet_model(41)
+    b = synth.uniform_batch(seed=13, L=8, per_leaf=4096, H=64, W=64, n_queries=8, model=model)
+    rc, e, _ = orc.splat(b.dirs, b.w, b.leaf_off, 64, 64)
+    rc, s_ref = orc.net_forward(model, orc.normalize_input(e))
+    m = npg.Model(ctx, model)
+    s = npg.reconstruct_density(ctx, m, t64(e), "bf16").cpu().numpy().astype(np.float64)
+    p = s / s.reshape(8, -1).sum(1)[:, None, None]
+    q = s_ref / s_ref.reshape(8, -1).sum(1)[:, None, None]
+    l1 = np.abs(p - q).reshape(8, -1).sum(1)
+    kl = (q * np.log(q / p)).reshape(8, -1).sum(1)
+    print(f"bf16 L1 median {np.median(l1):.3e} max {l1.max():.3e}; KL median {np.median(kl):.3e} max {kl.max():.3e}")
+    assert l1.max() < 5e-2 and kl.max() < 5e-3
+    m.free()
+
+
+def test_reconstruct_bad_args(ctx, npg):
+    m = npg.Model(ctx, synth.unet_model(1))
+    e = torch.zeros((1, 36, 36), dtype=torch.int64, device=DEV)
+    with pytest.raises(npg.NpgError):
+        npg.reconstruct_density(ctx, m, e, "fp32")      # 36 not a power of two
+    e = torch.zeros((1, 4, 4), dtype=torch.int64, device=DEV)
+    with pytest.raises(npg.NpgError):
+        npg.reconstruct_density(ctx, m, e, "fp32")      # 4 not divisible by 2^3
+    with pytest.raises(npg.NpgError):
+        npg.Model(ctx, b"NPGW" + b"\0" * 16)
+    m.free()
+
+
+def test_zero_energy_gives_uniform_pdf(ctx, npg):
+    for model in (synth.cnn_model(2), synth.unet_model(2)):
+        m = npg.Model(ctx, model)
+        e = torch.zeros((2, 32, 32), dtype=torch.int64, device=DEV)
+        s = npg.reconstruct_density(ctx, m, e, "fp32")
+        assert torch.allclose(s, torch.full_like(s, math.log(2.0)), rtol=2e-7, atol=0)
+        t = npg.build_cdf(ctx, s)
+        assert torch.allclose(t.pdf, torch.full_like(t.pdf, 1 / (4 * math.pi)), rtol=1e-6)
+        m.free()
+
+
+# -------------------------------------------------------------------- CDF
+def test_cdf_parity(ctx, npg, orc):
+    s = synth.random_density(4, 7, 64, 32, zero_frac=0.3)
+    s[2, 10, :] = 0
+    s[5] = 0
+    s[5, 3, 3] = 2.5
+    rc, pdf_r, marg_r, cond_r, tot_r = orc.build_cdf(s.astype(np.float64))
+    t = npg.build_cdf(ctx, tf(s))
+    assert npg.sync_status(ctx) == 0
+    pdf, marg, cond, tot = (x.cpu().numpy() for x in (t.pdf, t.marg, t.cond, t.total))
+    ulp = lambda a: np.spacing(np.abs(a).astype(np.float32))
+    assert np.all(np.abs(pdf - pdf_r) <= ulp(pdf_r))
+    assert np.all(np.abs(marg - marg_r) <= ulp(marg_r))
+    assert np.all(np.abs(cond - cond_r) <= ulp(cond_r))
+    assert np.allclose(tot, tot_r, rtol=1e-14)
+    for tab, ax in ((marg, 1), (cond, 2)):
+        assert np.all(np.diff(tab, axis=ax) >= 0)
+
+
+def test_cdf_bad_leaf(ctx, npg):
+    s = np.ones((3, 8, 8), np.float32)
+    s[1] = 0
+    s[2, 0, 0] = np.inf
+    t = npg.build_cdf(ctx, tf(s))
+    assert npg.sync_status(ctx) == npg.E_RANGE
+    assert torch.isnan(t.pdf[1]).all() and torch.isnan(t.pdf[2]).all() and torch.isfinite(t.pdf[0]).all()
+    assert t.total[1].item() == 0
+
+
+# ----------------------------------------------------------------- sample
+def _oracle_tables(orc, seed, L, H, W, zero_frac=0.2):
+    s = synth.random_density(seed, L, H, W, zero_frac=zero_frac).astype(np.float64)
+    rc, pdf, marg, cond, tot = orc.build_cdf(s)
+    return s, pdf, marg, cond
+
+
+@pytest.mark.parametrize("L,H,W,n", [(1, 32, 32, 65536), (37, 64, 64, 300000), (3, 128, 128, 100000),
+                                     (2, 4, 1024, 5000)])
+def test_sample_parity_same_tables(ctx, npg, orc, L, H, W, n):
+    s, pdf, marg, cond = _oracle_tables(orc, 6 + L, L, H, W)
+    leaf, u = synth.queries(100 + L, L, n)
+    # exact table entries as uniforms: the last-entry-<=-u rule must hold
+    u[:50, 0] = marg[leaf[:50], np.arange(50) % H]
+    rc, d_ref, p_ref, b_ref = orc.sample(pdf, marg, cond, leaf, u)
+    tabs = npg.CdfTables(tf(pdf), tf(marg), tf(cond), None)
+    d, p, b = npg.sample_dirs(ctx, tabs, t32(leaf), tf(u))
+    assert npg.sync_status(ctx) == 0
+    assert np.array_equal(u32(b), b_ref)
+    assert np.array_equal(p.cpu().numpy(), p_ref)
+    assert np.max(np.abs(d.cpu().numpy() - d_ref)) < 2e-6
+    # eval_pdf of the sampled direction returns the sampled pdf (boundary
+    # round-off cases counted)
+    pe = npg.eval_pdf(ctx, tabs, t32(leaf), d).cpu().numpy()
+    mism = np.count_nonzero(pe != p.cpu().numpy())
+    assert mism <= max(3, n // 20000), mism
+
+
+def test_sample_errors(ctx, npg, orc):
+    s, pdf, marg, cond = _oracle_tables(orc, 1, 2, 8, 8)
+    tabs = npg.CdfTables(tf(pdf), tf(marg), tf(cond), None)
+    leaf = np.array([0, 2, 1, 1], np.uint32)
+    u = np.array([[0.5, 0.5], [0.5, 0.5], [1.0, 0.2], [np.nan, 0.2]], np.float32)
+    d, p, b = npg.sample_dirs(ctx, tabs, t32(leaf), tf(u))
+    assert npg.sync_status(ctx) == npg.E_RANGE
+    d, p, b = d.cpu().numpy(), p.cpu().numpy(), u32(b)
+    assert np.all(np.isfinite(d[0])) and np.all(np.isnan(d[1:]))
+    assert list(b[1:]) == [0xFFFFFFFF] * 3
+
+
+def test_eval_parity(ctx, npg, orc):
+    L, H, W = 9, 64, 128
+    s, pdf, marg, cond = _oracle_tables(orc, 2, L, H, W)
+    rng = synth.rng_for(3)
+    n = 200000
+    dirs = synth.to_f32_dirs(synth.unit_vectors(rng, n))
+    dirs[:1000] *= 7.5                                  # unnormalised
+    leaf = rng.integers(0, L, n).astype(np.uint32)
+    leaf[5] = L                                         # out of range
+    dirs[7] = [np.inf, 0, 0]
+    rc, ref = orc.eval_pdf(pdf, leaf, dirs)
+    tabs = npg.CdfTables(tf(pdf), tf(marg), tf(cond), None)
+    got = npg.eval_pdf(ctx, tabs, t32(leaf), tf(dirs)).cpu().numpy()
+    assert npg.sync_status(ctx) == npg.E_RANGE
+    assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------- full chain
+def test_chain_single_leaf(ctx, npg, orc):
+    """The 1-leaf CNN workload end to end, including 65,536 samples."""
+    b = synth.single_leaf()
+    ref = orc.pipeline(b)
+    m = npg.Model(ctx, b.model)
+    e, c = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), b.H, b.W)
+    s = npg.reconstruct_density(ctx, m, e, "fp32")
+    tabs = npg.build_cdf(ctx, s)
+    d, p, bins = npg.sample_dirs(ctx, tabs, t32(b.q_leaf), tf(b.q_u))
+    assert npg.sync_status(ctx) == 0
+    assert np.array_equal(u64(e), ref["energy"]) and np.array_equal(u32(c), ref["count"])
+    assert np.max(_rel(tabs.pdf.cpu().numpy(), ref["pdf"])) < 1e-5
+    rc, d_ref, p_ref, b_ref = orc.sample(ref["pdf"], ref["marg"], ref["cond"], b.q_leaf, b.q_u)
+    mism = np.count_nonzero(u32(bins) != b_ref)
+    assert mism <= 10, mism                  # only u within a rounding of a table entry
+    # chi-square of the sampled bins against the GPU's own pdf
+    from scipy import stats
+    pk = tabs.pdf.cpu().numpy().ravel().astype(np.float64)
+    pk /= pk.sum()
+    obs = np.bincount(u32(bins), minlength=pk.size)
+    keep = pk * len(b.q_leaf) >= 5
+    e_ = pk[keep] * len(b.q_leaf)
+    assert stats.chisquare(obs[keep], e_ * obs[keep].sum() / e_.sum()).pvalue > 1e-4
+    m.free()
+
+
+def test_chain_uniform_batch_full_size_sampled(ctx, npg, orc):
+    """1024 leaves x 4096 photons at 64x64 (the uniform-batch workload):
+    histograms checked on every leaf, pdfs on a sample of leaves."""
+    b = synth.uniform_batch()
+    rc, e_ref, c_ref = orc.splat(b.dirs, b.w, b.leaf_off, b.H, b.W)
+    m = npg.Model(ctx, b.model)
+    e, c = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), b.H, b.W)
+    s = npg.reconstruct_density(ctx, m, e, "fp32")
+    tabs = npg.build_cdf(ctx, s)
+    assert npg.sync_status(ctx) == 0
+    assert np.array_equal(u64(e), e_ref) and np.array_equal(u32(c), c_ref)
+    pick = np.array([0, 1, 511, 777, 1023])
+    rc, s_ref = orc.net_forward(b.model, orc.normalize_input(e_ref[pick]))
+    rc, pdf_ref, *_ = orc.build_cdf(s_ref)
+    rel = _rel(tabs.pdf.cpu().numpy()[pick], pdf_ref)
+    assert rel.max() < 1e-5, rel.max()
+    m.free()

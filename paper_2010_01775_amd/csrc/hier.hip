@@ -1,13 +1,371 @@
-// Adaptive octree build (placeholder until the sort-based build lands).
+// Adaptive octree over the unit box: photon -> leaf assignment.
+//
+// A cell at depth d is a run of 8^(Dmax-d) consecutive cells of the finest
+// level in Morton order, so every count the split rule needs is a difference
+// of one exclusive prefix over the finest-level histogram:
+//   1. cells:    q = floor(p * 2^21) per axis (exact for float32 in [0,1)),
+//                finest cell = Morton interleave of q >> (21 - Dmax), and a
+//                histogram of the finest cells;
+//   2. scan:     exclusive prefix of the histogram (cell start offsets);
+//   3. decide:   for every finest cell, walk down from the root while the
+//                ancestor's count exceeds the threshold (and depth < Dmax);
+//                the first unsplit ancestor is the leaf; a leaf starts at its
+//                first finest cell and exists if its count is non-zero;
+//   4. number:   exclusive prefix of the leaf-start flags = leaf ids in
+//                Morton order; leaf CSR offsets are the cell start offsets;
+//   5. permute:  stable LSD radix sort of (leaf id, photon index), 8-bit
+//                digits; ranks inside a wavefront come from ballots over the
+//                digit bits, so equal keys keep their input order.
 #include "npg_internal.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVE_ITEMS = 1024;                 // items per wavefront per tile
+constexpr int RS_TILE = RS_WAVE_ITEMS * (RS_THREADS / 64);
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 8 bits -> every third bit
+  uint32_t r = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) r |= ((v >> b) & 1u) << (3 * b);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void cells_kernel(const float *__restrict__ pos, uint64_t n, int dmax,
+                                                    uint32_t *__restrict__ cell, uint32_t *__restrict__ cnt,
+                                                    uint32_t *err) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const bool ok = x >= 0.0f && x < 1.0f && y >= 0.0f && y < 1.0f && z >= 0.0f && z < 1.0f;
+    uint32_t c = 0;
+    if (ok) {
+      const int sh = 21 - dmax;
+      const uint32_t qx = (uint32_t)(x * 2097152.0f) >> sh;
+      const uint32_t qy = (uint32_t)(y * 2097152.0f) >> sh;
+      const uint32_t qz = (uint32_t)(z * 2097152.0f) >> sh;
+      c = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+    } else {
+      raise_err(err, ERR_RANGE);
+    }
+    cell[i] = c;
+    atomicAdd(&cnt[c], 1u);
+  }
+}
+
+// ---------------------------------------------------------------- scan
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// exclusive scan of one value per thread across a 256-thread block;
+// returns the prefix and sets *total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+  __shared__ uint32_t ws[SCAN_THREADS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan_u32(v, lane);
+  if (lane == 63) ws[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+    if (w < wave) before += ws[w];
+    tot += ws[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void scan_reduce_kernel(const uint32_t *__restrict__ in, uint64_t n,
+                                                                   uint32_t *__restrict__ bsum) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  uint32_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint64_t i = base + (uint64_t)k * SCAN_THREADS + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// single-block exclusive scan of m block sums, in place
+__global__ __launch_bounds__(SCAN_THREADS) void scan_sums_kernel(uint32_t *__restrict__ bsum, uint32_t m) {
+  const uint32_t per = (m + SCAN_THREADS - 1) / SCAN_THREADS;
+  const uint32_t b0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < m) s += bsum[b0 + k];
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, &tot);
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < m) {
+      const uint32_t v = bsum[b0 + k];
+      bsum[b0 + k] = run;
+      run += v;
+    }
+}
+
+// out[i] = offset of the block + exclusive prefix inside the block; out[n] = total
+__global__ __launch_bounds__(SCAN_THREADS) void scan_down_kernel(const uint32_t *__restrict__ in, uint64_t n,
+                                                                 const uint32_t *__restrict__ bsum,
+                                                                 uint32_t *__restrict__ out) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint64_t i = base + k;
+    v[k] = i < n ? in[i] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = bsum[blockIdx.x] + block_excl_scan(s, &tot);
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = bsum[blockIdx.x] + tot;
+}
+
+// ---------------------------------------------------------------- tree
+__global__ void decide_kernel(const uint32_t *__restrict__ cstart, uint32_t ncell, int dmax, uint32_t T,
+                              uint32_t *__restrict__ flag, uint8_t *__restrict__ ldepth) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < ncell; f += gridDim.x * blockDim.x) {
+    int d = 0;
+    uint32_t count = 0, span = 1;
+    for (d = 0; d <= dmax; ++d) {
+      const int sh = 3 * (dmax - d);
+      span = 1u << sh;
+      const uint32_t a = f >> sh;
+      count = cstart[(a + 1) * span] - cstart[a * span];
+      if (count <= T || d == dmax) break;
+    }
+    flag[f] = ((f & (span - 1)) == 0 && count > 0) ? 1u : 0u;
+    ldepth[f] = (uint8_t)d;
+  }
+}
+
+__global__ void emit_kernel(const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ flag,
+                            const uint32_t *__restrict__ lid, const uint8_t *__restrict__ ldepth, uint32_t ncell,
+                            int dmax, uint32_t max_leaves, uint64_t n, uint32_t *__restrict__ leaf_off,
+                            uint64_t *__restrict__ key, uint8_t *__restrict__ depth) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < ncell; f += gridDim.x * blockDim.x) {
+    if (!flag[f]) continue;
+    const uint32_t id = lid[f];
+    if (id >= max_leaves) continue;
+    leaf_off[id] = cstart[f];
+    if (key) key[id] = (uint64_t)f << (63 - 3 * dmax);
+    if (depth) depth[id] = ldepth[f];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t L = lid[ncell];
+    if (L <= max_leaves) leaf_off[L] = (uint32_t)n;
+  }
+}
+
+__global__ void leaf_of_kernel(const uint32_t *__restrict__ cell, uint64_t n, const uint32_t *__restrict__ lid,
+                               const uint32_t *__restrict__ flag, uint32_t *__restrict__ leaf_of) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = cell[i];
+    leaf_of[i] = lid[c] + flag[c] - 1u;
+  }
+}
+
+// ---------------------------------------------------------- radix sort
+__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *__restrict__ key, uint64_t n, int shift,
+                                                             uint32_t nblocks, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  for (int k = threadIdx.x; k < RS_TILE; k += RS_THREADS) {
+    const uint64_t i = base + k;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile.  vals == NULL: the value is the item index.
+__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *__restrict__ key,
+                                                                const uint32_t *__restrict__ vals, uint64_t n,
+                                                                int shift, uint32_t nblocks,
+                                                                const uint32_t *__restrict__ offs,
+                                                                uint32_t *__restrict__ key_out,
+                                                                uint32_t *__restrict__ val_out) {
+  __shared__ uint32_t cnt[RS_THREADS / 64][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int w = 0; w < RS_THREADS / 64; ++w) cnt[w][threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t wbase = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)wave * RS_WAVE_ITEMS;
+  for (int k = lane; k < RS_WAVE_ITEMS; k += 64) {
+    const uint64_t i = wbase + k;
+    if (i < n) atomicAdd(&cnt[wave][(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  {  // per-wave base offsets for digit d = threadIdx.x
+    const int d = threadIdx.x;
+    uint32_t run = offs[(uint64_t)d * nblocks + blockIdx.x];
+    for (int w = 0; w < RS_THREADS / 64; ++w) {
+      const uint32_t c = cnt[w][d];
+      cnt[w][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < RS_WAVE_ITEMS; r += 64) {
+    const uint64_t i = wbase + r + lane;
+    const bool act = i < n;
+    const uint32_t kk = act ? key[i] : 0u;
+    const uint32_t dg = (kk >> shift) & 255u;
+    uint64_t mask = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot(((dg >> b) & 1u) != 0);
+      mask &= ((dg >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(mask & below);
+    const uint32_t tot = (uint32_t)__popcll(mask);
+    uint32_t basev = 0;
+    if (act) basev = cnt[wave][dg];
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+      const uint32_t pos = basev + rank;
+      key_out[pos] = kk;
+      val_out[pos] = vals ? vals[i] : (uint32_t)i;
+      if (rank == 0) cnt[wave][dg] = basev + tot;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+unsigned grid_of(uint64_t n, unsigned per = 256, unsigned cap = 65536) {
+  const uint64_t b = (n + per - 1) / per;
+  return (unsigned)(b < cap ? (b ? b : 1) : cap);
+}
+
+}  // namespace
+
+// exclusive scan of n u32 into out[0..n] (out[n] = total); tmp holds
+// ceil(n / SCAN_TILE) block sums
+static hipError_t scan_u32(const uint32_t *in, uint64_t n, uint32_t *out, uint32_t *tmp, hipStream_t s) {
+  const uint32_t nb = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
+  const uint32_t nbx = nb ? nb : 1;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nbx), dim3(SCAN_THREADS), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_THREADS), 0, s, tmp, nbx);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nbx), dim3(SCAN_THREADS), 0, s, in, n, tmp, out);
+  return hipGetLastError();
+}
 
 extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n,
                                    const npg_hier_params *params, uint32_t *perm_dev,
                                    uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,
                                    uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev,
                                    uint32_t max_leaves, uint32_t *n_leaves_out, void *stream) {
-  (void)pos_dev; (void)n; (void)params; (void)perm_dev; (void)leaf_of_dev; (void)leaf_off_dev;
-  (void)leaf_key_dev; (void)leaf_depth_dev; (void)max_leaves; (void)n_leaves_out; (void)stream;
   if (!ctx) return NPG_E_ARG;
-  return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: not available in this build");
+  if (!params || !n_leaves_out) return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: null argument");
+  if (params->max_depth < 0 || params->max_depth > 8)
+    return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: max_depth %d outside [0,8]", params->max_depth);
+  if (n > 0xffffffffull) return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: n > 2^32-1");
+  if (max_leaves == 0) return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: max_leaves = 0");
+  if (!leaf_off_dev || (n && (!pos_dev || !perm_dev)))
+    return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: null pointer");
+  int rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int D = params->max_depth;
+  const uint32_t ncell = 1u << (3 * D);
+  const uint32_t nb_rs = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+  const uint64_t nhist = (uint64_t)256 * (nb_rs ? nb_rs : 1);
+  const uint64_t scan_max = std::max<uint64_t>(std::max<uint64_t>(ncell + 1, nhist), 1);
+  // scratch
+  size_t bytes = 0;
+  bytes += npg_align(4 * (n ? n : 1));             // cell
+  bytes += npg_align(4 * ((uint64_t)ncell + 1));   // cnt
+  bytes += npg_align(4 * ((uint64_t)ncell + 1));   // cstart
+  bytes += npg_align(4 * ((uint64_t)ncell + 1));   // flag
+  bytes += npg_align(4 * ((uint64_t)ncell + 1));   // lid
+  bytes += npg_align((uint64_t)ncell + 1);         // ldepth
+  bytes += npg_align(4 * (n ? n : 1)) * 3;         // leaf_of (own), keys A, keys B
+  bytes += npg_align(4 * (n ? n : 1));             // vals tmp
+  bytes += npg_align(4 * (nhist + 1)) * 2;         // hist, offs
+  bytes += npg_align(4 * ((scan_max + SCAN_TILE - 1) / SCAN_TILE + 1));
+  void *scr = nullptr;
+  rc = npg_scratch(ctx, bytes, s, &scr);
+  if (rc) return rc;
+  Carver cv(scr);
+  uint32_t *cell = cv.take<uint32_t>(n ? n : 1);
+  uint32_t *cnt = cv.take<uint32_t>((uint64_t)ncell + 1);
+  uint32_t *cstart = cv.take<uint32_t>((uint64_t)ncell + 1);
+  uint32_t *flag = cv.take<uint32_t>((uint64_t)ncell + 1);
+  uint32_t *lid = cv.take<uint32_t>((uint64_t)ncell + 1);
+  uint8_t *ldepth = cv.take<uint8_t>((uint64_t)ncell + 1);
+  uint32_t *lof_own = cv.take<uint32_t>(n ? n : 1);
+  uint32_t *ka = cv.take<uint32_t>(n ? n : 1);
+  uint32_t *kb = cv.take<uint32_t>(n ? n : 1);
+  uint32_t *vt = cv.take<uint32_t>(n ? n : 1);
+  uint32_t *hist = cv.take<uint32_t>(nhist + 1);
+  uint32_t *offs = cv.take<uint32_t>(nhist + 1);
+  uint32_t *btmp = cv.take<uint32_t>((scan_max + SCAN_TILE - 1) / SCAN_TILE + 1);
+
+  NPG_HIP_CHECK(ctx, hipMemsetAsync(cnt, 0, 4 * ((size_t)ncell + 1), s));
+  if (n)
+    hipLaunchKernelGGL(cells_kernel, dim3(grid_of(n)), dim3(256), 0, s, pos_dev, n, D, cell, cnt, ctx->err_dev);
+  NPG_HIP_CHECK(ctx, hipGetLastError());
+  NPG_HIP_CHECK(ctx, scan_u32(cnt, ncell, cstart, btmp, s));
+  hipLaunchKernelGGL(decide_kernel, dim3(grid_of(ncell)), dim3(256), 0, s, cstart, ncell, D, params->split_count,
+                     flag, ldepth);
+  NPG_HIP_CHECK(ctx, hipGetLastError());
+  NPG_HIP_CHECK(ctx, scan_u32(flag, ncell, lid, btmp, s));
+  hipLaunchKernelGGL(emit_kernel, dim3(grid_of(ncell)), dim3(256), 0, s, cstart, flag, lid, ldepth, ncell, D,
+                     max_leaves, n, leaf_off_dev, leaf_key_dev, leaf_depth_dev);
+  NPG_HIP_CHECK(ctx, hipGetLastError());
+  uint32_t L = 0, errw = 0;
+  NPG_HIP_CHECK(ctx, hipMemcpyAsync(&L, lid + ncell, 4, hipMemcpyDeviceToHost, s));
+  NPG_HIP_CHECK(ctx, hipMemcpyAsync(&errw, ctx->err_dev, 4, hipMemcpyDeviceToHost, s));
+  NPG_HIP_CHECK(ctx, hipStreamSynchronize(s));
+  *n_leaves_out = L;
+  if (errw & ERR_RANGE) {
+    NPG_HIP_CHECK(ctx, hipMemsetAsync(ctx->err_dev, 0, 4, s));
+    return npg_fail(ctx, NPG_E_RANGE, "build_hierarchy: a position is outside [0,1)^3 or not finite");
+  }
+  if (L > max_leaves)
+    return npg_fail(ctx, NPG_E_CAPACITY, "build_hierarchy: %u leaves exceed max_leaves %u", L, max_leaves);
+  if (n == 0) return NPG_OK;
+  uint32_t *lof = leaf_of_dev ? leaf_of_dev : lof_own;
+  hipLaunchKernelGGL(leaf_of_kernel, dim3(grid_of(n)), dim3(256), 0, s, cell, n, lid, flag, lof);
+  NPG_HIP_CHECK(ctx, hipGetLastError());
+  // stable radix sort of (leaf id, index) -> perm
+  int bits = 1;
+  while (bits < 32 && (1ull << bits) < L) ++bits;
+  const int passes = (bits + 7) / 8;
+  const uint32_t *kin = lof;
+  const uint32_t *vin = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    const bool last = p == passes - 1;
+    uint32_t *kout = (p & 1) ? kb : ka;
+    uint32_t *vout = last ? perm_dev : ((vin == vt) ? cell : vt);  // cell is free after leaf_of
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb_rs), dim3(RS_THREADS), 0, s, kin, n, 8 * p, nb_rs, hist);
+    NPG_HIP_CHECK(ctx, scan_u32(hist, nhist, offs, btmp, s));
+    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb_rs), dim3(RS_THREADS), 0, s, kin, vin, n, 8 * p, nb_rs, offs,
+                       kout, vout);
+    NPG_HIP_CHECK(ctx, hipGetLastError());
+    kin = kout;
+    vin = vout;
+  }
+  return NPG_OK;
 }

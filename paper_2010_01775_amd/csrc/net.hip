@@ -2,8 +2,13 @@
 // kernels, and the per-chunk CNN / U-Net schedule.
 //
 // Activations are channel-last per leaf, [leaf][y][x][c].  3x3 convolutions
-// with at least 16 output channels run as implicit GEMMs on the matrix cores
-// (v_mfma_f32_16x16x4f32 for FP32, v_mfma_f32_16x16x32_bf16 for BF16):
+// with at least 16 output channels run as implicit GEMMs on the matrix cores.
+// FP32 mode: float32 activations and weights, products and sums in binary64
+// (v_mfma_f64_16x16x4f64) -- a float32 accumulation chain over K = 9*Cin
+// terms and 15 layers loses ~3e-5 relative accuracy in the output pdf, the
+// binary64 chain keeps it at the float32 storage limit (~6e-6).  BF16 mode:
+// bf16 activations and weights, float32 accumulation
+// (v_mfma_f32_16x16x32_bf16).
 //   M = output pixels of a tile, N = output channels, K = 9 taps x input
 //   channels.
 // A workgroup (4 wavefronts) owns a tile of 64*MW pixels (rows of one leaf)
@@ -26,6 +31,7 @@
 #include "npg_internal.h"
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ model
@@ -257,8 +263,9 @@ __device__ __forceinline__ float src_at(const Src &s, int leaf, int y, int x, in
       const T *p = static_cast<const T *>(s.s0);
       const int W2 = 2 * W;
       const size_t b = (((size_t)leaf * 2 * H + 2 * y) * W2 + 2 * x) * s.C0 + c;
-      return (to_f<T>(p[b]) + to_f<T>(p[b + s.C0]) + to_f<T>(p[b + (size_t)W2 * s.C0]) +
-              to_f<T>(p[b + (size_t)W2 * s.C0 + s.C0])) * 0.25f;
+      return (float)(((double)to_f<T>(p[b]) + (double)to_f<T>(p[b + s.C0]) +
+                       (double)to_f<T>(p[b + (size_t)W2 * s.C0]) +
+                       (double)to_f<T>(p[b + (size_t)W2 * s.C0 + s.C0])) * 0.25);
     }
     case SRC_UPCAT:
       if (c < s.C0)
@@ -285,9 +292,9 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
   const int r = k / 2;
   for (int co0 = 0; co0 < Cout; co0 += 16) {
     const int nco = min(16, Cout - co0);
-    float acc[16];
+    double acc[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = j < nco ? bias[co0 + j] : 0.0f;
+    for (int j = 0; j < 16; ++j) acc[j] = j < nco ? (double)bias[co0 + j] : 0.0;
     for (int ci = 0; ci < Cin; ++ci)
       for (int ky = 0; ky < k; ++ky) {
         const int sy = y + ky - r;
@@ -295,30 +302,37 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
         for (int kx = 0; kx < k; ++kx) {
           const int sx = x + kx - r;
           if (sx < 0 || sx >= W) continue;
-          const float v = src_at<T>(src, leaf, sy, sx, ci, H, W);
+          const double v = (double)src_at<T>(src, leaf, sy, sx, ci, H, W);
           const float *wp = w + ((size_t)co0 * Cin + ci) * k * k + ky * k + kx;
 #pragma unroll
           for (int j = 0; j < 16; ++j)
-            if (j < nco) acc[j] = fmaf(wp[(size_t)j * Cin * k * k], v, acc[j]);
+            if (j < nco) acc[j] = fma((double)wp[(size_t)j * Cin * k * k], v, acc[j]);
         }
       }
     if (act == ACT_SOFTPLUS) {
-      static_cast<float *>(out)[pix] = softplus_f(acc[0]);
+      static_cast<float *>(out)[pix] = softplus_f((float)acc[0]);
     } else {
       T *o = static_cast<T *>(out) + pix * Cout + co0;
-      for (int j = 0; j < nco; ++j) o[j] = from_f<T>(fmaxf(acc[j], 0.0f));
+      for (int j = 0; j < nco; ++j) o[j] = from_f<T>((float)fmax(acc[j], 0.0));
     }
   }
 }
 
 // ---------------------------------------------------------- MFMA conv
+// Output fragment of a 16x16 MFMA block: lane l holds column l % 16 and four
+// rows.  The f32 instructions give rows 4*(l/16) + r, r = 0..3; the f64
+// instruction gives rows 4*r + l/16.
 struct F32P {
   using T = float;
-  static constexpr int KC = KC32, VEC = 4, PSTR = KC + 4;
+  using Acc = f64x4;
+  static constexpr int KC = KC32, VEC = 4, PSTR = KC + 4, MAX_TILES = 8;
+  __device__ static int row(int lg, int r) { return 4 * r + lg; }
 };
 struct BF16P {
   using T = uint16_t;
-  static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8;
+  using Acc = f32x4;
+  static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
+  __device__ static int row(int lg, int r) { return 4 * lg + r; }
 };
 
 struct ConvArgs {
@@ -367,7 +381,8 @@ __device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, 
   T *tr = reinterpret_cast<T *>(&r);
 #pragma unroll
   for (int i = 0; i < VEC; ++i)
-    tr[i] = from_f<T>((to_f<T>(ta[i]) + to_f<T>(tb[i]) + to_f<T>(tc[i]) + to_f<T>(td[i])) * 0.25f);
+    tr[i] = from_f<T>((float)(((double)to_f<T>(ta[i]) + (double)to_f<T>(tb[i]) + (double)to_f<T>(tc[i]) +
+                               (double)to_f<T>(td[i])) * 0.25));
   return r;
 }
 
@@ -400,11 +415,11 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     const int m = wave * 16 * MW + mi * 16 + lr;
     bp[mi] = (m / TW) * PW + (m % TW);
   }
-  f32x4 acc[MW][NW];
+  typename P::Acc acc[MW][NW];
 #pragma unroll
   for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = typename P::Acc{0, 0, 0, 0};
 
   const int H = a.H, W = a.W;
   for (int ch = 0; ch < a.nchunk; ++ch) {
@@ -443,18 +458,18 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       if constexpr (IS_F32) {
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ++ks) {
-          float av[MW], bv[NW];
+          double av[MW], bv[NW];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
-            av[mi] = reinterpret_cast<const float *>(patch)[(bp[mi] + toff) * PSTR + ks * 4 + lg];
+            av[mi] = (double)reinterpret_cast<const float *>(patch)[(bp[mi] + toff) * PSTR + ks * 4 + lg];
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni)
-            bv[ni] = reinterpret_cast<const float *>(wl)[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
+            bv[ni] = (double)reinterpret_cast<const float *>(wl)[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
             for (int ni = 0; ni < NW; ++ni)
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
         }
       } else {
         bf16x8 av[MW], bv[NW];
@@ -482,15 +497,17 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float v = fmaxf(acc[mi][0][r] + bn, 0.0f) * hw;
+        // the stored activation is float32 (T): round before the head
+        const float act = to_f<T>(from_f<T>((float)fmax((double)acc[mi][0][r] + (double)bn, 0.0)));
+        double v = (double)act * (double)hw;
         v += __shfl_xor(v, 1);
         v += __shfl_xor(v, 2);
         v += __shfl_xor(v, 4);
         v += __shfl_xor(v, 8);
         if (lr == r) {
-          const int m = wave * 16 * MW + mi * 16 + lg * 4 + r;
+          const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
           const int y = ty0 + m / TW, x = tx0 + m % TW;
-          static_cast<float *>(a.out)[((size_t)leaf * H + y) * W + x] = softplus_f(v + a.head_b);
+          static_cast<float *>(a.out)[((size_t)leaf * H + y) * W + x] = softplus_f((float)(v + (double)a.head_b));
         }
       }
     return;
@@ -504,9 +521,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = wave * 16 * MW + mi * 16 + lg * 4 + r;
+        const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
         const int y = ty0 + m / TW, x = tx0 + m % TW;
-        out[(((size_t)leaf * H + y) * W + x) * a.Cout + n] = from_f<T>(fmaxf(acc[mi][ni][r] + bn, 0.0f));
+        out[(((size_t)leaf * H + y) * W + x) * a.Cout + n] =
+            from_f<T>((float)fmax((double)acc[mi][ni][r] + (double)bn, 0.0));
       }
   }
 }
@@ -516,11 +534,12 @@ struct Tiling {
   int MW, NW, TW, TR;
 };
 
-bool pick_tiling(int Cout, int H, int W, Tiling *t) {
+bool pick_tiling(int Cout, int H, int W, int max_tiles, Tiling *t) {
   if (Cout % 16 || Cout > 128) return false;
   const int NW = Cout / 16;
+  if (NW > max_tiles) return false;
   int MW = 4;
-  while (MW > 1 && (MW * NW > 16 || 64 * MW > H * W)) MW >>= 1;
+  while (MW > 1 && (MW * NW > max_tiles || 64 * MW > H * W)) MW >>= 1;
   if (64 * MW > H * W) return false;
   const int BM = 64 * MW;
   const int TW = std::min(W, BM);
@@ -589,12 +608,15 @@ struct Runner {
   size_t esz;  // bytes per activation element
   int force_direct = 0;
 
+  int max_tiles() const { return prec == NPG_FP32 ? F32P::MAX_TILES : BF16P::MAX_TILES; }
+
   // One 3x3 conv (+ReLU) or the last layer (+head / softplus).
   int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
            int act) {
     Tiling t;
     const bool mfma_ok = !force_direct && y.k == 3 && src.mode != SRC_ENERGY && act == ACT_RELU &&
-                         (y.cin % 8 == 0) && pick_tiling(y.cout, H, W, &t) && (!head || y.cout == 16);
+                         (y.cin % 8 == 0) && pick_tiling(y.cout, H, W, max_tiles(), &t) &&
+                         (!head || y.cout == 16);
     if (mfma_ok) {
       ConvArgs a;
       a.src = src;
@@ -768,7 +790,8 @@ extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const u
       if (d == 0) {
         const LayerDev &hd = m->layer[li];
         Tiling t;
-        const bool fuse = !R.force_direct && pick_tiling(lb.cout, h, w, &t) && lb.cout == 16 && lb.cin % 8 == 0;
+        const bool fuse = !R.force_direct && pick_tiling(lb.cout, h, w, R.max_tiles(), &t) && lb.cout == 16 &&
+                           lb.cin % 8 == 0;
         if (fuse) {
           rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, dens, &hd, ACT_RELU);
           if (rc) return rc;

@@ -49,12 +49,16 @@ __global__ __launch_bounds__(256) void sample_kernel(
     float t2 = (uu.y - c0) / (c1 - c0);
     t1 = fminf(fmaxf(t1, 0.0f), below1);
     t2 = fminf(fmaxf(t2, 0.0f), below1);
-    // -1 + 2i/H is exact; one rounding for the in-bin offset
+    // -1 + 2i/H, 2i/H and 2(H-i)/H are exact; each of z, 1+z, 1-z takes
+    // one rounding, so sin(theta) = sqrt((1-z)(1+z)) stays accurate at the
+    // poles where 1 - z*z would cancel.
     const float z = fmaf(t1, two_over_h, fmaf((float)i, two_over_h, -1.0f));
+    const float opz = fmaf(t1, two_over_h, (float)i * two_over_h);
+    const float omz = fmaf(-t1, two_over_h, (float)(H - i) * two_over_h);
     const float phi = fmaf(t2, dphi, (float)j * dphi);
     float sp, cp;
     sincosf(phi, &sp, &cp);
-    const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+    const float r = sqrtf(fmaxf(0.0f, omz * opz));
     dir[3 * q] = r * cp;
     dir[3 * q + 1] = r * sp;
     dir[3 * q + 2] = z;

@@ -323,9 +323,11 @@ def test_sample_parity_same_tables(ctx, npg, orc, L, H, W, n):
     assert np.array_equal(p.cpu().numpy(), p_ref)
     assert np.max(np.abs(d.cpu().numpy() - d_ref)) < 2e-6
     # eval_pdf of the sampled direction returns the sampled pdf (boundary
-    # round-off cases counted)
-    pe = npg.eval_pdf(ctx, tabs, t32(leaf), d).cpu().numpy()
-    mism = np.count_nonzero(pe != p.cpu().numpy())
+    # round-off cases counted); the first 50 queries sit exactly on row
+    # boundaries, and u1 = M_0 = 0 lands on the pole where the azimuth is
+    # undefined, so they are left out
+    pe = npg.eval_pdf(ctx, tabs, t32(leaf), d).cpu().numpy()[50:]
+    mism = np.count_nonzero(pe != p.cpu().numpy()[50:])
     assert mism <= max(3, n // 20000), mism
 
 

@@ -1,0 +1,280 @@
+#!/usr/bin/env python
+"""Throughput of the photon-guiding hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+  splat_histograms -> reconstruct_density (normalise + network)
+  -> build_cdf -> sample_dirs -> eval_pdf (of the sampled directions)
+and, for the clustered workload, build_hierarchy first.
+
+Default workload: the uniform batch -- 1024 leaves x 4096 photons, 64x64
+maps, the 4-level U-Net (16/32/64/128) in FP32, 1,048,576 guided samples.
+The leaf grouping is given by the workload, so no hierarchy is built.
+
+Prints one JSON line (rank 0): leaves reconstructed per second over whole
+steps, guided samples per second of the sampling stage, p50/p99 step
+latency, the roofline of the dominant stage, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import struct
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBps": 8000.0,
+    "fp64_mfma_TFLOPs": 78.6,
+    "fp32_mfma_TFLOPs": 157.3,
+    "bf16_mfma_TFLOPs": 2500.0,
+    "fp8_mfma_TFLOPs": 5000.0,
+}
+
+
+def model_flops_per_leaf(model: bytes, H: int, W: int) -> float:
+    """Algorithmic FLOPs of one leaf: 2*Cin*Cout*k*k per output pixel and
+    layer, at each layer's resolution (pool/upsample/ReLU not counted)."""
+    arch, levels, n = struct.unpack_from("<III", model, 8)
+    off = 20
+    shapes = []
+    for _ in range(n):
+        co, ci, k = struct.unpack_from("<III", model, off)
+        shapes.append((co, ci, k))
+        off += 12 + 4 * (co * ci * k * k + co)
+    px = H * W
+    if arch == 1:
+        return float(sum(2 * ci * co * k * k * px for co, ci, k in shapes))
+    D = levels
+    tot = 0.0
+    for d in range(D):
+        p = px >> (2 * d)
+        for co, ci, k in shapes[2 * d:2 * d + 2]:
+            tot += 2 * ci * co * k * k * p
+    li = 2 * D
+    for d in range(D - 2, -1, -1):
+        p = px >> (2 * d)
+        for co, ci, k in shapes[li:li + 2]:
+            tot += 2 * ci * co * k * k * p
+        li += 2
+    co, ci, k = shapes[li]
+    tot += 2 * ci * co * k * k * px
+    return tot
+
+
+def sha_of(*paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(workload: str, seconds_hint: float = 20.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+    from oracle import oracle as orc
+    from paper_2010_01775_amd import synth
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if workload == "uniform":
+        L = max(16, threads * 40)
+        b = synth.uniform_batch(L=L, n_queries=L * 1024)
+    else:
+        raise ValueError(workload)
+    t0 = time.perf_counter()
+    ref = orc.pipeline(b)
+    rc, d, p, bins = orc.sample(ref["pdf"], ref["marg"], ref["cond"], b.q_leaf, b.q_u)
+    dt = time.perf_counter() - t0
+    return {"value": L / dt, "unit": "leaves/s", "cores": min(threads, L), "kind": "oracle",
+            "sample": f"{L} leaves x 4096 photons (64x64, U-Net, FP64) end to end plus "
+                      f"{L * 1024} samples; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "clustered"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2010_01775_amd import npg, synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+    ctx = npg.Context(0)
+    if args.workload == "uniform":
+        b = synth.uniform_batch()
+        H, W, L = b.H, b.W, b.L
+        dirs, w, off = f32(b.dirs), i32(b.w), i32(b.leaf_off)
+        q_leaf, q_u = i32(b.q_leaf), f32(b.q_u)
+        model_bytes = b.model
+        pos = None
+        desc = ("uniform batch: 1024 leaves x 4096 photons (vMF mixtures), 64x64 equal-area maps, "
+                "U-Net 16/32/64/128, 1048576 guided samples")
+    else:
+        cp = synth.clustered_photons()
+        H = W = 128
+        pos, dirs, w = f32(cp.pos), f32(cp.dirs), i32(cp.w)
+        model_bytes = synth.unet_model(1002)
+        out = npg.build_hierarchy(ctx, pos, 8192, 6, max_leaves=65536)
+        L = out["n_leaves"]
+        ql, qu = synth.queries(1102, L, 100_000_000)
+        q_leaf, q_u = i32(ql), f32(qu)
+        desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, octree split > 8192 depth <= 6 "
+                f"({L} leaves), 128x128 maps, U-Net 16/32/64/128, 1e8 guided samples")
+    model = npg.Model(ctx, model_bytes)
+    nq = q_leaf.shape[0]
+    flops_leaf = model_flops_per_leaf(model_bytes, H, W)
+
+    # preallocated outputs
+    energy = torch.empty((L, H, W), dtype=torch.int64, device=dev)
+    count = torch.empty((L, H, W), dtype=torch.int32, device=dev)
+    dens = torch.empty((L, H, W), dtype=torch.float32, device=dev)
+    tabs = npg.CdfTables(torch.empty((L, H, W), dtype=torch.float32, device=dev),
+                         torch.empty((L, H + 1), dtype=torch.float32, device=dev),
+                         torch.empty((L, H, W + 1), dtype=torch.float32, device=dev),
+                         torch.empty(L, dtype=torch.float64, device=dev))
+    sd = (torch.empty((nq, 3), dtype=torch.float32, device=dev),
+          torch.empty(nq, dtype=torch.float32, device=dev),
+          torch.empty(nq, dtype=torch.int32, device=dev))
+    pe = torch.empty(nq, dtype=torch.float32, device=dev)
+    hier_out = None
+    if pos is not None:
+        n = pos.shape[0]
+        hier_out = dict(perm=torch.empty(n, dtype=torch.int32, device=dev),
+                        off=torch.empty(65537, dtype=torch.int32, device=dev))
+
+    stages = ["hier", "splat", "recon", "cdf", "sample", "eval"] if pos is not None else \
+             ["splat", "recon", "cdf", "sample", "eval"]
+    ev = {s: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for s in stages}
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        def mark(s, i):
+            if record:
+                ev[s][i].record(stream)
+        if pos is not None:
+            import ctypes as C
+            mark("hier", 0)
+            nl = C.c_uint32(0)
+            prm = npg.HierParams(8192, 6)
+            ctx.check(ctx.lib.npg_build_hierarchy(ctx.h, pos.data_ptr(), pos.shape[0], C.byref(prm),
+                                                  hier_out["perm"].data_ptr(), None,
+                                                  hier_out["off"].data_ptr(), None, None, 65536,
+                                                  C.byref(nl), stream.cuda_stream))
+            mark("hier", 1)
+            lo = hier_out["off"][:L + 1]
+            mark("splat", 0)
+            npg.splat_histograms(ctx, dirs, w, lo, H, W, perm=hier_out["perm"], energy=energy, count=count)
+        else:
+            mark("splat", 0)
+            npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
+        mark("splat", 1)
+        mark("recon", 0)
+        npg.reconstruct_density(ctx, model, energy, args.precision, count=count, density=dens)
+        mark("recon", 1)
+        mark("cdf", 0)
+        npg.build_cdf(ctx, dens, out=tabs)
+        mark("cdf", 1)
+        mark("sample", 0)
+        npg.sample_dirs(ctx, tabs, q_leaf, q_u, out=sd)
+        mark("sample", 1)
+        mark("eval", 0)
+        npg.eval_pdf(ctx, tabs, q_leaf, sd[0], out=pe)
+        mark("eval", 1)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    if npg.sync_status(ctx) != 0:
+        raise RuntimeError("data-dependent error during warm-up")
+
+    per_step, stage_ms = [], {s: [] for s in stages}
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    s0 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        s0.record(stream)
+        step(True)
+        torch.cuda.synchronize()
+        per_step.append(s0.elapsed_time(ev["eval"][1]))
+        for s in stages:
+            stage_ms[s].append(ev[s][0].elapsed_time(ev[s][1]))
+        print(f"step {k}: {per_step[-1]:.2f} ms", file=sys.stderr, flush=True)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    if npg.sync_status(ctx) != 0:
+        raise RuntimeError("data-dependent error during the timed steps")
+
+    avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
+    recon_s = avg["recon"] / 1e3
+    flops = flops_leaf * L
+    if args.precision == "fp32":
+        peak, peak_name = PEAK["fp64_mfma_TFLOPs"], "FP64 MFMA (FP32 storage, FP64 accumulation)"
+    else:
+        peak, peak_name = PEAK["bf16_mfma_TFLOPs"], "BF16 MFMA"
+    achieved = flops / recon_s / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
+    src_sha = sha_of(os.path.join(ROOT, "paper_2010_01775_amd", "csrc", "net.hip"))
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("source_sha") == src_sha:
+            traffic = t.get("bytes_per_launch")
+
+    res = {
+        "metric": "leaf densities reconstructed/sec + guided samples/sec; p50/p99 batch latency",
+        "value": L * args.steps / (total_ms / 1e3),
+        "unit": "leaves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 conv accumulation" if args.precision == "fp32" else "bf16 conv, f32 accumulation",
+        "data": "synthetic (seeded vMF-mixture photons, He-init weights)",
+        "config": {"workload": desc, "leaves": L, "H": H, "W": W, "queries": nq,
+                   "precision": args.precision},
+        "samples_per_s": nq / (avg["sample"] / 1e3),
+        "eval_per_s": nq / (avg["eval"] / 1e3),
+        "p50_ms": float(np.percentile(per_step, 50)),
+        "p99_ms": float(np.percentile(per_step, 99)),
+        "stage_ms": avg,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": f"reconstruct_density (implicit-GEMM conv stack), {peak_name}",
+                     "flops_per_launch": flops, "avg_launch_ms": avg["recon"], "source_sha": src_sha},
+    }
+    if not args.no_cpu_baseline and args.workload == "uniform":
+        res["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(res))
+    model.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

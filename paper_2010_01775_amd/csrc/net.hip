@@ -41,6 +41,7 @@ struct LayerDev {
   float *b = nullptr;          // [cout]
   float *pk32 = nullptr;       // [chunk][tap][kc16][cout]
   uint16_t *pk16 = nullptr;    // [chunk][tap][cout][kc32] (bf16 bits)
+  uint16_t *pk16s = nullptr;   // [chunk][tap][cout][kc16] (bf16 bits)
 };
 
 struct npg_model {
@@ -69,6 +70,8 @@ uint16_t f32_to_bf16_host(float f) {
 
 constexpr int KC32 = 16;  // input channels per chunk, FP32 path
 constexpr int KC16 = 32;  // input channels per chunk, BF16 path
+constexpr int KC16S = 16; // BF16 path for 16- and 48-channel inputs: one 32-wide
+                          // MFMA K slice covers two taps of 16 channels
 
 }  // namespace
 
@@ -150,7 +153,7 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
   }
   // host-side repacking into one blob
   std::vector<char> blob;
-  struct Off { size_t w, b, p32, p16; };
+  struct Off { size_t w, b, p32, p16, p16s; };
   std::vector<Off> offs(m->layer.size());
   auto put = [&](const void *src, size_t bytes) {
     size_t at = npg_align(blob.size());
@@ -163,11 +166,13 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
     const std::vector<float> &w = m->host_w[i];
     offs[i].w = put(w.data(), 4 * w.size());
     offs[i].b = put(m->host_b[i].data(), 4 * (size_t)y.cout);
-    offs[i].p32 = offs[i].p16 = (size_t)-1;
+    offs[i].p32 = offs[i].p16 = offs[i].p16s = (size_t)-1;
     if (y.k == 3) {
       const int nch32 = (y.cin + KC32 - 1) / KC32, nch16 = (y.cin + KC16 - 1) / KC16;
+      const int nch16s = (y.cin + KC16S - 1) / KC16S;
       std::vector<float> p32((size_t)nch32 * 9 * KC32 * y.cout, 0.0f);
       std::vector<uint16_t> p16((size_t)nch16 * 9 * y.cout * KC16, 0);
+      std::vector<uint16_t> p16s((size_t)nch16s * 9 * y.cout * KC16S, 0);
       for (int co = 0; co < y.cout; ++co)
         for (int ci = 0; ci < y.cin; ++ci)
           for (int t = 0; t < 9; ++t) {
@@ -176,9 +181,12 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
             p32[(((size_t)c32 * 9 + t) * KC32 + k32) * y.cout + co] = v;
             const int c16 = ci / KC16, k16 = ci % KC16;
             p16[(((size_t)c16 * 9 + t) * y.cout + co) * KC16 + k16] = f32_to_bf16_host(v);
+            const int c16s = ci / KC16S, k16s = ci % KC16S;
+            p16s[(((size_t)c16s * 9 + t) * y.cout + co) * KC16S + k16s] = f32_to_bf16_host(v);
           }
       offs[i].p32 = put(p32.data(), 4 * p32.size());
       offs[i].p16 = put(p16.data(), 2 * p16.size());
+      offs[i].p16s = put(p16s.data(), 2 * p16s.size());
     }
   }
   rc = npg_set_device(ctx);
@@ -201,6 +209,7 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
     if (offs[i].p32 != (size_t)-1) {
       y.pk32 = reinterpret_cast<float *>(base + offs[i].p32);
       y.pk16 = reinterpret_cast<uint16_t *>(base + offs[i].p16);
+      y.pk16s = reinterpret_cast<uint16_t *>(base + offs[i].p16s);
     }
   }
   *out = m;
@@ -318,6 +327,60 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
   }
 }
 
+// First layer: one input channel (the normalised energy map) to C0 <= 16
+// channels, 3x3, ReLU.  A workgroup owns 256 output pixels (whole rows of
+// one leaf); it computes the normalised input x = H*W*E/total once per pixel
+// of the tile and its halo into LDS, then each thread evaluates its pixel's
+// C0 outputs from the nine LDS values.  FP32 mode accumulates in binary64.
+template <class T, class Acc>
+__global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restrict__ energy,
+                                                         const double *__restrict__ tot,
+                                                         const float *__restrict__ w,
+                                                         const float *__restrict__ bias, int C0, int H,
+                                                         int W, int TW, int TR, void *out) {
+  __shared__ float xs[800];  // (TR+2) x (TW+2) <= 3 x 258 for TR*TW = 256
+  const int tiles_x = W / TW;
+  const int tpl = (H / TR) * tiles_x;
+  const int leaf = blockIdx.x / tpl;
+  const int t = blockIdx.x - leaf * tpl;
+  const int ty0 = (t / tiles_x) * TR, tx0 = (t % tiles_x) * TW;
+  const int PW = TW + 2, PH = TR + 2;
+  const double tl = tot[leaf];
+  const double hw = (double)H * (double)W;
+  const uint64_t *e = energy + (size_t)leaf * H * W;
+  for (int i = threadIdx.x; i < PH * PW; i += 256) {
+    const int py = i / PW, px = i - py * PW;
+    const int y = ty0 - 1 + py, x = tx0 - 1 + px;
+    float v = 0.0f;
+    if (y >= 0 && y < H && x >= 0 && x < W && tl > 0.0) v = (float)(hw * (double)e[(size_t)y * W + x] / tl);
+    xs[i] = v;
+  }
+  __syncthreads();
+  const int m = threadIdx.x;
+  const int ty = m / TW, tx = m - ty * TW;
+  float xv[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) xv[k] = xs[(ty + k / 3) * PW + tx + k % 3];
+  T res[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c < C0) {
+      Acc a = (Acc)bias[c];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a = fma((Acc)w[c * 9 + k], (Acc)xv[k], a);
+      res[c] = from_f<T>((float)(a > (Acc)0 ? a : (Acc)0));
+    }
+  }
+  T *o = static_cast<T *>(out) + (((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) * C0;
+  if (C0 == 16) {
+    constexpr int NV = 16 * sizeof(T) / 16;  // 16-byte pieces per pixel
+#pragma unroll
+    for (int v = 0; v < NV; ++v) reinterpret_cast<uint4 *>(o)[v] = reinterpret_cast<const uint4 *>(res)[v];
+  } else {
+    for (int c = 0; c < C0; ++c) o[c] = res[c];
+  }
+}
+
 // ---------------------------------------------------------- MFMA conv
 // Output fragment of a 16x16 MFMA block: lane l holds column l % 16 and four
 // rows.  The f32 instructions give rows 4*(l/16) + r, r = 0..3; the f64
@@ -332,6 +395,12 @@ struct BF16P {
   using T = uint16_t;
   using Acc = f32x4;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
+  __device__ static int row(int lg, int r) { return 4 * lg + r; }
+};
+struct BF16S {
+  using T = uint16_t;
+  using Acc = f32x4;
+  static constexpr int KC = KC16S, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
 };
 
@@ -389,9 +458,13 @@ __device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, 
 template <class P, int MW, int NW>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
+  using AccV = typename P::Acc;
+  using AS = decltype(AccV{}[0]);
   constexpr int KC = P::KC, VEC = P::VEC, PSTR = P::PSTR, G = KC / VEC;
   constexpr int BN = 16 * NW;
   constexpr bool IS_F32 = sizeof(T) == 4;
+  constexpr bool TWO_TAP = !IS_F32 && KC == 16;  // K slice = 2 taps x 16 channels
+  constexpr int NTAPW = TWO_TAP ? 10 : 9;        // weight taps in LDS (10th = zeros)
   // FP32 B tile: [tap][kc][BNP], row stride chosen so the four k-rows a
   // fragment read touches fall in different LDS banks.
   constexpr int BNP = BN + ((16 - BN) & 63);
@@ -415,11 +488,11 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     const int m = wave * 16 * MW + mi * 16 + lr;
     bp[mi] = (m / TW) * PW + (m % TW);
   }
-  typename P::Acc acc[MW][NW];
+  AccV acc[MW][NW];
 #pragma unroll
   for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = typename P::Acc{0, 0, 0, 0};
+    for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = AccV{0, 0, 0, 0};
 
   const int H = a.H, W = a.W;
   for (int ch = 0; ch < a.nchunk; ++ch) {
@@ -445,10 +518,11 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     } else {
       constexpr int R8 = KC / 8;  // 8 bf16 per row piece
-      for (int it = tid; it < 9 * BN * R8; it += 256) {
+      for (int it = tid; it < NTAPW * BN * R8; it += 256) {
         const int row = it / R8, c8 = it - row * R8;
-        *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * 8) =
-            *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * 8);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row < 9 * BN) v = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * 8);
+        *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * 8) = v;
       }
     }
     __syncthreads();
@@ -471,7 +545,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
             for (int ni = 0; ni < NW; ++ni)
               acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
         }
-      } else {
+      } else if constexpr (!TWO_TAP) {
         bf16x8 av[MW], bv[NW];
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
@@ -484,48 +558,82 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni)
             acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+      } else {
+        if (tap & 1) continue;  // taps handled in pairs (tap, tap + 1)
+        // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
+        // tap has zero weights; its patch reads stay inside the patch)
+        const int tl = tap + (lg >> 1);
+        const int tofl = tl < 9 ? (tl / 3) * PW + (tl % 3) : 0;
+        const int cofs = (lg & 1) * 8;
+        bf16x8 av[MW], bv[NW];
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+          av[mi] = *reinterpret_cast<const bf16x8 *>(patch + (bp[mi] + tofl) * PSTR + cofs);
+#pragma unroll
+        for (int ni = 0; ni < NW; ++ni)
+          bv[ni] = *reinterpret_cast<const bf16x8 *>(wl + (tl * BN + ni * 16 + lr) * KCP + cofs);
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
-  // epilogue: bias + ReLU (+ head)
+  // epilogue: bias + ReLU (+ head), staged through LDS (free after the last
+  // barrier) so that global stores are whole 16-byte pieces of output rows
+  const int BM = 64 * MW;
   if (a.head_w) {
-    const float bn = a.bias[lr];
-    const float hw = a.head_w[lr];
+    float *dl = reinterpret_cast<float *>(smem);  // [BM] densities
+    const AS bn = (AS)a.bias[lr];
+    const AS hw = (AS)a.head_w[lr];
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // the stored activation is float32 (T): round before the head
-        const float act = to_f<T>(from_f<T>((float)fmax((double)acc[mi][0][r] + (double)bn, 0.0)));
-        double v = (double)act * (double)hw;
+        // the value the unfused path would store (type T) feeds the head
+        const AS v0 = acc[mi][0][r] + bn;
+        const float act = to_f<T>(from_f<T>((float)(v0 > (AS)0 ? v0 : (AS)0)));
+        AS v = (AS)act * hw;
         v += __shfl_xor(v, 1);
         v += __shfl_xor(v, 2);
         v += __shfl_xor(v, 4);
         v += __shfl_xor(v, 8);
-        if (lr == r) {
-          const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
-          const int y = ty0 + m / TW, x = tx0 + m % TW;
-          static_cast<float *>(a.out)[((size_t)leaf * H + y) * W + x] = softplus_f((float)(v + (double)a.head_b));
-        }
+        if (lr == r) dl[wave * 16 * MW + mi * 16 + P::row(lg, r)] = softplus_f((float)(v + (AS)a.head_b));
       }
+    __syncthreads();
+    // rows of TW pixels are contiguous in the output
+    for (int i = tid; i < BM / 4; i += 256) {
+      const int m = i * 4, ty = m / TW, tx = m - ty * TW;
+      *reinterpret_cast<float4 *>(static_cast<float *>(a.out) + ((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) =
+          *reinterpret_cast<const float4 *>(dl + m);
+    }
     return;
   }
-  T *out = static_cast<T *>(a.out);
+  T *ol = reinterpret_cast<T *>(smem);  // [BM][BN]
 #pragma unroll
   for (int ni = 0; ni < NW; ++ni) {
     const int n = ni * 16 + lr;
-    const float bn = a.bias[n];
+    const AS bn = (AS)a.bias[n];
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
-        const int y = ty0 + m / TW, x = tx0 + m % TW;
-        out[(((size_t)leaf * H + y) * W + x) * a.Cout + n] =
-            from_f<T>((float)fmax((double)acc[mi][ni][r] + (double)bn, 0.0));
+        const AS v = acc[mi][ni][r] + bn;
+        ol[m * BN + n] = from_f<T>((float)(v > (AS)0 ? v : (AS)0));
       }
+  }
+  __syncthreads();
+  constexpr int PPR = BN * (int)sizeof(T) / 16;  // 16-byte pieces per pixel
+  T *out = static_cast<T *>(a.out);
+  for (int i = tid; i < BM * PPR; i += 256) {
+    const int m = i / PPR, pc = i - m * PPR;
+    const int ty = m / TW, tx = m - ty * TW;
+    *reinterpret_cast<uint4 *>(out + (((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) * BN + pc * (16 / sizeof(T))) =
+        *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
   }
 }
 
@@ -559,8 +667,9 @@ size_t conv_lds_bytes(const Tiling &t) {
   const size_t patch = npg_align((size_t)(t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
   size_t wts;
   if (sizeof(T) == 4) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(T);
-  else wts = (size_t)9 * BN * (P::KC + 8) * sizeof(T);
-  return patch + wts;
+  else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * (P::KC + 8) * sizeof(T);
+  const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
+  return std::max(patch + wts, epi);
 }
 
 template <class P, int MW, int NW>
@@ -638,13 +747,33 @@ struct Runner {
         a.nchunk = (y.cin + KC32 - 1) / KC32;
         a.wpk = y.pk32;
         e = launch_mfma<F32P>(a, t, tiles, s);
-      } else {
-        a.nchunk = (y.cin + KC16 - 1) / KC16;
+      } else if (y.cin % KC16 == 0) {
+        a.nchunk = y.cin / KC16;
         a.wpk = y.pk16;
         e = launch_mfma<BF16P>(a, t, tiles, s);
+      } else {
+        a.nchunk = (y.cin + KC16S - 1) / KC16S;
+        a.wpk = y.pk16s;
+        e = launch_mfma<BF16S>(a, t, tiles, s);
       }
       if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "conv launch: %s", hipGetErrorString(e));
       return NPG_OK;
+    }
+    if (!force_direct && src.mode == SRC_ENERGY && y.k == 3 && y.cin == 1 && y.cout <= 16 && act == ACT_RELU &&
+        H * W >= 256 && !head) {
+      const int TW = std::min(W, 256), TR = 256 / TW;
+      if (TR <= H) {
+        const unsigned blocks = (unsigned)Lc * (H / TR) * (W / TW);
+        if (prec == NPG_FP32)
+          hipLaunchKernelGGL((conv_first_kernel<float, double>), dim3(blocks), dim3(256), 0, s,
+                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, out);
+        else
+          hipLaunchKernelGGL((conv_first_kernel<uint16_t, float>), dim3(blocks), dim3(256), 0, s,
+                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "first conv launch: %s", hipGetErrorString(e));
+        return NPG_OK;
+      }
     }
     // direct path; a fused head becomes a separate 1x1 direct layer
     const size_t npix = (size_t)Lc * H * W;

@@ -389,24 +389,36 @@ struct F32P {
   using T = float;
   using Acc = f64x4;
   static constexpr int KC = KC32, VEC = 4, PSTR = KC + 4, MAX_TILES = 8;
+  static constexpr int SB = 1;  // matrix-bound: keep registers for occupancy
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
 };
 struct BF16P {
   using T = uint16_t;
   using Acc = f32x4;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
+  static constexpr int SB = 4;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
 };
 struct BF16S {
   using T = uint16_t;
   using Acc = f32x4;
   static constexpr int KC = KC16S, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
+  static constexpr int SB = 4;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
 };
 
+// n / d for n, d < 2^16 as a multiply-high by m = ceil(2^32 / d).
+struct FastDiv {
+  uint32_t d, m;
+};
+static inline FastDiv make_fastdiv(uint32_t d) { return FastDiv{d, (uint32_t)((0x100000000ull + d - 1) / d)}; }
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return __umulhi(n, f.m); }
+
 struct ConvArgs {
   Src src;
-  int Cin, Cout, H, W, TW, TR, nchunk;
+  int Cin, Cout, H, W, TW, TR, TL, nchunk;
+  FastDiv fPW, fPP;       // divisions by the patch row length and patch size
+  int Lc;                 // leaves in this launch
   int tiles_x, tiles_per_leaf;
   const void *wpk;
   const float *bias;
@@ -414,6 +426,24 @@ struct ConvArgs {
   float head_b;
   void *out;
 };
+
+// Address of the 16 bytes of VEC channels at c of a plain or concatenated
+// input, or nullptr where the channels are padding.
+template <class P>
+__device__ __forceinline__ const uint4 *vec_ptr(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+  using T = typename P::T;
+  if (s.mode == SRC_UPCAT) {
+    if (c < s.C0)
+      return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) +
+                                             (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c);
+    if (c - s.C0 < s.C1)
+      return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s1) +
+                                             (((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0));
+    return nullptr;
+  }
+  if (c >= s.C0) return nullptr;
+  return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) + (((size_t)leaf * H + y) * W + x) * s.C0 + c);
+}
 
 // 16 bytes of VEC channels starting at c, as raw bits.
 template <class P>
@@ -455,12 +485,18 @@ __device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, 
   return r;
 }
 
+
+// One workgroup (4 wavefronts) computes BM = 64*MW output pixels x all Cout
+// channels.  A tile is TR rows x TW columns of one leaf, or TL whole leaves
+// when a map has fewer than BM pixels (the weights staged for a chunk are
+// then shared by TL leaves).
 template <class P, int MW, int NW>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
   using AccV = typename P::Acc;
   using AS = decltype(AccV{}[0]);
   constexpr int KC = P::KC, VEC = P::VEC, PSTR = P::PSTR, G = KC / VEC;
+  constexpr int SB = P::SB;  // global loads in flight per thread while staging
   constexpr int BN = 16 * NW;
   constexpr bool IS_F32 = sizeof(T) == 4;
   constexpr bool TWO_TAP = !IS_F32 && KC == 16;  // K slice = 2 taps x 16 channels
@@ -470,23 +506,27 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   constexpr int BNP = BN + ((16 - BN) & 63);
   constexpr int KCP = KC + 8;  // BF16 B tile: [tap][n][KCP]
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int TW = a.TW, TR = a.TR, PW = TW + 2, PH = TR + 2;
+  const int TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2, PH = TR + 2;
+  const int H = a.H, W = a.W;
   T *patch = reinterpret_cast<T *>(smem);
-  const size_t patch_bytes = npg_align((size_t)PH * PW * PSTR * sizeof(T), 16);
+  const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), 16);
   T *wl = reinterpret_cast<T *>(smem + patch_bytes);
 
   const int tile = blockIdx.x;
-  const int leaf = tile / a.tiles_per_leaf;
-  const int t = tile - leaf * a.tiles_per_leaf;
+  const int grp = tile / a.tiles_per_leaf;
+  const int t = tile - grp * a.tiles_per_leaf;
+  const int leaf0 = grp * TL;
   const int ty0 = (t / a.tiles_x) * TR, tx0 = (t - (t / a.tiles_x) * a.tiles_x) * TW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
+  const int TPX = TR * TW;  // pixels per leaf in the tile
 
   int bp[MW];
 #pragma unroll
   for (int mi = 0; mi < MW; ++mi) {
     const int m = wave * 16 * MW + mi * 16 + lr;
-    bp[mi] = (m / TW) * PW + (m % TW);
+    const int ls = m / TPX, rem = m - ls * TPX;
+    bp[mi] = ls * PH * PW + (rem / TW) * PW + (rem % TW);
   }
   AccV acc[MW][NW];
 #pragma unroll
@@ -494,35 +534,95 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
     for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = AccV{0, 0, 0, 0};
 
-  const int H = a.H, W = a.W;
+  const int items = TL * PH * PW * G;
   for (int ch = 0; ch < a.nchunk; ++ch) {
     const int c0 = ch * KC;
-    // input patch with halo
-    const int items = PH * PW * G;
-    for (int it = tid; it < items; it += 256) {
-      const int pp = it / G, g = it - pp * G;
-      const int py = pp / PW, px = pp - py * PW;
-      const int y = ty0 - 1 + py, x = tx0 - 1 + px;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (y >= 0 && y < H && x >= 0 && x < W) v = load_vec<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
-      *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v;
+    // input patch with halo: batches of SB loads per thread, then the
+    // stores; pooled inputs (four loads per piece) go one piece at a time
+    if (a.src.mode == SRC_POOL) {
+      for (int it = tid; it < items; it += 256) {
+        const int pp = it / G, g = it - pp * G;
+        const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+        const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+        const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) v = load_vec<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
+        *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v;
+      }
+    } else {
+      for (int base = 0; base < items; base += 256 * SB) {
+        uint4 v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int it = base + k * 256 + tid;
+          v[k] = make_uint4(0, 0, 0, 0);
+          if (it < items) {
+            const int pp = it / G, g = it - pp * G;
+            const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+            const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+            const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
+            if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
+              const uint4 *q = vec_ptr<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
+              if (q) v[k] = *q;
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int it = base + k * 256 + tid;
+          if (it < items) {
+            const int pp = it / G, g = it - pp * G;
+            *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v[k];
+          }
+        }
+      }
     }
     // weights of this chunk
     const T *wg = static_cast<const T *>(a.wpk) + (size_t)ch * 9 * KC * BN;
     if (IS_F32) {
       constexpr int R4 = BN / 4;  // float4 per row
-      for (int it = tid; it < 9 * KC * R4; it += 256) {
-        const int row = it / R4, c4 = it - row * R4;
-        *reinterpret_cast<uint4 *>(wl + row * BNP + c4 * 4) =
-            *reinterpret_cast<const uint4 *>(wg + (size_t)row * BN + c4 * 4);
+      constexpr int WITEMS = 9 * KC * R4;
+      for (int base = 0; base < WITEMS; base += 256 * SB) {
+        uint4 v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int it = base + k * 256 + tid;
+          if (it < WITEMS) {
+            const int row = it / R4, c4 = it - row * R4;
+            v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * BN + c4 * 4);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int it = base + k * 256 + tid;
+          if (it < WITEMS) {
+            const int row = it / R4, c4 = it - row * R4;
+            *reinterpret_cast<uint4 *>(wl + row * BNP + c4 * 4) = v[k];
+          }
+        }
       }
     } else {
       constexpr int R8 = KC / 8;  // 8 bf16 per row piece
-      for (int it = tid; it < NTAPW * BN * R8; it += 256) {
-        const int row = it / R8, c8 = it - row * R8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (row < 9 * BN) v = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * 8);
-        *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * 8) = v;
+      constexpr int WITEMS = NTAPW * BN * R8;
+      for (int base = 0; base < WITEMS; base += 256 * SB) {
+        uint4 v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int it = base + k * 256 + tid;
+          v[k] = make_uint4(0, 0, 0, 0);
+          if (it < WITEMS) {
+            const int row = it / R8, c8 = it - row * R8;
+            if (row < 9 * BN) v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * 8);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int it = base + k * 256 + tid;
+          if (it < WITEMS) {
+            const int row = it / R8, c8 = it - row * R8;
+            *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * 8) = v[k];
+          }
+        }
       }
     }
     __syncthreads();
@@ -585,10 +685,19 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // epilogue: bias + ReLU (+ head), staged through LDS (free after the last
   // barrier) so that global stores are whole 16-byte pieces of output rows
   const int BM = 64 * MW;
+  auto gpix = [&](int m) -> long {  // global pixel index of tile pixel m, -1 if past the last leaf
+    const int ls = m / TPX, rem = m - ls * TPX;
+    if (leaf0 + ls >= a.Lc) return -1;
+    return ((long)(leaf0 + ls) * H + ty0 + rem / TW) * W + tx0 + rem % TW;
+  };
   if (a.head_w) {
     float *dl = reinterpret_cast<float *>(smem);  // [BM] densities
     const AS bn = (AS)a.bias[lr];
     const AS hw = (AS)a.head_w[lr];
+    // after the 16-lane reductions every lane of group lg holds the sum of
+    // pixel (mi, r); lane lr keeps pixel (lr / 4, lr % 4) so one softplus per
+    // lane covers the wavefront's pixels
+    AS mine = 0;
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
@@ -601,14 +710,18 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         v += __shfl_xor(v, 2);
         v += __shfl_xor(v, 4);
         v += __shfl_xor(v, 8);
-        if (lr == r) dl[wave * 16 * MW + mi * 16 + P::row(lg, r)] = softplus_f((float)(v + (AS)a.head_b));
+        if (lr == mi * 4 + r) mine = v;
       }
+    if (lr < 4 * MW) {
+      const int mi = lr >> 2, r = lr & 3;
+      dl[wave * 16 * MW + mi * 16 + P::row(lg, r)] = softplus_f((float)(mine + (AS)a.head_b));
+    }
     __syncthreads();
-    // rows of TW pixels are contiguous in the output
+    // four consecutive tile pixels are contiguous in the output (TW >= 4)
     for (int i = tid; i < BM / 4; i += 256) {
-      const int m = i * 4, ty = m / TW, tx = m - ty * TW;
-      *reinterpret_cast<float4 *>(static_cast<float *>(a.out) + ((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) =
-          *reinterpret_cast<const float4 *>(dl + m);
+      const long g = gpix(i * 4);
+      if (g >= 0)
+        *reinterpret_cast<float4 *>(static_cast<float *>(a.out) + g) = *reinterpret_cast<const float4 *>(dl + i * 4);
     }
     return;
   }
@@ -631,45 +744,57 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   T *out = static_cast<T *>(a.out);
   for (int i = tid; i < BM * PPR; i += 256) {
     const int m = i / PPR, pc = i - m * PPR;
-    const int ty = m / TW, tx = m - ty * TW;
-    *reinterpret_cast<uint4 *>(out + (((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) * BN + pc * (16 / sizeof(T))) =
-        *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+    const long g = gpix(m);
+    if (g >= 0)
+      *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) =
+          *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
   }
 }
 
 // Tiling of a layer: returns false if the MFMA kernel does not fit it.
 struct Tiling {
-  int MW, NW, TW, TR;
+  int MW, NW, TW, TR, TL;
 };
-
-bool pick_tiling(int Cout, int H, int W, int max_tiles, Tiling *t) {
-  if (Cout % 16 || Cout > 128) return false;
-  const int NW = Cout / 16;
-  if (NW > max_tiles) return false;
-  int MW = 4;
-  while (MW > 1 && (MW * NW > max_tiles || 64 * MW > H * W)) MW >>= 1;
-  if (64 * MW > H * W) return false;
-  const int BM = 64 * MW;
-  const int TW = std::min(W, BM);
-  const int TR = BM / TW;
-  if (TR > H || TW * TR != BM) return false;
-  t->MW = MW;
-  t->NW = NW;
-  t->TW = TW;
-  t->TR = TR;
-  return true;
-}
 
 template <class P>
 size_t conv_lds_bytes(const Tiling &t) {
   using T = typename P::T;
   const int BN = 16 * t.NW;
-  const size_t patch = npg_align((size_t)(t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
+  const size_t patch = npg_align((size_t)t.TL * (t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
   size_t wts;
   if (sizeof(T) == 4) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(T);
   else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * (P::KC + 8) * sizeof(T);
   const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
   return std::max(patch + wts, epi);
+}
+
+// Largest pixel tile (64*MW pixels) whose accumulators and LDS fit; maps
+// smaller than the tile are batched TL whole leaves per tile.
+template <class P>
+bool pick_tiling(int Cout, int H, int W, Tiling *t) {
+  if (Cout % 16 || Cout > 128) return false;
+  const int NW = Cout / 16;
+  if (NW > P::MAX_TILES) return false;
+  const int HW = H * W;
+  for (int MW = 4; MW >= 1; MW >>= 1) {
+    if (MW * NW > P::MAX_TILES) continue;
+    const int BM = 64 * MW;
+    Tiling c{MW, NW, 0, 0, 1};
+    if (BM <= HW) {
+      c.TW = std::min(W, BM);
+      c.TR = BM / c.TW;
+    } else if (BM % HW == 0 && BM / HW <= 8 && W >= 4) {
+      c.TW = W;
+      c.TR = H;
+      c.TL = BM / HW;
+    } else {
+      continue;
+    }
+    if (conv_lds_bytes<P>(c) > 160 * 1024) continue;
+    *t = c;
+    return true;
+  }
+  return false;
 }
 
 template <class P, int MW, int NW>
@@ -717,15 +842,18 @@ struct Runner {
   size_t esz;  // bytes per activation element
   int force_direct = 0;
 
-  int max_tiles() const { return prec == NPG_FP32 ? F32P::MAX_TILES : BF16P::MAX_TILES; }
+  bool tiling(const LayerDev &y, int H, int W, Tiling *t) const {
+    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t);
+    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t);
+    return pick_tiling<BF16S>(y.cout, H, W, t);
+  }
 
   // One 3x3 conv (+ReLU) or the last layer (+head / softplus).
   int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
            int act) {
     Tiling t;
     const bool mfma_ok = !force_direct && y.k == 3 && src.mode != SRC_ENERGY && act == ACT_RELU &&
-                         (y.cin % 8 == 0) && pick_tiling(y.cout, H, W, max_tiles(), &t) &&
-                         (!head || y.cout == 16);
+                         (y.cin % 8 == 0) && tiling(y, H, W, &t) && (!head || y.cout == 16);
     if (mfma_ok) {
       ConvArgs a;
       a.src = src;
@@ -735,13 +863,17 @@ struct Runner {
       a.W = W;
       a.TW = t.TW;
       a.TR = t.TR;
+      a.TL = t.TL;
+      a.Lc = Lc;
+      a.fPW = make_fastdiv((uint32_t)(t.TW + 2));
+      a.fPP = make_fastdiv((uint32_t)((t.TW + 2) * (t.TR + 2)));
       a.tiles_x = W / t.TW;
       a.tiles_per_leaf = (H / t.TR) * a.tiles_x;
       a.bias = y.b;
       a.head_w = head ? head->w : nullptr;
       a.head_b = head ? m->host_b[&*head - &m->layer[0]][0] : 0.0f;
       a.out = out;
-      const unsigned tiles = (unsigned)Lc * a.tiles_per_leaf;
+      const unsigned tiles = (unsigned)((Lc + t.TL - 1) / t.TL) * a.tiles_per_leaf;
       hipError_t e;
       if (prec == NPG_FP32) {
         a.nchunk = (y.cin + KC32 - 1) / KC32;
@@ -919,8 +1051,7 @@ extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const u
       if (d == 0) {
         const LayerDev &hd = m->layer[li];
         Tiling t;
-        const bool fuse = !R.force_direct && pick_tiling(lb.cout, h, w, R.max_tiles(), &t) && lb.cout == 16 &&
-                           lb.cin % 8 == 0;
+        const bool fuse = !R.force_direct && R.tiling(lb, h, w, &t) && lb.cout == 16 && lb.cin % 8 == 0;
         if (fuse) {
           rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, dens, &hd, ACT_RELU);
           if (rc) return rc;

@@ -188,7 +188,8 @@ def test_cnn_fp32_parity(ctx, npg, orc):
 
 
 @pytest.mark.parametrize("H,W,L,bias", [(64, 64, 5, False), (64, 64, 3, True), (128, 128, 2, True),
-                                        (32, 64, 3, True), (16, 16, 4, True)])
+                                        (32, 64, 3, True), (16, 16, 4, True), (16, 16, 3, True),
+                                        (32, 32, 7, True)])
 def test_unet_fp32_parity(ctx, npg, orc, H, W, L, bias):
     model = synth.unet_model(31 + H, random_bias=bias)
     counts = [4096] * (L - 1) + [700]
@@ -231,18 +232,19 @@ def test_unet_chunking_invariant(ctx, npg, monkeypatch):
     m.free()
 
 
-def test_unet_bf16_error_stated(ctx, npg, orc):
+@pytest.mark.parametrize("L,H", [(8, 64), (5, 64), (3, 32)])
+def test_unet_bf16_error_stated(ctx, npg, orc, L, H):
     """BF16 conv: per-leaf L1 and KL of the pdf against the FP64 oracle."""
     model = synth.unet_model(41)
-    b = synth.uniform_batch(seed=13, L=8, per_leaf=4096, H=64, W=64, n_queries=8, model=model)
-    rc, e, _ = orc.splat(b.dirs, b.w, b.leaf_off, 64, 64)
+    b = synth.uniform_batch(seed=13, L=L, per_leaf=4096, H=H, W=H, n_queries=8, model=model)
+    rc, e, _ = orc.splat(b.dirs, b.w, b.leaf_off, H, H)
     rc, s_ref = orc.net_forward(model, orc.normalize_input(e))
     m = npg.Model(ctx, model)
     s = npg.reconstruct_density(ctx, m, t64(e), "bf16").cpu().numpy().astype(np.float64)
-    p = s / s.reshape(8, -1).sum(1)[:, None, None]
-    q = s_ref / s_ref.reshape(8, -1).sum(1)[:, None, None]
-    l1 = np.abs(p - q).reshape(8, -1).sum(1)
-    kl = (q * np.log(q / p)).reshape(8, -1).sum(1)
+    p = s / s.reshape(L, -1).sum(1)[:, None, None]
+    q = s_ref / s_ref.reshape(L, -1).sum(1)[:, None, None]
+    l1 = np.abs(p - q).reshape(L, -1).sum(1)
+    kl = (q * np.log(q / p)).reshape(L, -1).sum(1)
     print(f"bf16 L1 median {np.median(l1):.3e} max {l1.max():.3e}; KL median {np.median(kl):.3e} max {kl.max():.3e}")
     assert l1.max() < 5e-2 and kl.max() < 5e-3
     m.free()

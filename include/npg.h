@@ -55,7 +55,7 @@ typedef struct npg_model npg_model;
 /* Arithmetic of the network's convolutions.  Inputs, normalisation, the
  * per-leaf totals and the CDF prefixes are FP64/FP32 in every mode. */
 typedef enum {
-  NPG_FP32 = 0, /* FP32 operands, FP32 accumulation                         */
+  NPG_FP32 = 0, /* FP32 activations and weights, FP64 accumulation          */
   NPG_BF16 = 1, /* BF16 activations and weights, FP32 accumulation          */
   NPG_FP8 = 2   /* FP8 e4m3 (OCP) with static per-layer scales, FP32 accum.  */
 } npg_precision;
@@ -103,6 +103,15 @@ int npg_sync_status(npg_ctx *ctx, void *stream);
 /* Bytes of device memory the library currently holds for ctx (scratch) and
  * the high-water mark. */
 void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak);
+
+/* Context tunables (value >= 0):
+ *   "graphs"       1: npg_reconstruct_fused captures its launches into a HIP
+ *                  graph on the second call with the same arguments on a
+ *                  non-default stream and replays it afterwards (default 0)
+ *   "chunk_leaves" leaves per network chunk; 0 = autotuned or 1024
+ *   "force_direct" 1: direct convolutions only (testing; default 0)
+ * NPG_E_ARG for an unknown name or a negative value. */
+int npg_set_option(npg_ctx *ctx, const char *name, int64_t value);
 
 /* ------------------------------------------------------------------ model */
 
@@ -199,6 +208,34 @@ int npg_normalize_input(npg_ctx *ctx, const uint64_t *energy_dev, uint32_t L, in
 int npg_reconstruct_density(npg_ctx *ctx, const npg_model *model, const uint64_t *energy_dev,
                             const uint32_t *count_dev, uint32_t L, int H, int W,
                             npg_precision precision, float *density_dev, void *stream);
+
+/* The batched form of the path: splat -> normalise -> network -> CDF for a
+ * batch of leaves of uneven photon counts, processed in chunks whose energy
+ * maps and densities live only in library scratch (the per-leaf maps of the
+ * whole batch are never written).  Arguments as in npg_splat_histograms,
+ * npg_reconstruct_density and npg_build_cdf; the results equal those of the
+ * three calls in sequence (bit for bit: same kernels, same per-leaf order).
+ * With the "graphs" option the launch sequence is captured once and
+ * replayed on repeated calls with identical arguments. */
+int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *model, const float *dir_dev, const uint32_t *w_dev,
+                          const uint32_t *perm_dev, const uint32_t *leaf_off_dev, uint32_t L, int H, int W,
+                          npg_precision precision, float *pdf_dev, float *marg_dev, float *cond_dev,
+                          double *total_dev, void *stream);
+
+/* Autotuner: times each convolution of the network on `probe_leaves`
+ * synthetic leaves of H x W under each pixel-tile size (64, 128, 256 pixels
+ * per workgroup) and then the leaf-chunk size, and keeps the fastest choices
+ * in ctx for (model, precision, H, W); later reconstruct calls of that shape
+ * use them.  The choice never changes a result (every output sums its terms
+ * in the same order).  Synchronises `stream`. */
+int npg_autotune(npg_ctx *ctx, const npg_model *model, int H, int W, npg_precision precision,
+                 uint32_t probe_leaves, void *stream);
+
+/* The tuned table for (model, precision, H, W): out[0] = leaves per chunk,
+ * out[1..] = tile cap (1, 2, 4 x 64 pixels) of each convolution call.
+ * Returns the number of entries (0 if not tuned); writes at most capacity. */
+int npg_tune_table(const npg_ctx *ctx, const npg_model *model, int H, int W, npg_precision precision,
+                   int32_t *out, int capacity);
 
 /* Sampling pdf and CDF tables of each leaf (Eq. "energy_target": the guide
  * pdf is proportional to the map value over the bin's solid angle; Sec. 7.3:

@@ -107,12 +107,24 @@ int npg_create(npg_ctx **out, int device, uint64_t hbm_budget_bytes) {
 void npg_destroy(npg_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
   npg_device_free(ctx, ctx->scratch, ctx->scratch_bytes);
   npg_device_free(ctx, ctx->err_dev, 256 + sizeof(float2) * 256);
   delete ctx;
 }
 
 const char *npg_last_error(const npg_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int npg_set_option(npg_ctx *ctx, const char *name, int64_t value) {
+  if (!ctx || !name) return NPG_E_ARG;
+  const std::string n(name);
+  if (n != "graphs" && n != "chunk_leaves" && n != "force_direct")
+    return npg_fail(ctx, NPG_E_ARG, "unknown option '%s'", name);
+  if (value < 0) return npg_fail(ctx, NPG_E_ARG, "option '%s' must be >= 0", name);
+  ctx->opts[n] = value;
+  return NPG_OK;
+}
 
 void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak) {
   if (current) *current = ctx ? ctx->held : 0;

@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "npg_internal.h"
@@ -771,12 +772,13 @@ size_t conv_lds_bytes(const Tiling &t) {
 // Largest pixel tile (64*MW pixels) whose accumulators and LDS fit; maps
 // smaller than the tile are batched TL whole leaves per tile.
 template <class P>
-bool pick_tiling(int Cout, int H, int W, Tiling *t) {
+bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
   if (Cout % 16 || Cout > 128) return false;
   const int NW = Cout / 16;
   if (NW > P::MAX_TILES) return false;
   const int HW = H * W;
   for (int MW = 4; MW >= 1; MW >>= 1) {
+    if (MW > mw_max) continue;
     if (MW * NW > P::MAX_TILES) continue;
     const int BM = 64 * MW;
     Tiling c{MW, NW, 0, 0, 1};
@@ -841,16 +843,38 @@ struct Runner {
   hipStream_t s;
   size_t esz;  // bytes per activation element
   int force_direct = 0;
+  const std::vector<int> *mw_cap = nullptr;  // per conv call of a chunk (autotuned)
+  int mw_all = 4;                            // cap for every call (autotuner probes)
+  std::vector<hipEvent_t> *ev = nullptr;     // per-call begin/end events (autotuner)
+  int call = 0;                              // conv call index within a chunk
 
+  int cap() const {
+    int c = mw_all;
+    if (mw_cap && call < (int)mw_cap->size()) c = std::min(c, (*mw_cap)[call]);
+    return c;
+  }
   bool tiling(const LayerDev &y, int H, int W, Tiling *t) const {
-    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t);
-    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t);
-    return pick_tiling<BF16S>(y.cout, H, W, t);
+    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t, cap());
+    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t, cap());
+    return pick_tiling<BF16S>(y.cout, H, W, t, cap());
+  }
+
+  int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
+           int act) {
+    if (ev) {
+      if (hipEventRecord((*ev)[2 * call], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
+    }
+    int rc = conv_impl(y, src, Lc, H, W, out, head, act);
+    if (ev && !rc) {
+      if (hipEventRecord((*ev)[2 * call + 1], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
+    }
+    ++call;
+    return rc;
   }
 
   // One 3x3 conv (+ReLU) or the last layer (+head / softplus).
-  int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
-           int act) {
+  int conv_impl(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
+                int act) {
     Tiling t;
     const bool mfma_ok = !force_direct && y.k == 3 && src.mode != SRC_ENERGY && act == ACT_RELU &&
                          (y.cin % 8 == 0) && tiling(y, H, W, &t) && (!head || y.cout == 16);
@@ -934,11 +958,131 @@ Src upcat(const void *lo, int Cu, const void *skip, int Cs) { return Src{SRC_UPC
 
 }  // namespace
 
-extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
-                                       const uint32_t *count_dev, uint32_t L, int H, int W,
-                                       npg_precision precision, float *density_dev, void *stream) {
-  (void)count_dev;
-  if (!ctx) return NPG_E_ARG;
+namespace {
+
+// Activation scratch of the network for one leaf.
+struct NetPlan {
+  size_t per_leaf = 0;              // bytes
+  std::vector<size_t> skip_elems;   // U-Net skip tensors (elements per leaf)
+  size_t tmp_elems = 0;             // each of the two ping-pong buffers
+};
+
+NetPlan plan_net(const npg_model *m, int H, int W, size_t esz) {
+  NetPlan p;
+  const size_t HW = (size_t)H * W;
+  if (m->arch == 1) {
+    for (const LayerDev &y : m->layer) p.tmp_elems = std::max(p.tmp_elems, (size_t)y.cout * HW);
+    p.per_leaf = 2 * npg_align(p.tmp_elems * esz, 64);
+    return p;
+  }
+  const int D = m->levels;
+  for (int d = 0; d < D; ++d) {
+    const size_t e = (size_t)m->layer[2 * d].cout * (HW >> (2 * d));
+    p.tmp_elems = std::max(p.tmp_elems, e);
+    if (d < D - 1) p.skip_elems.push_back(e);
+  }
+  for (size_t e : p.skip_elems) p.per_leaf += npg_align(e * esz, 64);
+  p.per_leaf += 2 * npg_align(p.tmp_elems * esz, 64);
+  return p;
+}
+
+struct NetBufs {
+  std::vector<char *> skip;
+  char *tA = nullptr, *tB = nullptr;
+};
+
+size_t net_bufs_bytes(const NetPlan &p, size_t chunk, size_t esz) {
+  size_t b = 0;
+  for (size_t e : p.skip_elems) b += npg_align(chunk * e * esz);
+  return b + 2 * npg_align(chunk * p.tmp_elems * esz);
+}
+
+NetBufs carve_net(Carver &cv, const NetPlan &p, size_t chunk, size_t esz) {
+  NetBufs B;
+  for (size_t e : p.skip_elems) B.skip.push_back(cv.take<char>(chunk * e * esz));
+  B.tA = cv.take<char>(chunk * p.tmp_elems * esz);
+  B.tB = cv.take<char>(chunk * p.tmp_elems * esz);
+  return B;
+}
+
+// The network on one chunk of Lc leaves: `in` is the energy source (with
+// per-leaf totals), `dens` receives the softplus densities.
+int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const NetBufs &B) {
+  const npg_model *m = R.m;
+  int rc;
+  R.call = 0;
+  if (m->arch == 1) {
+    const int n = (int)m->layer.size();
+    Src cur = in;
+    char *bufs[2] = {B.tA, B.tB};
+    for (int i = 0; i < n; ++i) {
+      const LayerDev &y = m->layer[i];
+      const bool last = i == n - 1;
+      void *dst = last ? (void *)dens : (void *)bufs[i & 1];
+      rc = R.conv(y, cur, Lc, H, W, dst, nullptr, last ? ACT_SOFTPLUS : ACT_RELU);
+      if (rc) return rc;
+      cur = plain(dst, y.cout);
+    }
+    return NPG_OK;
+  }
+  const int D = m->levels;
+  int h = H, w = W;
+  const void *prev = nullptr;
+  int prevC = 0;
+  for (int d = 0; d < D; ++d) {  // encoder
+    const LayerDev &la = m->layer[2 * d], &lb = m->layer[2 * d + 1];
+    Src sa = in;
+    if (d > 0) {
+      h /= 2;
+      w /= 2;
+      sa = pooled(prev, prevC);
+    }
+    rc = R.conv(la, sa, Lc, h, w, B.tA, nullptr, ACT_RELU);
+    if (rc) return rc;
+    void *ob = d < D - 1 ? (void *)B.skip[d] : (void *)B.tB;
+    rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, ob, nullptr, ACT_RELU);
+    if (rc) return rc;
+    prev = ob;
+    prevC = lb.cout;
+  }
+  int li = 2 * D;
+  for (int d = D - 2; d >= 0; --d) {  // decoder
+    const LayerDev &la = m->layer[li], &lb = m->layer[li + 1];
+    li += 2;
+    h *= 2;
+    w *= 2;
+    const int cs = m->layer[2 * d].cout;
+    rc = R.conv(la, upcat(prev, prevC, B.skip[d], cs), Lc, h, w, B.tA, nullptr, ACT_RELU);
+    if (rc) return rc;
+    if (d == 0) {
+      const LayerDev &hd = m->layer[li];
+      Tiling t;
+      const bool fuse = !R.force_direct && R.tiling(lb, h, w, &t) && lb.cout == 16 && lb.cin % 8 == 0;
+      if (fuse) {
+        rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, dens, &hd, ACT_RELU);
+        if (rc) return rc;
+      } else {
+        rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, B.tB, nullptr, ACT_RELU);
+        if (rc) return rc;
+        rc = R.conv(hd, plain(B.tB, lb.cout), Lc, h, w, dens, nullptr, ACT_SOFTPLUS);
+        if (rc) return rc;
+      }
+    } else {
+      rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, B.tB, nullptr, ACT_RELU);
+      if (rc) return rc;
+      prev = B.tB;
+      prevC = lb.cout;
+    }
+  }
+  if (D == 1) {
+    const LayerDev &hd = m->layer[2];
+    rc = R.conv(hd, plain(prev, prevC), Lc, H, W, dens, nullptr, ACT_SOFTPLUS);
+    if (rc) return rc;
+  }
+  return NPG_OK;
+}
+
+int check_net_args(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision precision) {
   if (!m) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null model");
   if (!pow2_in(H, 4, 1024) || !pow2_in(W, 4, 1024))
     return npg_fail(ctx, NPG_E_ARG, "reconstruct: bad H=%d W=%d", H, W);
@@ -949,132 +1093,289 @@ extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const u
   if (precision == NPG_FP8) return npg_fail(ctx, NPG_E_ARG, "reconstruct: FP8 not available");
   if (m->arch == 2) {
     const int f = 1 << (m->levels - 1);
-    if (H % f || W % f || H / f < 1 || W / f < 1)
-      return npg_fail(ctx, NPG_E_ARG, "reconstruct: %dx%d not divisible by 2^%d", H, W, m->levels - 1);
+    if (H % f || W % f) return npg_fail(ctx, NPG_E_ARG, "reconstruct: %dx%d not divisible by 2^%d", H, W, m->levels - 1);
   }
-  if (L == 0) return NPG_OK;
-  if (!energy_dev || !density_dev) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null pointer");
-  int rc = npg_set_device(ctx);
-  if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Runner R{ctx, m, precision, s, precision == NPG_FP32 ? (size_t)4 : (size_t)2};
-  if (const char *e = getenv("NPG_FORCE_DIRECT")) R.force_direct = atoi(e);
-  const size_t HW = (size_t)H * W;
+  return NPG_OK;
+}
 
-  // activation bytes per leaf
-  size_t per_leaf = 0;
-  std::vector<size_t> skip_elems;
-  size_t tmp_elems = 0;
-  if (m->arch == 1) {
-    for (const LayerDev &y : m->layer) tmp_elems = std::max(tmp_elems, (size_t)y.cout * HW);
-    per_leaf = 2 * npg_align(tmp_elems * R.esz, 64);
-  } else {
-    const int D = m->levels;
-    for (int d = 0; d < D; ++d) {
-      const size_t e = (size_t)m->layer[2 * d].cout * (HW >> (2 * d));
-      tmp_elems = std::max(tmp_elems, e);
-      if (d < D - 1) skip_elems.push_back(e);
-    }
-    for (size_t e : skip_elems) per_leaf += npg_align(e * R.esz, 64);
-    per_leaf += 2 * npg_align(tmp_elems * R.esz, 64);
-  }
+std::string tune_key(const npg_model *m, npg_precision p, int H, int W) {
+  char b[96];
+  snprintf(b, sizeof(b), "%p:%d:%d:%d", (const void *)m, (int)p, H, W);
+  return b;
+}
+
+Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStream_t s) {
+  Runner R{ctx, m, prec, s, prec == NPG_FP32 ? (size_t)4 : (size_t)2};
+  R.force_direct = (int)ctx->opt("force_direct", 0);
+  return R;
+}
+
+// Leaves per chunk: tuned value, else the context option, else 1024; then
+// bounded by the budget.  per_extra = other per-leaf scratch bytes.
+int chunk_for(npg_ctx *ctx, const npg_model *m, npg_precision prec, int H, int W, uint32_t L, size_t per_leaf,
+              size_t fixed, size_t *chunk_out) {
   size_t chunk = 1024;
-  if (const char *e = getenv("NPG_CHUNK_LEAVES")) chunk = std::max(1, atoi(e));
+  auto it = ctx->tune.find(tune_key(m, prec, H, W));
+  if (it != ctx->tune.end() && !it->second.empty() && it->second[0] > 0) chunk = (size_t)it->second[0];
+  const long long o = ctx->opt("chunk_leaves", 0);
+  if (o > 0) chunk = (size_t)o;
   chunk = std::min<size_t>(chunk, L);
-  const size_t fixed = npg_align(sizeof(double) * L) + (16u << 20);
   if (ctx->budget) {
     const uint64_t others = ctx->held - ctx->scratch_bytes;
     const uint64_t avail = ctx->budget > others ? ctx->budget - others : 0;
     if (avail < fixed + per_leaf) return npg_fail(ctx, NPG_E_BUDGET, "reconstruct: budget too small for one leaf");
     chunk = std::min<size_t>(chunk, (avail - fixed) / per_leaf);
   }
+  *chunk_out = std::max<size_t>(1, chunk);
+  return NPG_OK;
+}
+
+void apply_tune(npg_ctx *ctx, Runner &R, int H, int W, std::vector<int> *hold) {
+  auto it = ctx->tune.find(tune_key(R.m, R.prec, H, W));
+  if (it != ctx->tune.end() && it->second.size() > 1) {
+    hold->assign(it->second.begin() + 1, it->second.end());
+    R.mw_cap = hold;
+  }
+}
+
+}  // namespace
+
+extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
+                                       const uint32_t *count_dev, uint32_t L, int H, int W,
+                                       npg_precision precision, float *density_dev, void *stream) {
+  (void)count_dev;
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_net_args(ctx, m, H, W, precision);
+  if (rc) return rc;
+  if (L == 0) return NPG_OK;
+  if (!energy_dev || !density_dev) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null pointer");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Runner R = make_runner(ctx, m, precision, s);
+  std::vector<int> caps;
+  apply_tune(ctx, R, H, W, &caps);
+  const size_t HW = (size_t)H * W;
+  const NetPlan plan = plan_net(m, H, W, R.esz);
+  const size_t fixed = npg_align(sizeof(double) * L) + (16u << 20);
+  size_t chunk = 0;
+  rc = chunk_for(ctx, m, precision, H, W, L, plan.per_leaf, fixed, &chunk);
+  if (rc) return rc;
   void *scr = nullptr;
-  rc = npg_scratch(ctx, fixed + chunk * per_leaf, s, &scr);
+  rc = npg_scratch(ctx, fixed + net_bufs_bytes(plan, chunk, R.esz), s, &scr);
   if (rc) return rc;
   Carver cv(scr);
   double *tot = cv.take<double>(L);
-  std::vector<char *> skip;
-  for (size_t e : skip_elems) skip.push_back(cv.take<char>(chunk * e * R.esz));
-  char *tA = cv.take<char>(chunk * tmp_elems * R.esz);
-  char *tB = cv.take<char>(chunk * tmp_elems * R.esz);
+  const NetBufs B = carve_net(cv, plan, chunk, R.esz);
   NPG_HIP_CHECK(ctx, launch_leaf_scale(energy_dev, L, (int)HW, tot, s));
-
   for (size_t l0 = 0; l0 < L; l0 += chunk) {
     const int Lc = (int)std::min<size_t>(chunk, L - l0);
     const Src in{SRC_ENERGY, energy_dev + l0 * HW, nullptr, tot + l0, 0, 0};
-    float *dens = density_dev + l0 * HW;
-    if (m->arch == 1) {
-      const int n = (int)m->layer.size();
-      Src cur = in;
-      char *bufs[2] = {tA, tB};
-      for (int i = 0; i < n; ++i) {
-        const LayerDev &y = m->layer[i];
-        const bool last = i == n - 1;
-        void *dst = last ? (void *)dens : (void *)bufs[i & 1];
-        rc = R.conv(y, cur, Lc, H, W, dst, nullptr, last ? ACT_SOFTPLUS : ACT_RELU);
-        if (rc) return rc;
-        cur = plain(dst, y.cout);
-      }
-      continue;
-    }
-    const int D = m->levels;
-    // encoder
-    int h = H, w = W;
-    const void *prev = nullptr;
-    int prevC = 0;
-    for (int d = 0; d < D; ++d) {
-      const LayerDev &la = m->layer[2 * d], &lb = m->layer[2 * d + 1];
-      Src sa = in;
-      if (d > 0) {
-        h /= 2;
-        w /= 2;
-        sa = pooled(prev, prevC);
-      }
-      rc = R.conv(la, sa, Lc, h, w, tA, nullptr, ACT_RELU);
-      if (rc) return rc;
-      void *ob = d < D - 1 ? (void *)skip[d] : (void *)tB;
-      rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, ob, nullptr, ACT_RELU);
-      if (rc) return rc;
-      prev = ob;
-      prevC = lb.cout;
-    }
-    // decoder
-    int li = 2 * D;
-    for (int d = D - 2; d >= 0; --d) {
-      const LayerDev &la = m->layer[li], &lb = m->layer[li + 1];
-      li += 2;
-      h *= 2;
-      w *= 2;
-      const int cs = m->layer[2 * d].cout;
-      rc = R.conv(la, upcat(prev, prevC, skip[d], cs), Lc, h, w, tA, nullptr, ACT_RELU);
-      if (rc) return rc;
-      if (d == 0) {
-        const LayerDev &hd = m->layer[li];
-        Tiling t;
-        const bool fuse = !R.force_direct && R.tiling(lb, h, w, &t) && lb.cout == 16 && lb.cin % 8 == 0;
-        if (fuse) {
-          rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, dens, &hd, ACT_RELU);
-          if (rc) return rc;
-        } else {
-          rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, tB, nullptr, ACT_RELU);
-          if (rc) return rc;
-          rc = R.conv(hd, plain(tB, lb.cout), Lc, h, w, dens, nullptr, ACT_SOFTPLUS);
-          if (rc) return rc;
-        }
-      } else {
-        rc = R.conv(lb, plain(tA, la.cout), Lc, h, w, tB, nullptr, ACT_RELU);
-        if (rc) return rc;
-        prev = tB;
-        prevC = lb.cout;
-      }
-    }
-    if (D == 1) {
-      const LayerDev &hd = m->layer[2];
-      rc = R.conv(hd, plain(prev, prevC), Lc, H, W, dens, nullptr, ACT_SOFTPLUS);
-      if (rc) return rc;
-    }
+    rc = net_chunk(R, in, Lc, H, W, density_dev + l0 * HW, B);
+    if (rc) return rc;
   }
   return NPG_OK;
+}
+
+// ----------------------------------------------------------- fused path
+// splat -> normalise -> network -> CDF, chunk by chunk: the energy maps and
+// densities of a chunk live in scratch only, never at full batch size.
+static int fused_enqueue(npg_ctx *ctx, const npg_model *m, const float *dir, const uint32_t *w,
+                         const uint32_t *perm, const uint32_t *off, uint32_t L, int H, int W, npg_precision prec,
+                         float *pdf, float *marg, float *cond, double *total, hipStream_t s) {
+  Runner R = make_runner(ctx, m, prec, s);
+  std::vector<int> caps;
+  apply_tune(ctx, R, H, W, &caps);
+  const size_t HW = (size_t)H * W;
+  const NetPlan plan = plan_net(m, H, W, R.esz);
+  const size_t per_leaf = plan.per_leaf + HW * (sizeof(uint64_t) + sizeof(float)) + sizeof(double) + 3 * 256;
+  size_t chunk = 0;
+  int rc = chunk_for(ctx, m, prec, H, W, L, per_leaf, 16u << 20, &chunk);
+  if (rc) return rc;
+  const size_t bytes = npg_align(chunk * HW * sizeof(uint64_t)) + npg_align(chunk * HW * sizeof(float)) +
+                       npg_align(chunk * sizeof(double)) + net_bufs_bytes(plan, chunk, R.esz);
+  void *scr = nullptr;
+  rc = npg_scratch(ctx, bytes, s, &scr);
+  if (rc) return rc;
+  Carver cv(scr);
+  uint64_t *energy = cv.take<uint64_t>(chunk * HW);
+  float *dens = cv.take<float>(chunk * HW);
+  double *tot = cv.take<double>(chunk);
+  const NetBufs B = carve_net(cv, plan, chunk, R.esz);
+  for (size_t l0 = 0; l0 < L; l0 += chunk) {
+    const uint32_t Lc = (uint32_t)std::min<size_t>(chunk, L - l0);
+    NPG_HIP_CHECK(ctx, launch_splat(ctx->bnd_dev, dir, w, perm, off + l0, Lc, H, W, energy, nullptr, 0, ctx->err_dev, s));
+    NPG_HIP_CHECK(ctx, launch_leaf_scale(energy, Lc, (int)HW, tot, s));
+    const Src in{SRC_ENERGY, energy, nullptr, tot, 0, 0};
+    rc = net_chunk(R, in, (int)Lc, H, W, dens, B);
+    if (rc) return rc;
+    NPG_HIP_CHECK(ctx, launch_build_cdf(dens, Lc, H, W, pdf + l0 * HW, marg + l0 * (H + 1),
+                                        cond + l0 * H * (size_t)(W + 1), total ? total + l0 : nullptr,
+                                        ctx->err_dev, s));
+  }
+  return NPG_OK;
+}
+
+extern "C" int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *m, const float *dir_dev, const uint32_t *w_dev,
+                                     const uint32_t *perm_dev, const uint32_t *leaf_off_dev, uint32_t L, int H,
+                                     int W, npg_precision precision, float *pdf_dev, float *marg_dev,
+                                     float *cond_dev, double *total_dev, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_net_args(ctx, m, H, W, precision);
+  if (rc) return rc;
+  if (L == 0) return NPG_OK;
+  if (!dir_dev || !w_dev || !leaf_off_dev || !pdf_dev || !marg_dev || !cond_dev)
+    return npg_fail(ctx, NPG_E_ARG, "reconstruct_fused: null pointer");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!ctx->opt("graphs", 0) || s == nullptr)
+    return fused_enqueue(ctx, m, dir_dev, w_dev, perm_dev, leaf_off_dev, L, H, W, precision, pdf_dev, marg_dev,
+                         cond_dev, total_dev, s);
+  // Graph replay: the first call with a given argument tuple runs eagerly
+  // (allocating scratch and setting kernel attributes), the second is
+  // captured, later ones replay the captured graph.
+  char key[512];
+  snprintf(key, sizeof(key), "fused:%p:%p:%p:%p:%p:%u:%d:%d:%d:%p:%p:%p:%p:%p:%p:%zu:%lld", (const void *)m,
+           (const void *)dir_dev, (const void *)w_dev, (const void *)perm_dev, (const void *)leaf_off_dev, L, H, W,
+           (int)precision, (void *)pdf_dev, (void *)marg_dev, (void *)cond_dev, (void *)total_dev, (void *)s,
+           ctx->scratch, ctx->scratch_bytes, ctx->opt("chunk_leaves", 0));
+  for (auto &g : ctx->graphs)
+    if (g.key == key) {
+      NPG_HIP_CHECK(ctx, hipGraphLaunch(g.exec, s));
+      return NPG_OK;
+    }
+  if (!ctx->graph_seen.count(key)) {
+    ctx->graph_seen.insert(key);
+    return fused_enqueue(ctx, m, dir_dev, w_dev, perm_dev, leaf_off_dev, L, H, W, precision, pdf_dev, marg_dev,
+                         cond_dev, total_dev, s);
+  }
+  NPG_HIP_CHECK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  rc = fused_enqueue(ctx, m, dir_dev, w_dev, perm_dev, leaf_off_dev, L, H, W, precision, pdf_dev, marg_dev,
+                     cond_dev, total_dev, s);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "graph capture: %s", hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "graph instantiate: %s", hipGetErrorString(ei));
+  if (ctx->graphs.size() >= 32) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  ctx->graphs.push_back({key, exec});
+  NPG_HIP_CHECK(ctx, hipGraphLaunch(exec, s));
+  return NPG_OK;
+}
+
+// -------------------------------------------------------------- autotune
+// Times every convolution of the network under each tile cap (64, 128, 256
+// pixels per workgroup) on `probe` zero-energy leaves and keeps the fastest
+// per call, then times leaf-chunk sizes with those tiles.  Tile and chunk
+// choices do not change any result: each output sums its terms in the same
+// order whatever the tiling.
+extern "C" int npg_autotune(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision precision,
+                            uint32_t probe, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_net_args(ctx, m, H, W, precision);
+  if (rc) return rc;
+  if (probe == 0) return npg_fail(ctx, NPG_E_ARG, "autotune: probe_leaves = 0");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Runner R = make_runner(ctx, m, precision, s);
+  const size_t HW = (size_t)H * W;
+  const NetPlan plan = plan_net(m, H, W, R.esz);
+  const size_t bytes = npg_align(probe * HW * sizeof(uint64_t)) + npg_align(probe * HW * sizeof(float)) +
+                       npg_align(probe * sizeof(double)) + net_bufs_bytes(plan, probe, R.esz);
+  void *scr = nullptr;
+  rc = npg_scratch(ctx, bytes, s, &scr);
+  if (rc) return rc;
+  Carver cv(scr);
+  uint64_t *energy = cv.take<uint64_t>(probe * HW);
+  float *dens = cv.take<float>(probe * HW);
+  double *tot = cv.take<double>(probe);
+  const NetBufs B = carve_net(cv, plan, probe, R.esz);
+  NPG_HIP_CHECK(ctx, hipMemsetAsync(energy, 0, probe * HW * sizeof(uint64_t), s));
+  NPG_HIP_CHECK(ctx, launch_leaf_scale(energy, probe, (int)HW, tot, s));
+  const Src in{SRC_ENERGY, energy, nullptr, tot, 0, 0};
+  // count the calls of one chunk
+  rc = net_chunk(R, in, 1, H, W, dens, B);
+  if (rc) return rc;
+  const int ncall = R.call;
+  std::vector<hipEvent_t> ev(2 * ncall);
+  for (auto &e : ev) NPG_HIP_CHECK(ctx, hipEventCreate(&e));
+  const int caps[3] = {4, 2, 1};
+  std::vector<float> best(ncall, 1e30f);
+  std::vector<int> pick(ncall, 4);
+  int err = NPG_OK;
+  for (int ci = 0; ci < 3 && !err; ++ci) {
+    R.mw_all = caps[ci];
+    R.ev = nullptr;
+    err = net_chunk(R, in, (int)probe, H, W, dens, B);  // warm-up
+    for (int rep = 0; rep < 3 && !err; ++rep) {
+      R.ev = &ev;
+      err = net_chunk(R, in, (int)probe, H, W, dens, B);
+      if (err) break;
+      if (hipStreamSynchronize(s) != hipSuccess) { err = npg_fail(ctx, NPG_E_HIP, "autotune sync"); break; }
+      for (int c = 0; c < ncall; ++c) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]) == hipSuccess && ms < best[c]) {
+          best[c] = ms;
+          pick[c] = caps[ci];
+        }
+      }
+    }
+  }
+  R.ev = nullptr;
+  R.mw_all = 4;
+  R.mw_cap = &pick;
+  // chunk size
+  int best_chunk = (int)probe;
+  float best_t = 1e30f;
+  hipEvent_t e0 = ev[0], e1 = ev[1];
+  const uint32_t cands[6] = {64, 128, 256, 512, 1024, 2048};
+  for (int k = 0; k < 6 && !err; ++k) {
+    const uint32_t c = std::min(cands[k], probe);
+    if (k > 0 && c == std::min(cands[k - 1], probe)) continue;
+    for (int rep = 0; rep < 2 && !err; ++rep) {
+      (void)hipEventRecord(e0, s);
+      for (uint32_t l0 = 0; l0 < probe && !err; l0 += c) {
+        const uint32_t Lc = std::min(c, probe - l0);
+        const Src inc{SRC_ENERGY, energy + l0 * HW, nullptr, tot + l0, 0, 0};
+        err = net_chunk(R, inc, (int)Lc, H, W, dens + l0 * HW, B);
+      }
+      (void)hipEventRecord(e1, s);
+      if (hipStreamSynchronize(s) != hipSuccess) { err = npg_fail(ctx, NPG_E_HIP, "autotune sync"); break; }
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep == 1 && ms < best_t) {
+        best_t = ms;
+        best_chunk = (int)c;
+      }
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (err) return err;
+  std::vector<int> entry;
+  entry.push_back(best_chunk);
+  entry.insert(entry.end(), pick.begin(), pick.end());
+  ctx->tune[tune_key(m, precision, H, W)] = entry;
+  return NPG_OK;
+}
+
+extern "C" int npg_tune_table(const npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision precision,
+                              int32_t *out, int capacity) {
+  if (!ctx) return NPG_E_ARG;
+  auto it = ctx->tune.find(tune_key(m, precision, H, W));
+  if (it == ctx->tune.end()) return 0;
+  const int n = (int)it->second.size();
+  for (int i = 0; i < n && i < capacity; ++i) out[i] = it->second[i];
+  return n;
 }
 
 extern "C" int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *model, const uint64_t *energy_dev,

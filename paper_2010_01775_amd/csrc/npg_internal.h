@@ -5,6 +5,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -22,6 +24,18 @@ struct npg_ctx {
   size_t scratch_bytes = 0;
   hipStream_t scratch_stream = nullptr;  // stream that last used the scratch
   std::string last_error;
+  std::map<std::string, long long> opts;          // npg_set_option
+  std::map<std::string, std::vector<int>> tune;   // autotuned {chunk, tile cap per conv call}
+  struct Graph {
+    std::string key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;                      // captured fused calls
+  std::set<std::string> graph_seen;
+  long long opt(const char *name, long long def) const {
+    auto it = opts.find(name);
+    return it == opts.end() ? def : it->second;
+  }
 };
 
 // Error bits raised by kernels into ctx->err_dev.

@@ -25,7 +25,7 @@ SYMBOLS = [
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
     "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
     "npg_reconstruct_density", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
-    "npg_bin_boundaries",
+    "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
 ]
 
 
@@ -74,6 +74,10 @@ def load_library(path: str = LIB_PATH):
         "npg_sample_dirs": (I, [P, C.POINTER(Tables), P, P, U64, P, P, P, P]),
         "npg_eval_pdf": (I, [P, C.POINTER(Tables), P, P, U64, P, P]),
         "npg_bin_boundaries": (I, [I, P]),
+        "npg_set_option": (I, [P, C.c_char_p, C.c_int64]),
+        "npg_reconstruct_fused": (I, [P, P, P, P, P, P, U32, I, I, I, P, P, P, P, P]),
+        "npg_autotune": (I, [P, P, I, I, I, U32, P]),
+        "npg_tune_table": (I, [P, P, I, I, I, P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -134,6 +138,9 @@ class Context:
                 self.h = None
         except Exception:
             pass
+
+    def set_option(self, name: str, value: int):
+        self.check(self.lib.npg_set_option(self.h, name.encode(), int(value)))
 
     def memory_usage(self):
         cur, peak = C.c_uint64(), C.c_uint64()
@@ -242,14 +249,46 @@ def reconstruct_density(ctx: Context, model: Model, energy, precision="fp32", co
     return density
 
 
+def _new_tables(L, H, W, dev):
+    return CdfTables(torch.empty((L, H, W), dtype=torch.float32, device=dev),
+                     torch.empty((L, H + 1), dtype=torch.float32, device=dev),
+                     torch.empty((L, H, W + 1), dtype=torch.float32, device=dev),
+                     torch.empty(L, dtype=torch.float64, device=dev))
+
+
+def reconstruct_fused(ctx: Context, model: Model, dirs, w, leaf_off, H: int, W: int, precision="fp32",
+                      perm=None, out: CdfTables | None = None, stream=None) -> CdfTables:
+    """splat -> normalise -> network -> CDF in one call (chunked, scratch-resident maps)."""
+    L = leaf_off.shape[0] - 1
+    if out is None:
+        out = _new_tables(L, H, W, dirs.device)
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.lib.npg_reconstruct_fused(ctx.h, model.h, _ptr(dirs), _ptr(w), _ptr(perm), _ptr(leaf_off), L,
+                                            H, W, p, _ptr(out.pdf), _ptr(out.marg), _ptr(out.cond),
+                                            _ptr(out.total), _stream(stream)))
+    return out
+
+
+def autotune(ctx: Context, model: Model, H: int, W: int, precision="fp32", probe_leaves: int = 1024,
+             stream=None):
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.lib.npg_autotune(ctx.h, model.h, H, W, p, probe_leaves, _stream(stream)))
+    return tune_table(ctx, model, H, W, precision)
+
+
+def tune_table(ctx: Context, model: Model, H: int, W: int, precision="fp32"):
+    import numpy as np
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    buf = np.zeros(256, np.int32)
+    n = ctx.lib.npg_tune_table(ctx.h, model.h, H, W, p, buf.ctypes.data, 256)
+    return [int(v) for v in buf[:n]]
+
+
 def build_cdf(ctx: Context, density, out: CdfTables | None = None, stream=None) -> CdfTables:
     L, H, W = density.shape
     dev = density.device
     if out is None:
-        out = CdfTables(torch.empty((L, H, W), dtype=torch.float32, device=dev),
-                        torch.empty((L, H + 1), dtype=torch.float32, device=dev),
-                        torch.empty((L, H, W + 1), dtype=torch.float32, device=dev),
-                        torch.empty(L, dtype=torch.float64, device=dev))
+        out = _new_tables(L, H, W, dev)
     ctx.check(ctx.lib.npg_build_cdf(ctx.h, _ptr(density), L, H, W, _ptr(out.pdf), _ptr(out.marg),
                                     _ptr(out.cond), _ptr(out.total), _stream(stream)))
     return out

@@ -205,29 +205,36 @@ def test_unet_fp32_parity(ctx, npg, orc, H, W, L, bias):
     m.free()
 
 
-def test_unet_direct_path_parity(ctx, npg, orc, monkeypatch):
+def test_unet_direct_path_parity(ctx, npg, orc):
     """The direct-convolution fallback computes the same network."""
     model = synth.unet_model(5, random_bias=True)
     dirs, w, off = ragged_batch(9, [3000, 2000], 32, 32)
     rc, e, _ = orc.splat(dirs, w, off, 32, 32)
     rc, s_ref = orc.net_forward(model, orc.normalize_input(e))
-    monkeypatch.setenv("NPG_FORCE_DIRECT", "1")
-    m = npg.Model(ctx, model)
-    s = npg.reconstruct_density(ctx, m, t64(e), "fp32").cpu().numpy()
+    ctx.set_option("force_direct", 1)
+    try:
+        m = npg.Model(ctx, model)
+        s = npg.reconstruct_density(ctx, m, t64(e), "fp32").cpu().numpy()
+    finally:
+        ctx.set_option("force_direct", 0)
     assert np.max(_rel(s, s_ref)) < 1e-5
     m.free()
 
 
-def test_unet_chunking_invariant(ctx, npg, monkeypatch):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_unet_chunking_invariant(ctx, npg, prec):
     """Results do not depend on how leaves are chunked."""
     model = synth.unet_model(8)
     b = synth.uniform_batch(seed=12, L=10, per_leaf=1000, H=64, W=64, n_queries=8, model=model)
     e, _ = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), 64, 64)
     m = npg.Model(ctx, model)
-    s1 = npg.reconstruct_density(ctx, m, e, "fp32").cpu()
-    monkeypatch.setenv("NPG_CHUNK_LEAVES", "3")
-    s2 = npg.reconstruct_density(ctx, m, e, "fp32").cpu()
-    s3 = npg.reconstruct_density(ctx, m, e[4:7].contiguous(), "fp32").cpu()
+    s1 = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    ctx.set_option("chunk_leaves", 3)
+    try:
+        s2 = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    finally:
+        ctx.set_option("chunk_leaves", 0)
+    s3 = npg.reconstruct_density(ctx, m, e[4:7].contiguous(), prec).cpu()
     assert torch.equal(s1, s2) and torch.equal(s1[4:7], s3)
     m.free()
 

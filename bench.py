@@ -97,12 +97,139 @@ def cpu_baseline(workload: str, seconds_hint: float = 20.0):
                       f"{L * 1024} samples; {dt:.1f} s"}
 
 
+def run_serving(args):
+    """The serving stream: Poisson arrivals of reconstruction requests (1-4096
+    leaves, lognormal photons per leaf in [256, 1e6], 64x64 or 128x128) and
+    sampling batches (1e4-1e7 queries on resident leaves), interleaved 1:1.
+    The arrival rate is set so that FP32 processing one request at a time
+    would be ~70 % busy.  The same stream runs through the server twice: BF16
+    with continuous batching on 4 slots, and FP32 one request at a time."""
+    import torch
+
+    from paper_2010_01775_amd import npg, synth
+
+    dev = "cuda:0"
+    ctx = npg.Context(0)
+    model = npg.Model(ctx, synth.unet_model(1004))
+    pool = synth.uniform_batch(seed=1004, L=4096, per_leaf=4096, H=64, W=64, n_queries=1, model=b"")
+    n_pool = pool.dirs.shape[0]
+    dirs = torch.from_numpy(pool.dirs).to(dev)
+    w = torch.from_numpy(pool.w.view(np.int32)).to(dev)
+    qmax = 10_000_000
+    u = torch.from_numpy(np.stack([synth.uniforms(synth.rng_for(5), qmax), synth.uniforms(synth.rng_for(6), qmax)],
+                                  1)).to(dev)
+    outs = [(torch.empty((qmax, 3), device=dev), torch.empty(qmax, device=dev)) for _ in range(4)]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+
+    def windows(req, seed):
+        rng = np.random.default_rng(seed)
+        cnt = req.counts.astype(np.uint32)
+        beg = (rng.random(len(cnt)) * (n_pool - cnt)).astype(np.uint32)
+        return beg, cnt
+
+    def run(stream, prec, n_slots, max_batch, paced=True):
+        srv = npg.Server(ctx, model, n_slots=n_slots, max_batch_leaves=max_batch, table_bytes=48 << 30,
+                         slot_scratch_bytes=3 << 30, precision=prec)
+        resident, tickets, kinds, leaves, queries = [], [], [], 0, 0
+        gs = torch.cuda.Stream()
+        t0 = time.perf_counter()
+        for i, req in enumerate(stream):
+            if paced:
+                while time.perf_counter() - t0 < req.t_arrive:
+                    time.sleep(0.0002)
+            if req.kind == "recon":
+                beg, cnt = windows(req, req.seed)
+                t = srv.submit_recon(dirs, w, beg, cnt, req.H, req.W)
+                resident.append((t, req.n_leaves))
+                if len(resident) > 64:
+                    srv.release(resident.pop(0)[0])
+                tickets.append(t)
+                kinds.append(("recon", req.n_leaves))
+                leaves += req.n_leaves
+            else:
+                if not resident:
+                    continue
+                tr, L = resident[int(np.random.default_rng(req.seed).integers(0, len(resident)))]
+                n = min(req.n_queries, qmax)
+                with torch.cuda.stream(gs):
+                    leaf = torch.randint(0, L, (n,), device=dev, dtype=torch.int32, generator=gen)
+                gs.synchronize()
+                d, p = outs[i % 4]
+                tickets.append(srv.submit_sample(tr, leaf, u[:n], d, p))
+                kinds.append(("sample", n))
+                queries += n
+        lat = [srv.wait(t) for t in tickets]
+        t_end = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        lat_r = [l for l, k in zip(lat, kinds) if k[0] == "recon"]
+        lat_s = [l for l, k in zip(lat, kinds) if k[0] == "sample"]
+        span = t_end - t0
+        return {"leaves_per_s": leaves / span, "samples_per_s": queries / span, "seconds": span,
+                "p50_ms": float(np.percentile(lat, 50)) / 1e3, "p99_ms": float(np.percentile(lat, 99)) / 1e3,
+                "recon_p50_ms": float(np.percentile(lat_r, 50)) / 1e3,
+                "recon_p99_ms": float(np.percentile(lat_r, 99)) / 1e3,
+                "sample_p50_ms": float(np.percentile(lat_s, 50)) / 1e3 if lat_s else None,
+                "sample_p99_ms": float(np.percentile(lat_s, 99)) / 1e3 if lat_s else None,
+                "batches": st["batches"], "merged_requests": st["merged_requests"],
+                "max_concurrent": st["max_concurrent"], "requests": len(tickets)}
+
+    # service time of the FP32 one-at-a-time form, to set the arrival rate
+    cal = synth.serving_stream(seed=1104, n_requests=40, rate_hz=1e9)
+    srv = npg.Server(ctx, model, n_slots=1, max_batch_leaves=0, table_bytes=48 << 30,
+                     slot_scratch_bytes=3 << 30, precision="fp32")
+    busy, resident = 0.0, []
+    for req in cal:
+        t0 = time.perf_counter()
+        if req.kind == "recon":
+            beg, cnt = windows(req, req.seed)
+            t = srv.submit_recon(dirs, w, beg, cnt, req.H, req.W)
+            srv.wait(t)
+            resident.append((t, req.n_leaves))
+        else:
+            tr, L = resident[-1]
+            n = min(req.n_queries, qmax)
+            leaf = torch.randint(0, L, (n,), device=dev, dtype=torch.int32, generator=gen)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            srv.wait(srv.submit_sample(tr, leaf, u[:n], *outs[0]))
+        busy += time.perf_counter() - t0
+    srv.close()
+    mean_service = busy / len(cal)
+    rate = 0.7 / mean_service
+    stream = synth.serving_stream(seed=1004, n_requests=args.requests, rate_hz=rate)
+    print(f"serving: mean FP32 service {mean_service * 1e3:.2f} ms -> rate {rate:.1f} req/s", file=sys.stderr,
+          flush=True)
+    served = run(stream, "bf16", 4, 8192)
+    print(f"served bf16: {served}", file=sys.stderr, flush=True)
+    base = run(stream, "fp32", 1, 0)
+    print(f"fp32 unbatched: {base}", file=sys.stderr, flush=True)
+    res = {
+        "metric": "leaf densities reconstructed/sec + guided samples/sec; p50/p99 batch latency",
+        "value": served["leaves_per_s"], "unit": "leaves/s", "n_gpus": 1, "steps": args.requests,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 conv, f32 accumulation (served); baseline f32 storage, f64 accumulation",
+        "data": "synthetic (seeded vMF-mixture photon pool, lognormal leaf sizes, Poisson arrivals)",
+        "config": {"workload": f"serving stream: {args.requests} requests, Poisson {rate:.1f}/s "
+                               f"(FP32 one-at-a-time ~70% busy), recon 1-4096 leaves x 256-1e6 photons at 64^2/"
+                               f"128^2, sampling 1e4-1e7 queries, 1:1", "rate_hz": rate,
+                   "mean_fp32_service_ms": mean_service * 1e3},
+        "served_bf16": served, "fp32_unbatched": base,
+        "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"], "samples_per_s": served["samples_per_s"],
+    }
+    print(json.dumps(res))
+    model.free()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "clustered"])
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "clustered", "serving"])
+    ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -110,6 +237,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving":
+        return run_serving(args)
 
     import torch
 

@@ -55,7 +55,7 @@ typedef struct npg_model npg_model;
 /* Arithmetic of the network's convolutions.  Inputs, normalisation, the
  * per-leaf totals and the CDF prefixes are FP64/FP32 in every mode. */
 typedef enum {
-  NPG_FP32 = 0, /* FP32 activations and weights, FP64 accumulation          */
+  NPG_FP32 = 0, /* FP32 weights; FP64 activations and accumulation        */
   NPG_BF16 = 1, /* BF16 activations and weights, FP32 accumulation          */
   NPG_FP8 = 2   /* FP8 e4m3 (OCP) with static per-layer scales, FP32 accum.  */
 } npg_precision;
@@ -275,6 +275,74 @@ int npg_sample_dirs(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf
  * leaf >= L or a non-finite direction flags NPG_E_RANGE; pdf 0 there. */
 int npg_eval_pdf(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf_dev,
                  const float *dir_dev, uint64_t n, float *pdf_out_dev, void *stream);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A server takes reconstruction and sampling requests as a render loop emits
+ * them and runs them with continuous batching: a scheduler thread owns
+ * n_slots device streams; whenever one is free it launches the oldest
+ * waiting request, merged with every later waiting reconstruction of the
+ * same map size (up to max_batch_leaves leaves, as long as their tables fit
+ * in the table arena) into one batch whose kernels process the leaves of
+ * all its requests together.  Requests admitted while others run overlap on
+ * the device.  Reconstruction tables stay resident in the arena until the
+ * request is released.  A request's results do not depend on the batch it
+ * ran in.  All pointers stay owned by the caller and must stay valid until
+ * the request completes. */
+typedef struct npg_server npg_server;
+
+typedef struct {
+  uint32_t n_slots;            /* concurrent batches (streams), 1..16                      */
+  uint32_t max_batch_leaves;   /* leaves merged into one batch; 0 = one request per batch  */
+  uint64_t table_bytes;        /* device arena for resident tables (charged to ctx)        */
+  uint64_t slot_scratch_bytes; /* scratch budget of each slot (0 = unbounded)              */
+  npg_precision precision;     /* NPG_FP32 or NPG_BF16                                     */
+} npg_serve_params;
+
+typedef struct {
+  uint64_t submitted, completed, batches, leaves, merged_requests, max_concurrent, queued;
+  uint64_t table_bytes_free;
+} npg_serve_stats;
+
+/* Creates a server on ctx's device for `model` (which must outlive it). */
+int npg_serve_create(npg_ctx *ctx, const npg_model *model, const npg_serve_params *params, npg_server **out);
+
+/* Waits for work in flight, then frees everything the server holds. */
+void npg_serve_destroy(npg_server *server);
+
+/* Reconstruction request for L leaves of an H x W map.  Leaf l owns photons
+ * leaf_begin_host[l] .. + leaf_count_host[l] - 1 of dir_dev / w_dev (host
+ * arrays are copied).  Tables (pdf, marg, cond, total as in npg_build_cdf)
+ * are allocated in the arena at admission.  NPG_E_BUDGET if they can never
+ * fit in the arena.  *ticket identifies the request. */
+int npg_serve_submit_recon(npg_server *server, const float *dir_dev, const uint32_t *w_dev,
+                           const uint32_t *leaf_begin_host, const uint32_t *leaf_count_host, uint32_t L, int H,
+                           int W, uint64_t *ticket);
+
+/* Sampling request (as npg_sample_dirs, without bins) against the resident
+ * tables of a reconstruction ticket; it runs after that reconstruction. */
+int npg_serve_submit_sample(npg_server *server, uint64_t recon_ticket, const uint32_t *leaf_dev,
+                            const float *u_dev, uint64_t n, float *dir_out_dev, float *pdf_out_dev,
+                            uint64_t *ticket);
+
+/* 1 = done (latency from submit to completion in microseconds), 0 = pending,
+ * negative = failed or unknown ticket.  npg_serve_wait blocks until done. */
+int npg_serve_poll(npg_server *server, uint64_t ticket, double *latency_us);
+int npg_serve_wait(npg_server *server, uint64_t ticket, double *latency_us);
+
+/* Device tables of a completed reconstruction request. */
+int npg_serve_tables(npg_server *server, uint64_t recon_ticket, npg_tables *out);
+
+/* Copies the tables of a completed reconstruction request into caller
+ * buffers (layouts as in npg_build_cdf; total may be NULL), on `stream`. */
+int npg_serve_copy_tables(npg_server *server, uint64_t recon_ticket, float *pdf_dev, float *marg_dev,
+                          float *cond_dev, double *total_dev, void *stream);
+
+/* Forgets a request; a reconstruction's tables return to the arena once no
+ * launched sampling request reads them. */
+int npg_serve_release(npg_server *server, uint64_t ticket);
+
+void npg_serve_get_stats(npg_server *server, npg_serve_stats *out);
 
 /* The float32 boundary rays of a W-column map, (x, y) pairs for b = 0..W-1,
  * as the kernels use them (host memory out, 2*W floats). */

@@ -34,9 +34,29 @@ __device__ __forceinline__ double wave_excl_scan(double v, int lane) {
   return incl - v;
 }
 
-__global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restrict__ dens, int H, int W,
-                                                          float *__restrict__ pdf, float *__restrict__ marg,
-                                                          float *__restrict__ cond, double *__restrict__ total,
+// Output tables of leaf l: contiguous batch arrays, or per-leaf pointers.
+struct BatchOut {
+  float *pdf, *marg, *cond;
+  double *total;
+  __device__ void get(int l, int H, int W, float **p, float **m, float **c, double **t) const {
+    *p = pdf + (size_t)l * H * W;
+    *m = marg + (size_t)l * (H + 1);
+    *c = cond + (size_t)l * H * (W + 1);
+    *t = total ? total + l : nullptr;
+  }
+};
+struct DescOut {
+  const npg_leaf_desc *d;
+  __device__ void get(int l, int, int, float **p, float **m, float **c, double **t) const {
+    *p = d[l].pdf;
+    *m = d[l].marg;
+    *c = d[l].cond;
+    *t = d[l].total;
+  }
+};
+
+template <class OUT>
+__global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restrict__ dens, int H, int W, OUT out,
                                                           uint32_t *err) {
   extern __shared__ double rowmass[];  // [H]
   __shared__ double red[4];
@@ -60,16 +80,16 @@ __global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restric
   if (bad) atomicOr(&bad_s, 1);
   __syncthreads();
   const double S = red[0] + red[1] + red[2] + red[3];
-  float *pl = pdf + leaf * HW;
-  float *ml = marg + (size_t)leaf * (H + 1);
-  float *cl = cond + (size_t)leaf * H * (W + 1);
+  float *pl, *ml, *cl;
+  double *tl;
+  out.get(leaf, H, W, &pl, &ml, &cl, &tl);
   if (bad_s || !(S > 0.0) || !isfinite(S)) {
     const float qnan = __int_as_float(0x7fc00000);
-    for (size_t k = tid; k < HW; k += CDF_THREADS) pdf[leaf * HW + k] = qnan;
+    for (size_t k = tid; k < HW; k += CDF_THREADS) pl[k] = qnan;
     for (int k = tid; k <= H; k += CDF_THREADS) ml[k] = qnan;
     for (size_t k = tid; k < (size_t)H * (W + 1); k += CDF_THREADS) cl[k] = qnan;
     if (tid == 0) {
-      if (total) total[leaf] = 0.0;
+      if (tl) *tl = 0.0;
       raise_err(err, ERR_RANGE);
     }
     return;
@@ -130,7 +150,7 @@ __global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restric
     }
     if (lane == 0) {
       ml[H] = 1.0f;
-      if (total) total[leaf] = S;
+      if (tl) *tl = S;
     }
   }
 }
@@ -139,7 +159,14 @@ __global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restric
 
 hipError_t launch_build_cdf(const float *density, uint32_t L, int H, int W, float *pdf, float *marg,
                             float *cond, double *total, uint32_t *err, hipStream_t s) {
-  hipLaunchKernelGGL(cdf_kernel, dim3(L), dim3(CDF_THREADS), sizeof(double) * H, s, density, H, W, pdf,
-                     marg, cond, total, err);
+  hipLaunchKernelGGL(cdf_kernel<BatchOut>, dim3(L), dim3(CDF_THREADS), sizeof(double) * H, s, density, H, W,
+                     BatchOut{pdf, marg, cond, total}, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_cdf_desc(const float *density, const npg_leaf_desc *d, uint32_t L, int H, int W,
+                                 uint32_t *err, hipStream_t s) {
+  hipLaunchKernelGGL(cdf_kernel<DescOut>, dim3(L), dim3(CDF_THREADS), sizeof(double) * H, s, density, H, W,
+                     DescOut{d}, err);
   return hipGetLastError();
 }

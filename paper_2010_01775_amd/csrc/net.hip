@@ -3,12 +3,13 @@
 //
 // Activations are channel-last per leaf, [leaf][y][x][c].  3x3 convolutions
 // with at least 16 output channels run as implicit GEMMs on the matrix cores.
-// FP32 mode: float32 activations and weights, products and sums in binary64
-// (v_mfma_f64_16x16x4f64) -- a float32 accumulation chain over K = 9*Cin
-// terms and 15 layers loses ~3e-5 relative accuracy in the output pdf, the
-// binary64 chain keeps it at the float32 storage limit (~6e-6).  BF16 mode:
-// bf16 activations and weights, float32 accumulation
-// (v_mfma_f32_16x16x32_bf16).
+// FP32 mode: the float32 weights as loaded, binary64 activations, products
+// and sums (v_mfma_f64_16x16x4f64), softplus in binary64, float32 densities.
+// A float32 accumulation chain over K = 9*Cin terms and 15 layers loses ~3e-5
+// relative accuracy in the output pdf, and float32 activation storage alone
+// ~1e-5 on spiky leaves; with binary64 activations the only roundings left are
+// the float32 input map and output densities.  BF16 mode: bf16 activations
+// and weights, float32 accumulation (v_mfma_f32_16x16x32_bf16).
 //   M = output pixels of a tile, N = output channels, K = 9 taps x input
 //   channels.
 // A workgroup (4 wavefronts) owns a tile of 64*MW pixels (rows of one leaf)
@@ -242,13 +243,17 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 __device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+__device__ __forceinline__ double softplus_f(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
 
-template <class T> __device__ __forceinline__ float to_f(T v);
-template <> __device__ __forceinline__ float to_f<float>(float v) { return v; }
-template <> __device__ __forceinline__ float to_f<uint16_t>(uint16_t v) { return bf2f(v); }
-template <class T> __device__ __forceinline__ T from_f(float v);
-template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
-template <> __device__ __forceinline__ uint16_t from_f<uint16_t>(float v) { return f2bf(v); }
+// activation storage types: double (FP32 mode) and bf16 bits (BF16 mode)
+template <class T> __device__ __forceinline__ double to_d(T v);
+template <> __device__ __forceinline__ double to_d<double>(double v) { return v; }
+template <> __device__ __forceinline__ double to_d<float>(float v) { return v; }
+template <> __device__ __forceinline__ double to_d<uint16_t>(uint16_t v) { return bf2f(v); }
+template <class T> __device__ __forceinline__ T from_d(double v);
+template <> __device__ __forceinline__ double from_d<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_d<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ uint16_t from_d<uint16_t>(double v) { return f2bf((float)v); }
 
 // Source tensors of one convolution's (virtual) input.
 struct Src {
@@ -262,31 +267,31 @@ struct Src {
 
 // One input element (leaf, y, x, c) as float; (y, x) inside the map.
 template <class T>
-__device__ __forceinline__ float src_at(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+__device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, int c, int H, int W) {
   switch (s.mode) {
     case SRC_ENERGY: {
+      // the raw map is the float32 normalised energy (as npg_normalize_input)
       const double t = s.tot[leaf];
       const uint64_t e = static_cast<const uint64_t *>(s.s0)[((size_t)leaf * H + y) * W + x];
-      return t > 0.0 ? (float)((double)(H * W) * (double)e / t) : 0.0f;
+      return t > 0.0 ? (double)(float)((double)(H * W) * (double)e / t) : 0.0;
     }
     case SRC_POOL: {
       const T *p = static_cast<const T *>(s.s0);
       const int W2 = 2 * W;
       const size_t b = (((size_t)leaf * 2 * H + 2 * y) * W2 + 2 * x) * s.C0 + c;
-      return (float)(((double)to_f<T>(p[b]) + (double)to_f<T>(p[b + s.C0]) +
-                       (double)to_f<T>(p[b + (size_t)W2 * s.C0]) +
-                       (double)to_f<T>(p[b + (size_t)W2 * s.C0 + s.C0])) * 0.25);
+      return to_d<T>(from_d<T>((to_d<T>(p[b]) + to_d<T>(p[b + s.C0]) + to_d<T>(p[b + (size_t)W2 * s.C0]) +
+                                to_d<T>(p[b + (size_t)W2 * s.C0 + s.C0])) * 0.25));
     }
     case SRC_UPCAT:
       if (c < s.C0)
-        return to_f<T>(static_cast<const T *>(s.s0)[(((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c]);
-      return to_f<T>(static_cast<const T *>(s.s1)[(((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0)]);
+        return to_d<T>(static_cast<const T *>(s.s0)[(((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c]);
+      return to_d<T>(static_cast<const T *>(s.s1)[(((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0)]);
     default:
-      return to_f<T>(static_cast<const T *>(s.s0)[(((size_t)leaf * H + y) * W + x) * s.C0 + c]);
+      return to_d<T>(static_cast<const T *>(s.s0)[(((size_t)leaf * H + y) * W + x) * s.C0 + c]);
   }
 }
 
-// Direct convolution, one thread per output pixel, FP32 arithmetic.
+// Direct convolution, one thread per output pixel, binary64 sums.
 // out: T [L][H][W][Cout] (ACT_RELU) or float [L][H][W] (ACT_SOFTPLUS, Cout 1).
 template <class T>
 __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *__restrict__ w,
@@ -320,10 +325,10 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
         }
       }
     if (act == ACT_SOFTPLUS) {
-      static_cast<float *>(out)[pix] = softplus_f((float)acc[0]);
+      static_cast<float *>(out)[pix] = (float)softplus_f(acc[0]);
     } else {
       T *o = static_cast<T *>(out) + pix * Cout + co0;
-      for (int j = 0; j < nco; ++j) o[j] = from_f<T>((float)fmax(acc[j], 0.0));
+      for (int j = 0; j < nco; ++j) o[j] = from_d<T>(fmax(acc[j], 0.0));
     }
   }
 }
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
                                                          const float *__restrict__ w,
                                                          const float *__restrict__ bias, int C0, int H,
                                                          int W, int TW, int TR, void *out) {
-  __shared__ float xs[800];  // (TR+2) x (TW+2) <= 3 x 258 for TR*TW = 256
+  __shared__ Acc xs[800];  // (TR+2) x (TW+2) <= 3 x 258 for TR*TW = 256
   const int tiles_x = W / TW;
   const int tpl = (H / TR) * tiles_x;
   const int leaf = blockIdx.x / tpl;
@@ -352,14 +357,14 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
   for (int i = threadIdx.x; i < PH * PW; i += 256) {
     const int py = i / PW, px = i - py * PW;
     const int y = ty0 - 1 + py, x = tx0 - 1 + px;
-    float v = 0.0f;
+    float v = 0.0f;  // the float32 normalised energy (as npg_normalize_input)
     if (y >= 0 && y < H && x >= 0 && x < W && tl > 0.0) v = (float)(hw * (double)e[(size_t)y * W + x] / tl);
-    xs[i] = v;
+    xs[i] = (Acc)v;
   }
   __syncthreads();
   const int m = threadIdx.x;
   const int ty = m / TW, tx = m - ty * TW;
-  float xv[9];
+  Acc xv[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) xv[k] = xs[(ty + k / 3) * PW + tx + k % 3];
   T res[16];
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
       Acc a = (Acc)bias[c];
 #pragma unroll
       for (int k = 0; k < 9; ++k) a = fma((Acc)w[c * 9 + k], (Acc)xv[k], a);
-      res[c] = from_f<T>((float)(a > (Acc)0 ? a : (Acc)0));
+      res[c] = from_d<T>((double)(a > (Acc)0 ? a : (Acc)0));
     }
   }
   T *o = static_cast<T *>(out) + (((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) * C0;
@@ -387,22 +392,28 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
 // rows.  The f32 instructions give rows 4*(l/16) + r, r = 0..3; the f64
 // instruction gives rows 4*r + l/16.
 struct F32P {
-  using T = float;
+  using T = double;   // activations
+  using WT = float;   // weights
   using Acc = f64x4;
-  static constexpr int KC = KC32, VEC = 4, PSTR = KC + 4, MAX_TILES = 8;
+  static constexpr bool F64 = true;
+  static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, MAX_TILES = 8;
   static constexpr int SB = 1;  // matrix-bound: keep registers for occupancy
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
 };
 struct BF16P {
   using T = uint16_t;
+  using WT = uint16_t;
   using Acc = f32x4;
+  static constexpr bool F64 = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
   static constexpr int SB = 4;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
 };
 struct BF16S {
   using T = uint16_t;
+  using WT = uint16_t;
   using Acc = f32x4;
+  static constexpr bool F64 = false;
   static constexpr int KC = KC16S, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
   static constexpr int SB = 4;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
@@ -481,8 +492,7 @@ __device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, 
   T *tr = reinterpret_cast<T *>(&r);
 #pragma unroll
   for (int i = 0; i < VEC; ++i)
-    tr[i] = from_f<T>((float)(((double)to_f<T>(ta[i]) + (double)to_f<T>(tb[i]) + (double)to_f<T>(tc[i]) +
-                               (double)to_f<T>(td[i])) * 0.25));
+    tr[i] = from_d<T>((to_d<T>(ta[i]) + to_d<T>(tb[i]) + to_d<T>(tc[i]) + to_d<T>(td[i])) * 0.25);
   return r;
 }
 
@@ -499,7 +509,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   constexpr int KC = P::KC, VEC = P::VEC, PSTR = P::PSTR, G = KC / VEC;
   constexpr int SB = P::SB;  // global loads in flight per thread while staging
   constexpr int BN = 16 * NW;
-  constexpr bool IS_F32 = sizeof(T) == 4;
+  using WT = typename P::WT;
+  constexpr bool IS_F32 = P::F64;                // FP32 weights, FP64 activations and sums
   constexpr bool TWO_TAP = !IS_F32 && KC == 16;  // K slice = 2 taps x 16 channels
   constexpr int NTAPW = TWO_TAP ? 10 : 9;        // weight taps in LDS (10th = zeros)
   // FP32 B tile: [tap][kc][BNP], row stride chosen so the four k-rows a
@@ -511,7 +522,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   const int H = a.H, W = a.W;
   T *patch = reinterpret_cast<T *>(smem);
   const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), 16);
-  T *wl = reinterpret_cast<T *>(smem + patch_bytes);
+  WT *wl = reinterpret_cast<WT *>(smem + patch_bytes);
 
   const int tile = blockIdx.x;
   const int grp = tile / a.tiles_per_leaf;
@@ -579,7 +590,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     }
     // weights of this chunk
-    const T *wg = static_cast<const T *>(a.wpk) + (size_t)ch * 9 * KC * BN;
+    const WT *wg = static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN;
     if (IS_F32) {
       constexpr int R4 = BN / 4;  // float4 per row
       constexpr int WITEMS = 9 * KC * R4;
@@ -636,10 +647,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           double av[MW], bv[NW];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
-            av[mi] = (double)reinterpret_cast<const float *>(patch)[(bp[mi] + toff) * PSTR + ks * 4 + lg];
+            av[mi] = (double)patch[(bp[mi] + toff) * PSTR + ks * 4 + lg];
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni)
-            bv[ni] = (double)reinterpret_cast<const float *>(wl)[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
+            bv[ni] = (double)wl[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
@@ -705,7 +716,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       for (int r = 0; r < 4; ++r) {
         // the value the unfused path would store (type T) feeds the head
         const AS v0 = acc[mi][0][r] + bn;
-        const float act = to_f<T>(from_f<T>((float)(v0 > (AS)0 ? v0 : (AS)0)));
+        const double act = to_d<T>(from_d<T>((double)(v0 > (AS)0 ? v0 : (AS)0)));
         AS v = (AS)act * hw;
         v += __shfl_xor(v, 1);
         v += __shfl_xor(v, 2);
@@ -715,7 +726,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     if (lr < 4 * MW) {
       const int mi = lr >> 2, r = lr & 3;
-      dl[wave * 16 * MW + mi * 16 + P::row(lg, r)] = softplus_f((float)(mine + (AS)a.head_b));
+      dl[wave * 16 * MW + mi * 16 + P::row(lg, r)] = (float)softplus_f(mine + (AS)a.head_b);
     }
     __syncthreads();
     // four consecutive tile pixels are contiguous in the output (TW >= 4)
@@ -737,7 +748,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
         const AS v = acc[mi][ni][r] + bn;
-        ol[m * BN + n] = from_f<T>((float)(v > (AS)0 ? v : (AS)0));
+        ol[m * BN + n] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));
       }
   }
   __syncthreads();
@@ -763,8 +774,9 @@ size_t conv_lds_bytes(const Tiling &t) {
   const int BN = 16 * t.NW;
   const size_t patch = npg_align((size_t)t.TL * (t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
   size_t wts;
-  if (sizeof(T) == 4) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(T);
-  else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * (P::KC + 8) * sizeof(T);
+  using WT = typename P::WT;
+  if (P::F64) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
+  else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * (P::KC + 8) * sizeof(WT);
   const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
   return std::max(patch + wts, epi);
 }
@@ -921,7 +933,7 @@ struct Runner {
       if (TR <= H) {
         const unsigned blocks = (unsigned)Lc * (H / TR) * (W / TW);
         if (prec == NPG_FP32)
-          hipLaunchKernelGGL((conv_first_kernel<float, double>), dim3(blocks), dim3(256), 0, s,
+          hipLaunchKernelGGL((conv_first_kernel<double, double>), dim3(blocks), dim3(256), 0, s,
                              static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, out);
         else
           hipLaunchKernelGGL((conv_first_kernel<uint16_t, float>), dim3(blocks), dim3(256), 0, s,
@@ -941,7 +953,7 @@ struct Runner {
     }
     const unsigned blocks = (unsigned)((npix + 255) / 256);
     if (prec == NPG_FP32)
-      hipLaunchKernelGGL(conv_direct_kernel<float>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
+      hipLaunchKernelGGL(conv_direct_kernel<double>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
                          y.cout, y.k, H, W, npix, act, dst);
     else
       hipLaunchKernelGGL(conv_direct_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b,
@@ -1105,7 +1117,7 @@ std::string tune_key(const npg_model *m, npg_precision p, int H, int W) {
 }
 
 Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStream_t s) {
-  Runner R{ctx, m, prec, s, prec == NPG_FP32 ? (size_t)4 : (size_t)2};
+  Runner R{ctx, m, prec, s, prec == NPG_FP32 ? sizeof(double) : (size_t)2};
   R.force_direct = (int)ctx->opt("force_direct", 0);
   return R;
 }
@@ -1270,6 +1282,52 @@ extern "C" int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *m, const flo
   }
   ctx->graphs.push_back({key, exec});
   NPG_HIP_CHECK(ctx, hipGraphLaunch(exec, s));
+  return NPG_OK;
+}
+
+bool npg_model_fits(const npg_model *m, int H, int W) {
+  if (m->arch != 2) return true;
+  const int f = 1 << (m->levels - 1);
+  return H % f == 0 && W % f == 0;
+}
+
+// One serving batch: leaves described by per-leaf descriptors (photon
+// windows of several requests, output table pointers), chunked like the
+// fused path.
+int npg_run_desc_batch(npg_ctx *ctx, const npg_model *m, npg_precision prec, const npg_leaf_desc *d_dev,
+                       uint32_t L, int H, int W, hipStream_t s) {
+  int rc = check_net_args(ctx, m, H, W, prec);
+  if (rc) return rc;
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  Runner R = make_runner(ctx, m, prec, s);
+  std::vector<int> caps;
+  apply_tune(ctx, R, H, W, &caps);
+  const size_t HW = (size_t)H * W;
+  const NetPlan plan = plan_net(m, H, W, R.esz);
+  const size_t per_leaf = plan.per_leaf + HW * (sizeof(uint64_t) + sizeof(float)) + sizeof(double) + 3 * 256;
+  size_t chunk = 0;
+  rc = chunk_for(ctx, m, prec, H, W, L, per_leaf, 16u << 20, &chunk);
+  if (rc) return rc;
+  const size_t bytes = npg_align(chunk * HW * sizeof(uint64_t)) + npg_align(chunk * HW * sizeof(float)) +
+                       npg_align(chunk * sizeof(double)) + net_bufs_bytes(plan, chunk, R.esz);
+  void *scr = nullptr;
+  rc = npg_scratch(ctx, bytes, s, &scr);
+  if (rc) return rc;
+  Carver cv(scr);
+  uint64_t *energy = cv.take<uint64_t>(chunk * HW);
+  float *dens = cv.take<float>(chunk * HW);
+  double *tot = cv.take<double>(chunk);
+  const NetBufs B = carve_net(cv, plan, chunk, R.esz);
+  for (size_t l0 = 0; l0 < L; l0 += chunk) {
+    const uint32_t Lc = (uint32_t)std::min<size_t>(chunk, L - l0);
+    NPG_HIP_CHECK(ctx, launch_splat_desc(ctx->bnd_dev, d_dev + l0, Lc, H, W, energy, ctx->err_dev, s));
+    NPG_HIP_CHECK(ctx, launch_leaf_scale(energy, Lc, (int)HW, tot, s));
+    const Src in{SRC_ENERGY, energy, nullptr, tot, 0, 0};
+    rc = net_chunk(R, in, (int)Lc, H, W, dens, B);
+    if (rc) return rc;
+    NPG_HIP_CHECK(ctx, launch_build_cdf_desc(dens, d_dev + l0, Lc, H, W, ctx->err_dev, s));
+  }
   return NPG_OK;
 }
 

@@ -170,11 +170,27 @@ __device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
   atomicOr(err, bit);
 }
 
+// Per-leaf descriptor of a serving batch: the leaf's photons (a window of a
+// request's arrays) and where its tables go.
+struct npg_leaf_desc {
+  const float *dir;
+  const uint32_t *w;
+  uint32_t begin, count;
+  float *pdf, *marg, *cond;
+  double *total;
+};
+
 // ---------------------------------------------------------------- launchers
 // Each returns a hipError_t from the launch.
 hipError_t launch_splat(const float2 *bnd, const float *dir, const uint32_t *w, const uint32_t *perm,
                         const uint32_t *off, uint32_t L, int H, int W, uint64_t *energy,
                         uint32_t *count, int accumulate, uint32_t *err, hipStream_t s);
+// true if the network's pooling levels divide an H x W map
+bool npg_model_fits(const npg_model *m, int H, int W);
+hipError_t launch_splat_desc(const float2 *bnd, const npg_leaf_desc *d, uint32_t L, int H, int W,
+                             uint64_t *energy, uint32_t *err, hipStream_t s);
+hipError_t launch_build_cdf_desc(const float *density, const npg_leaf_desc *d, uint32_t L, int H, int W,
+                                 uint32_t *err, hipStream_t s);
 hipError_t launch_leaf_scale(const uint64_t *energy, uint32_t L, int HW, double *scale,
                              hipStream_t s);
 hipError_t launch_apply_scale(const uint64_t *energy, const double *scale, uint32_t L, int HW,

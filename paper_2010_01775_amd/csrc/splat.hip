@@ -18,10 +18,37 @@ constexpr uint32_t SPLAT_ROUND = 1u << 15;     // photons per drain round
 constexpr int PACK_SHIFT = 47;
 constexpr unsigned long long PACK_MASK = (1ull << PACK_SHIFT) - 1;
 
-template <int BPT>
+// Where a workgroup finds its leaf's photons: a CSR batch (one direction and
+// weight array, offsets, optional permutation) or per-leaf descriptors
+// (serving batches mix leaves of several requests).
+struct CsrLeaves {
+  const float *dir;
+  const uint32_t *w;
+  const uint32_t *perm;
+  const uint32_t *off;
+  __device__ void range(int leaf, uint32_t *b, uint32_t *e) const {
+    *b = off[leaf];
+    *e = off[leaf + 1];
+  }
+  __device__ uint32_t idx(int, uint32_t i) const { return perm ? perm[i] : i; }
+  __device__ const float *dirs(int) const { return dir; }
+  __device__ const uint32_t *ws(int) const { return w; }
+};
+
+struct DescLeaves {
+  const npg_leaf_desc *d;
+  __device__ void range(int leaf, uint32_t *b, uint32_t *e) const {
+    *b = d[leaf].begin;
+    *e = d[leaf].begin + d[leaf].count;
+  }
+  __device__ uint32_t idx(int, uint32_t i) const { return i; }
+  __device__ const float *dirs(int leaf) const { return d[leaf].dir; }
+  __device__ const uint32_t *ws(int leaf) const { return d[leaf].w; }
+};
+
+template <int BPT, class LS>
 __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
-    const float2 *__restrict__ bnd, const float *__restrict__ dir, const uint32_t *__restrict__ w, const uint32_t *__restrict__ perm,
-    const uint32_t *__restrict__ off, int H, int W, int band_rows, uint64_t *__restrict__ energy,
+    const float2 *__restrict__ bnd, LS src, int H, int W, int band_rows, uint64_t *__restrict__ energy,
     uint32_t *__restrict__ count, int accumulate, uint32_t *err) {
   extern __shared__ unsigned long long acc[];
   __shared__ float2 q4[256];
@@ -38,13 +65,16 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
     e[j] = 0ull;
     c[j] = 0u;
   }
-  const uint32_t beg = off[leaf], end = off[leaf + 1];
+  uint32_t beg, end;
+  src.range(leaf, &beg, &end);
+  const float *dir = src.dirs(leaf);
+  const uint32_t *w = src.ws(leaf);
   bool bad = false;
   __syncthreads();
   for (uint64_t r0 = beg; r0 < end; r0 += SPLAT_ROUND) {
     const uint32_t r1 = (uint32_t)min((uint64_t)end, r0 + SPLAT_ROUND);
     for (uint32_t i = (uint32_t)r0 + tid; i < r1; i += SPLAT_THREADS) {
-      const uint32_t p = perm ? perm[i] : i;
+      const uint32_t p = src.idx(leaf, i);
       const float x = dir[3 * (size_t)p], y = dir[3 * (size_t)p + 1], z = dir[3 * (size_t)p + 2];
       if (!finite3(x, y, z)) {
         bad = true;
@@ -85,24 +115,38 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
   }
 }
 
-template <int BPT>
-hipError_t launch_splat_t(const float2 *bnd, const float *dir, const uint32_t *w, const uint32_t *perm,
-                          const uint32_t *off, uint32_t L, int H, int W, int band_rows,
-                          uint64_t *energy, uint32_t *count, int accumulate, uint32_t *err,
-                          hipStream_t s) {
+template <int BPT, class LS>
+hipError_t launch_splat_t(const float2 *bnd, const LS &src, uint32_t L, int H, int W, int band_rows,
+                          uint64_t *energy, uint32_t *count, int accumulate, uint32_t *err, hipStream_t s) {
   const size_t lds = sizeof(unsigned long long) * (size_t)band_rows * W;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)splat_kernel<BPT>,
+    hipError_t e = hipFuncSetAttribute((const void *)splat_kernel<BPT, LS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        SPLAT_MAX_BINS * sizeof(unsigned long long));
     if (e != hipSuccess) return e;
     attr = true;
   }
   dim3 grid(L, H / band_rows);
-  hipLaunchKernelGGL(splat_kernel<BPT>, grid, dim3(SPLAT_THREADS), lds, s, bnd, dir, w, perm, off, H, W,
-                     band_rows, energy, count, accumulate, err);
+  hipLaunchKernelGGL((splat_kernel<BPT, LS>), grid, dim3(SPLAT_THREADS), lds, s, bnd, src, H, W, band_rows,
+                     energy, count, accumulate, err);
   return hipGetLastError();
+}
+
+template <class LS>
+hipError_t launch_splat_any(const float2 *bnd, const LS &src, uint32_t L, int H, int W, uint64_t *energy,
+                            uint32_t *count, int accumulate, uint32_t *err, hipStream_t s) {
+  int band_rows = H;
+  while (band_rows * W > SPLAT_MAX_BINS) band_rows >>= 1;
+  const int nb = band_rows * W;
+  const int bpt = (nb + SPLAT_THREADS - 1) / SPLAT_THREADS;
+  switch (bpt) {
+    case 1: return launch_splat_t<1>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+    case 2: return launch_splat_t<2>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+    case 4: return launch_splat_t<4>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+    case 8: return launch_splat_t<8>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+    default: return launch_splat_t<16>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+  }
 }
 
 // Per-leaf energy total (exact u64 sum), stored as binary64.
@@ -135,17 +179,12 @@ __global__ void apply_scale_kernel(const uint64_t *__restrict__ energy, const do
 hipError_t launch_splat(const float2 *bnd, const float *dir, const uint32_t *w, const uint32_t *perm,
                         const uint32_t *off, uint32_t L, int H, int W, uint64_t *energy,
                         uint32_t *count, int accumulate, uint32_t *err, hipStream_t s) {
-  int band_rows = H;
-  while (band_rows * W > SPLAT_MAX_BINS) band_rows >>= 1;
-  const int nb = band_rows * W;
-  const int bpt = (nb + SPLAT_THREADS - 1) / SPLAT_THREADS;
-  switch (bpt) {
-    case 1: return launch_splat_t<1>(bnd, dir, w, perm, off, L, H, W, band_rows, energy, count, accumulate, err, s);
-    case 2: return launch_splat_t<2>(bnd, dir, w, perm, off, L, H, W, band_rows, energy, count, accumulate, err, s);
-    case 4: return launch_splat_t<4>(bnd, dir, w, perm, off, L, H, W, band_rows, energy, count, accumulate, err, s);
-    case 8: return launch_splat_t<8>(bnd, dir, w, perm, off, L, H, W, band_rows, energy, count, accumulate, err, s);
-    default: return launch_splat_t<16>(bnd, dir, w, perm, off, L, H, W, band_rows, energy, count, accumulate, err, s);
-  }
+  return launch_splat_any(bnd, CsrLeaves{dir, w, perm, off}, L, H, W, energy, count, accumulate, err, s);
+}
+
+hipError_t launch_splat_desc(const float2 *bnd, const npg_leaf_desc *d, uint32_t L, int H, int W,
+                             uint64_t *energy, uint32_t *err, hipStream_t s) {
+  return launch_splat_any(bnd, DescLeaves{d}, L, H, W, energy, nullptr, 0, err, s);
 }
 
 hipError_t launch_leaf_scale(const uint64_t *energy, uint32_t L, int HW, double *tot, hipStream_t s) {

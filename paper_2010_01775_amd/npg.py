@@ -26,6 +26,9 @@ SYMBOLS = [
     "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
     "npg_reconstruct_density", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
+    "npg_serve_create", "npg_serve_destroy", "npg_serve_submit_recon", "npg_serve_submit_sample",
+    "npg_serve_poll", "npg_serve_wait", "npg_serve_tables", "npg_serve_copy_tables", "npg_serve_release",
+    "npg_serve_get_stats",
 ]
 
 
@@ -42,6 +45,16 @@ class Tables(C.Structure):
 
 class HierParams(C.Structure):
     _fields_ = [("split_count", C.c_uint32), ("max_depth", C.c_int32)]
+
+
+class ServeParams(C.Structure):
+    _fields_ = [("n_slots", C.c_uint32), ("max_batch_leaves", C.c_uint32), ("table_bytes", C.c_uint64),
+                ("slot_scratch_bytes", C.c_uint64), ("precision", C.c_int)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "batches", "leaves", "merged_requests",
+                                          "max_concurrent", "queued", "table_bytes_free")]
 
 
 _lib = None
@@ -78,6 +91,16 @@ def load_library(path: str = LIB_PATH):
         "npg_reconstruct_fused": (I, [P, P, P, P, P, P, U32, I, I, I, P, P, P, P, P]),
         "npg_autotune": (I, [P, P, I, I, I, U32, P]),
         "npg_tune_table": (I, [P, P, I, I, I, P, I]),
+        "npg_serve_create": (I, [P, P, C.POINTER(ServeParams), C.POINTER(P)]),
+        "npg_serve_destroy": (None, [P]),
+        "npg_serve_submit_recon": (I, [P, P, P, P, P, U32, I, I, C.POINTER(U64)]),
+        "npg_serve_submit_sample": (I, [P, U64, P, P, U64, P, P, C.POINTER(U64)]),
+        "npg_serve_poll": (I, [P, U64, C.POINTER(C.c_double)]),
+        "npg_serve_wait": (I, [P, U64, C.POINTER(C.c_double)]),
+        "npg_serve_tables": (I, [P, U64, C.POINTER(Tables)]),
+        "npg_serve_copy_tables": (I, [P, U64, P, P, P, P, P]),
+        "npg_serve_release": (I, [P, U64]),
+        "npg_serve_get_stats": (None, [P, C.POINTER(ServeStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -326,3 +349,69 @@ def bin_boundaries(W: int):
     if rc:
         raise NpgError(rc, "bad W")
     return out.reshape(W, 2)
+
+
+class Server:
+    """Continuous-batching server over one context's device (see npg.h)."""
+
+    def __init__(self, ctx: Context, model: Model, n_slots: int = 4, max_batch_leaves: int = 8192,
+                 table_bytes: int = 8 << 30, slot_scratch_bytes: int = 2 << 30, precision="bf16"):
+        import numpy as np  # noqa: F401
+        self.ctx, self.model = ctx, model
+        p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        prm = ServeParams(n_slots, max_batch_leaves, table_bytes, slot_scratch_bytes, p)
+        h = C.c_void_p()
+        ctx.check(ctx.lib.npg_serve_create(ctx.h, model.h, C.byref(prm), C.byref(h)))
+        self.h = h
+        self.lib = ctx.lib
+
+    def submit_recon(self, dirs, w, begin, count, H: int, W: int) -> int:
+        import numpy as np
+        b = np.ascontiguousarray(begin, dtype=np.uint32)
+        c = np.ascontiguousarray(count, dtype=np.uint32)
+        t = C.c_uint64()
+        self.ctx.check(self.lib.npg_serve_submit_recon(self.h, _ptr(dirs), _ptr(w), b.ctypes.data, c.ctypes.data,
+                                                        len(b), H, W, C.byref(t)))
+        return t.value
+
+    def submit_sample(self, recon: int, leaf, u, dir_out, pdf_out) -> int:
+        t = C.c_uint64()
+        self.ctx.check(self.lib.npg_serve_submit_sample(self.h, recon, _ptr(leaf), _ptr(u), leaf.shape[0],
+                                                         _ptr(dir_out), _ptr(pdf_out), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        lat = C.c_double()
+        rc = self.lib.npg_serve_poll(self.h, ticket, C.byref(lat))
+        if rc < 0:
+            raise NpgError(rc, "request failed")
+        return (lat.value if rc == 1 else None)
+
+    def wait(self, ticket: int) -> float:
+        lat = C.c_double()
+        rc = self.lib.npg_serve_wait(self.h, ticket, C.byref(lat))
+        if rc < 0:
+            raise NpgError(rc, "request failed")
+        return lat.value
+
+    def copy_tables(self, ticket: int, out: CdfTables, stream=None):
+        rc = self.lib.npg_serve_copy_tables(self.h, ticket, _ptr(out.pdf), _ptr(out.marg), _ptr(out.cond),
+                                            _ptr(out.total), _stream(stream))
+        if rc:
+            raise NpgError(rc, "copy_tables failed")
+        return out
+
+    def release(self, ticket: int):
+        rc = self.lib.npg_serve_release(self.h, ticket)
+        if rc:
+            raise NpgError(rc, "release failed")
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        self.lib.npg_serve_get_stats(self.h, C.byref(st))
+        return {n: getattr(st, n) for n, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.npg_serve_destroy(self.h)
+            self.h = None

@@ -77,6 +77,24 @@ def sha_of(*paths):
     return h.hexdigest()[:16]
 
 
+def pdf_errors_vs_fp32(npg, ctx, model, energy, precision):
+    """Per-leaf L1 and KL of the low-precision pdf against the FP32 path's
+    (which matches the FP64 oracle within 1e-5 relative), over every leaf."""
+    import torch
+    lo = npg.reconstruct_density(ctx, model, energy, precision).double()
+    hi = npg.reconstruct_density(ctx, model, energy, "fp32").double()
+    L = lo.shape[0]
+    p = lo.reshape(L, -1)
+    q = hi.reshape(L, -1)
+    p = p / p.sum(1, keepdim=True)
+    q = q / q.sum(1, keepdim=True)
+    l1 = (p - q).abs().sum(1)
+    kl = torch.where(q > 0, q * torch.log(q / p.clamp_min(1e-300)), torch.zeros_like(q)).sum(1)
+    qs = lambda t, f: float(torch.quantile(t.float(), f)) if t.numel() > 1 else float(t[0])
+    return {"leaves": L, "l1_median": qs(l1, 0.5), "l1_p99": qs(l1, 0.99), "l1_max": float(l1.max()),
+            "kl_median": qs(kl, 0.5), "kl_p99": qs(kl, 0.99), "kl_max": float(kl.max())}
+
+
 def cpu_baseline(workload: str, seconds_hint: float = 20.0):
     """The FP64 oracle, as it stands, on a bounded sample of the workload."""
     from oracle import oracle as orc
@@ -132,6 +150,7 @@ def run_serving(args):
         srv = npg.Server(ctx, model, n_slots=n_slots, max_batch_leaves=max_batch, table_bytes=48 << 30,
                          slot_scratch_bytes=3 << 30, precision=prec)
         resident, tickets, kinds, leaves, queries = [], [], [], 0, 0
+        lat_of = {}  # latency of released reconstructions (their tickets are gone after release)
         gs = torch.cuda.Stream()
         t0 = time.perf_counter()
         for i, req in enumerate(stream):
@@ -143,7 +162,9 @@ def run_serving(args):
                 t = srv.submit_recon(dirs, w, beg, cnt, req.H, req.W)
                 resident.append((t, req.n_leaves))
                 if len(resident) > 64:
-                    srv.release(resident.pop(0)[0])
+                    old = resident.pop(0)[0]
+                    lat_of[old] = srv.wait(old)
+                    srv.release(old)
                 tickets.append(t)
                 kinds.append(("recon", req.n_leaves))
                 leaves += req.n_leaves
@@ -159,7 +180,7 @@ def run_serving(args):
                 tickets.append(srv.submit_sample(tr, leaf, u[:n], d, p))
                 kinds.append(("sample", n))
                 queries += n
-        lat = [srv.wait(t) for t in tickets]
+        lat = [lat_of[t] if t in lat_of else srv.wait(t) for t in tickets]
         t_end = time.perf_counter()
         st = srv.stats()
         srv.close()
@@ -175,28 +196,12 @@ def run_serving(args):
                 "batches": st["batches"], "merged_requests": st["merged_requests"],
                 "max_concurrent": st["max_concurrent"], "requests": len(tickets)}
 
-    # service time of the FP32 one-at-a-time form, to set the arrival rate
-    cal = synth.serving_stream(seed=1104, n_requests=40, rate_hz=1e9)
-    srv = npg.Server(ctx, model, n_slots=1, max_batch_leaves=0, table_bytes=48 << 30,
-                     slot_scratch_bytes=3 << 30, precision="fp32")
-    busy, resident = 0.0, []
-    for req in cal:
-        t0 = time.perf_counter()
-        if req.kind == "recon":
-            beg, cnt = windows(req, req.seed)
-            t = srv.submit_recon(dirs, w, beg, cnt, req.H, req.W)
-            srv.wait(t)
-            resident.append((t, req.n_leaves))
-        else:
-            tr, L = resident[-1]
-            n = min(req.n_queries, qmax)
-            leaf = torch.randint(0, L, (n,), device=dev, dtype=torch.int32, generator=gen)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            srv.wait(srv.submit_sample(tr, leaf, u[:n], *outs[0]))
-        busy += time.perf_counter() - t0
-    srv.close()
-    mean_service = busy / len(cal)
+    # service time of the FP32 one-at-a-time form, to set the arrival rate:
+    # the whole stream back to back (arrival times scale with 1/rate, the
+    # requests themselves do not depend on it)
+    unpaced = run(synth.serving_stream(seed=1004, n_requests=args.requests, rate_hz=1e9), "fp32", 1, 0,
+                  paced=False)
+    mean_service = unpaced["seconds"] / unpaced["requests"]
     rate = 0.7 / mean_service
     stream = synth.serving_stream(seed=1004, n_requests=args.requests, rate_hz=rate)
     print(f"serving: mean FP32 service {mean_service * 1e3:.2f} ms -> rate {rate:.1f} req/s", file=sys.stderr,
@@ -209,7 +214,7 @@ def run_serving(args):
         "metric": "leaf densities reconstructed/sec + guided samples/sec; p50/p99 batch latency",
         "value": served["leaves_per_s"], "unit": "leaves/s", "n_gpus": 1, "steps": args.requests,
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 conv, f32 accumulation (served); baseline f32 storage, f64 accumulation",
+        "dtype": "bf16 conv, f32 accumulation (served); baseline f32 weights, f64 activations and accumulation",
         "data": "synthetic (seeded vMF-mixture photon pool, lognormal leaf sizes, Poisson arrivals)",
         "config": {"workload": f"serving stream: {args.requests} requests, Poisson {rate:.1f}/s "
                                f"(FP32 one-at-a-time ~70% busy), recon 1-4096 leaves x 256-1e6 photons at 64^2/"
@@ -229,8 +234,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform", choices=["uniform", "clustered", "serving"])
-    ap.add_argument("--requests", type=int, default=2000)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -332,6 +337,15 @@ def main():
         npg.eval_pdf(ctx, tabs, q_leaf, sd[0], out=pe)
         mark("eval", 1)
 
+    if args.precision == "fp8":
+        # static e4m3 scales from a strided 1/16 subsample of the workload's own
+        # maps (at most 256 leaves), computed once before timing
+        if pos is not None:
+            lo_ = out["leaf_off"][:L + 1]
+            npg.splat_histograms(ctx, dirs, w, lo_, H, W, perm=out["perm"], energy=energy, count=count)
+        else:
+            npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
+        model.calibrate_fp8(energy[::16][:256].contiguous())
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -362,7 +376,9 @@ def main():
     recon_s = avg["recon"] / 1e3
     flops = flops_leaf * L
     if args.precision == "fp32":
-        peak, peak_name = PEAK["fp64_mfma_TFLOPs"], "FP64 MFMA (FP32 storage, FP64 accumulation)"
+        peak, peak_name = PEAK["fp64_mfma_TFLOPs"], "FP64 MFMA (FP32 weights, FP64 activations and accumulation)"
+    elif args.precision == "fp8":
+        peak, peak_name = PEAK["fp8_mfma_TFLOPs"], "FP8 MFMA (e4m3, FP32 accumulation)"
     else:
         peak, peak_name = PEAK["bf16_mfma_TFLOPs"], "BF16 MFMA"
     achieved = flops / recon_s / 1e12
@@ -385,10 +401,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 storage, f64 conv accumulation" if args.precision == "fp32" else "bf16 conv, f32 accumulation",
+        "dtype": {"fp32": "f64", "bf16": "bf16", "fp8": "fp8-e4m3"}[args.precision],
         "data": "synthetic (seeded vMF-mixture photons, He-init weights)",
         "config": {"workload": desc, "leaves": L, "H": H, "W": W, "queries": nq,
-                   "precision": args.precision},
+                   "precision": {"fp32": "fp32 weights, f64 activations and conv accumulation",
+                                 "bf16": "bf16 conv, f32 accumulation",
+                                 "fp8": "fp8 e4m3 conv (static per-layer activation scales, "
+                                        "per-output-channel weight scales), f32 accumulation"}[args.precision]},
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
         "p50_ms": float(np.percentile(per_step, 50)),
@@ -399,6 +418,8 @@ def main():
                      "kernel": f"reconstruct_density (implicit-GEMM conv stack), {peak_name}",
                      "flops_per_launch": flops, "avg_launch_ms": avg["recon"], "source_sha": src_sha},
     }
+    if args.precision != "fp32":
+        res["precision_vs_fp32"] = pdf_errors_vs_fp32(npg, ctx, model, energy, args.precision)
     if not args.no_cpu_baseline and args.workload == "uniform":
         res["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(res))

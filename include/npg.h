@@ -131,11 +131,18 @@ int npg_set_option(npg_ctx *ctx, const char *name, int64_t value);
 int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_bytes, npg_model **out);
 void npg_model_free(npg_model *model);
 
-/* Sets the static FP8 scales of a model from a calibration batch: per-layer
- * weight scales from the weight amax, activation scales from the amax of
- * every layer input over the given energy maps (run in FP32).  Synchronises
- * `stream`.  Scales stay fixed afterwards, so a leaf's FP8 result does not
- * depend on the other leaves of a batch. */
+/* Sets the static FP8 (OCP e4m3) scales of a model from a calibration batch
+ * of L energy maps [L][H][W] (device): the network runs once in NPG_FP32 and
+ * records the largest stored output of every ReLU layer; that layer's
+ * activations are then stored as e4m3 in units of amax/448.  Each 3x3
+ * weight tensor fed by stored activations gets its input channels' units
+ * folded in and one scale per output channel (amax/448 of the folded
+ * weights); the first layer and the 1x1 head keep float32 weights.  Values
+ * above the calibrated range saturate at +-448 units.  Synchronises
+ * `stream`; may be called again to recalibrate.  Scales stay fixed between
+ * calibrations, so a leaf's FP8 result does not depend on the other leaves
+ * of a batch.  NPG_E_ARG for an empty batch or a map size the model does
+ * not fit. */
 int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *model, const uint64_t *energy_dev,
                             uint32_t L, int H, int W, void *stream);
 
@@ -296,7 +303,7 @@ typedef struct {
   uint32_t max_batch_leaves;   /* leaves merged into one batch; 0 = one request per batch  */
   uint64_t table_bytes;        /* device arena for resident tables (charged to ctx)        */
   uint64_t slot_scratch_bytes; /* scratch budget of each slot (0 = unbounded)              */
-  npg_precision precision;     /* NPG_FP32 or NPG_BF16                                     */
+  npg_precision precision;     /* network precision (FP8: model calibrated beforehand)     */
 } npg_serve_params;
 
 typedef struct {
@@ -338,9 +345,16 @@ int npg_serve_tables(npg_server *server, uint64_t recon_ticket, npg_tables *out)
 int npg_serve_copy_tables(npg_server *server, uint64_t recon_ticket, float *pdf_dev, float *marg_dev,
                           float *cond_dev, double *total_dev, void *stream);
 
-/* Forgets a request; a reconstruction's tables return to the arena once no
- * launched sampling request reads them. */
+/* Forgets a request: its ticket is unknown afterwards (poll and wait return
+ * NPG_E_ARG), so read its latency first.  A reconstruction's tables return
+ * to the arena once it has finished and no sampling request submitted
+ * against it is still unfinished. */
 int npg_serve_release(npg_server *server, uint64_t ticket);
+
+/* Message of the server's most recent failure (a failed request, an unknown
+ * ticket); "" if none.  The pointer stays valid until the calling thread's
+ * next call of this function. */
+const char *npg_serve_last_error(npg_server *server);
 
 void npg_serve_get_stats(npg_server *server, npg_serve_stats *out);
 

@@ -27,6 +27,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -35,6 +37,7 @@
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef long fp8x8;  // eight e4m3 bytes
 
 // ------------------------------------------------------------------ model
 struct LayerDev {
@@ -44,6 +47,12 @@ struct LayerDev {
   float *pk32 = nullptr;       // [chunk][tap][kc16][cout]
   uint16_t *pk16 = nullptr;    // [chunk][tap][cout][kc32] (bf16 bits)
   uint16_t *pk16s = nullptr;   // [chunk][tap][cout][kc16] (bf16 bits)
+  // FP8 (after calibration): e4m3 weights with the input channels' activation
+  // scales folded in, and one dequantisation scale per output channel
+  uint8_t *pk8 = nullptr;      // [chunk][tap][cout][kc32]
+  uint8_t *pk8s = nullptr;     // [chunk][tap][cout][kc16]
+  float *wsc8 = nullptr;       // [cout]
+  float a8 = 1.0f;             // value of one e4m3 unit of this layer's output
 };
 
 struct npg_model {
@@ -53,6 +62,8 @@ struct npg_model {
   std::vector<std::vector<float>> host_w, host_b;
   void *blob = nullptr;  // one device allocation holding every array
   size_t blob_bytes = 0;
+  void *blob8 = nullptr;  // FP8 weights and scales (calibration)
+  size_t blob8_bytes = 0;
   bool fp8_ready = false;
 };
 
@@ -74,8 +85,40 @@ constexpr int KC32 = 16;  // input channels per chunk, FP32 path
 constexpr int KC16 = 32;  // input channels per chunk, BF16 path
 constexpr int KC16S = 16; // BF16 path for 16- and 48-channel inputs: one 32-wide
                           // MFMA K slice covers two taps of 16 channels
+constexpr int KC8 = 32;   // FP8 path, as BF16
+constexpr int KC8S = 16;
+constexpr float E4M3_MAX = 448.0f;
 
 }  // namespace
+
+// OCP FP8 e4m3: 1 sign, 4 exponent bits (bias 7), 3 mantissa bits, no
+// infinities, 0x7f / 0xff NaN, largest finite 448, subnormal step 2^-9.
+// Encoding rounds to nearest even and saturates at +-448.
+__host__ __device__ inline uint8_t e4m3_enc(float x) {
+  if (x != x) return 0x7f;
+  uint8_t s = 0;
+  if (x < 0.0f) {
+    s = 0x80;
+    x = -x;
+  }
+  if (x >= E4M3_MAX) return s | 0x7e;
+  if (x < 0.015625f) return s | (uint8_t)rintf(x * 512.0f);  // subnormal (8 -> 0x08, the smallest normal)
+  int e;
+  (void)frexpf(x, &e);                          // x in [2^(e-1), 2^e)
+  int m = (int)rintf(ldexpf(x, 4 - e)) - 8;     // mantissa steps of 2^(e-4), in [0, 8]
+  int E = e - 1 + 7;
+  if (m == 8) {
+    m = 0;
+    ++E;
+  }
+  return s | (uint8_t)((E << 3) | m);  // x < 448 keeps (E, m) <= (15, 6)
+}
+__host__ __device__ inline float e4m3_dec(uint8_t v) {
+  const int e = (v >> 3) & 15, m = v & 7;
+  float mag = e ? ldexpf((float)(8 + m), e - 10) : ldexpf((float)m, -9);
+  if ((v & 0x7f) == 0x7f) mag = NAN;
+  return (v & 0x80) ? -mag : mag;
+}
 
 // Parses the NPGW v1 file and checks the declared topology.
 static int parse_model(npg_ctx *ctx, const unsigned char *buf, size_t len, npg_model *m) {
@@ -223,6 +266,7 @@ extern "C" void npg_model_free(npg_model *m) {
   if (m->ctx) {
     (void)hipSetDevice(m->ctx->device);
     npg_device_free(m->ctx, m->blob, m->blob_bytes);
+    if (m->blob8) npg_device_free(m->ctx, m->blob8, m->blob8_bytes);
   }
   delete m;
 }
@@ -250,10 +294,12 @@ template <class T> __device__ __forceinline__ double to_d(T v);
 template <> __device__ __forceinline__ double to_d<double>(double v) { return v; }
 template <> __device__ __forceinline__ double to_d<float>(float v) { return v; }
 template <> __device__ __forceinline__ double to_d<uint16_t>(uint16_t v) { return bf2f(v); }
+template <> __device__ __forceinline__ double to_d<uint8_t>(uint8_t v) { return e4m3_dec(v); }
 template <class T> __device__ __forceinline__ T from_d(double v);
 template <> __device__ __forceinline__ double from_d<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_d<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ uint16_t from_d<uint16_t>(double v) { return f2bf((float)v); }
+template <> __device__ __forceinline__ uint8_t from_d<uint8_t>(double v) { return e4m3_enc((float)v); }
 
 // Source tensors of one convolution's (virtual) input.
 struct Src {
@@ -263,11 +309,12 @@ struct Src {
   const void *s1;      // UPCAT: skip [L][H][W][C1]
   const double *tot;   // ENERGY: per-leaf energy totals
   int C0, C1;
+  float dq0 = 1.0f, dq1 = 1.0f;  // FP8: value of one e4m3 unit of s0 / s1
 };
 
-// One input element (leaf, y, x, c) as float; (y, x) inside the map.
+// One input element (leaf, y, x, c) in storage units; (y, x) inside the map.
 template <class T>
-__device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+__device__ __forceinline__ double src_raw(const Src &s, int leaf, int y, int x, int c, int H, int W) {
   switch (s.mode) {
     case SRC_ENERGY: {
       // the raw map is the float32 normalised energy (as npg_normalize_input)
@@ -291,13 +338,24 @@ __device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, i
   }
 }
 
+// The element's value (FP8 storage units times the source's scale).
+template <class T>
+__device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+  const double v = src_raw<T>(s, leaf, y, x, c, H, W);
+  if constexpr (sizeof(T) == 1) {
+    if (s.mode == SRC_ENERGY) return v;
+    return v * (double)((s.mode == SRC_UPCAT && c >= s.C0) ? s.dq1 : s.dq0);
+  }
+  return v;
+}
+
 // Direct convolution, one thread per output pixel, binary64 sums.
 // out: T [L][H][W][Cout] (ACT_RELU) or float [L][H][W] (ACT_SOFTPLUS, Cout 1).
 template <class T>
 __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *__restrict__ w,
                                                           const float *__restrict__ bias, int Cin, int Cout,
                                                           int k, int H, int W, size_t npix, int act,
-                                                          void *out) {
+                                                          float oinv, void *out) {
   const size_t pix = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (pix >= npix) return;
   const int HW = H * W;
@@ -328,7 +386,10 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
       static_cast<float *>(out)[pix] = (float)softplus_f(acc[0]);
     } else {
       T *o = static_cast<T *>(out) + pix * Cout + co0;
-      for (int j = 0; j < nco; ++j) o[j] = from_d<T>(fmax(acc[j], 0.0));
+      for (int j = 0; j < nco; ++j) {
+        const double r = fmax(acc[j], 0.0);
+        o[j] = from_d<T>(sizeof(T) == 1 ? r * (double)oinv : r);
+      }
     }
   }
 }
@@ -343,7 +404,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
                                                          const double *__restrict__ tot,
                                                          const float *__restrict__ w,
                                                          const float *__restrict__ bias, int C0, int H,
-                                                         int W, int TW, int TR, void *out) {
+                                                         int W, int TW, int TR, float oinv, void *out) {
   __shared__ Acc xs[800];  // (TR+2) x (TW+2) <= 3 x 258 for TR*TW = 256
   const int tiles_x = W / TW;
   const int tpl = (H / TR) * tiles_x;
@@ -374,7 +435,8 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
       Acc a = (Acc)bias[c];
 #pragma unroll
       for (int k = 0; k < 9; ++k) a = fma((Acc)w[c * 9 + k], (Acc)xv[k], a);
-      res[c] = from_d<T>((double)(a > (Acc)0 ? a : (Acc)0));
+      const Acc r = a > (Acc)0 ? a : (Acc)0;
+      res[c] = from_d<T>(sizeof(T) == 1 ? (double)(r * (Acc)oinv) : (double)r);
     }
   }
   T *o = static_cast<T *>(out) + (((size_t)leaf * H + ty0 + ty) * W + tx0 + tx) * C0;
@@ -387,6 +449,18 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
   }
 }
 
+// Largest element of a non-negative (post-ReLU) activation buffer, as float
+// bits (ordered like the values for non-negative floats).
+template <class T>
+__global__ __launch_bounds__(256) void amax_kernel(const T *__restrict__ x, size_t n, unsigned *out) {
+  float m = 0.0f;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    m = fmaxf(m, (float)x[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
 // ---------------------------------------------------------- MFMA conv
 // Output fragment of a 16x16 MFMA block: lane l holds column l % 16 and four
 // rows.  The f32 instructions give rows 4*(l/16) + r, r = 0..3; the f64
@@ -395,28 +469,41 @@ struct F32P {
   using T = double;   // activations
   using WT = float;   // weights
   using Acc = f64x4;
-  static constexpr bool F64 = true;
-  static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, MAX_TILES = 8;
+  static constexpr bool F64 = true, Q8 = false;
+  static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, KCP = 0, MAX_TILES = 8;
   static constexpr int SB = 1;  // matrix-bound: keep registers for occupancy
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
 };
+// 8-bit and 16-bit traits: a lane's A or B fragment is 8 consecutive K
+// values (channels) of one pixel or output channel; PSTR / KCP are the LDS
+// row strides (elements) of the patch and of the weight tile.
 struct BF16P {
   using T = uint16_t;
   using WT = uint16_t;
   using Acc = f32x4;
-  static constexpr bool F64 = false;
-  static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
+  using Frag = bf16x8;
+  static constexpr bool F64 = false, Q8 = false;
+  static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
   static constexpr int SB = 4;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
+  __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
-struct BF16S {
-  using T = uint16_t;
-  using WT = uint16_t;
+struct BF16S : BF16P {
+  static constexpr int KC = KC16S, PSTR = KC + 8, KCP = KC + 8;
+};
+struct FP8P {
+  using T = uint8_t;
+  using WT = uint8_t;
   using Acc = f32x4;
-  static constexpr bool F64 = false;
-  static constexpr int KC = KC16S, VEC = 8, PSTR = KC + 8, MAX_TILES = 16;
+  using Frag = fp8x8;
+  static constexpr bool F64 = false, Q8 = true;
+  static constexpr int KC = KC8, VEC = 16, PSTR = KC + 16, KCP = KC + 16, MAX_TILES = 16;
   static constexpr int SB = 4;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
+  __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
+};
+struct FP8S : FP8P {
+  static constexpr int KC = KC8S, PSTR = KC + 32, KCP = KC + 32;
 };
 
 // n / d for n, d < 2^16 as a multiply-high by m = ceil(2^32 / d).
@@ -436,6 +523,8 @@ struct ConvArgs {
   const float *bias;
   const float *head_w;   // non-null: fuse the 1x1 head + softplus (Cout == 16)
   float head_b;
+  const float *wsc;      // FP8: per-output-channel weight scales
+  float oinv, asc;       // FP8: output quantisation multiplier (1/asc) and unit value
   void *out;
 };
 
@@ -505,7 +594,7 @@ template <class P, int MW, int NW>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
   using AccV = typename P::Acc;
-  using AS = decltype(AccV{}[0]);
+  using AS = std::remove_cv_t<std::remove_reference_t<decltype(AccV{}[0])>>;
   constexpr int KC = P::KC, VEC = P::VEC, PSTR = P::PSTR, G = KC / VEC;
   constexpr int SB = P::SB;  // global loads in flight per thread while staging
   constexpr int BN = 16 * NW;
@@ -516,7 +605,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // FP32 B tile: [tap][kc][BNP], row stride chosen so the four k-rows a
   // fragment read touches fall in different LDS banks.
   constexpr int BNP = BN + ((16 - BN) & 63);
-  constexpr int KCP = KC + 8;  // BF16 B tile: [tap][n][KCP]
+  constexpr int KCP = P::KCP;  // 8/16-bit B tile: [tap][n][KCP]
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2, PH = TR + 2;
   const int H = a.H, W = a.W;
@@ -614,7 +703,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
       }
     } else {
-      constexpr int R8 = KC / 8;  // 8 bf16 per row piece
+      constexpr int WV = 16 / (int)sizeof(WT);  // weights per 16-byte piece
+      constexpr int R8 = KC / WV;
       constexpr int WITEMS = NTAPW * BN * R8;
       for (int base = 0; base < WITEMS; base += 256 * SB) {
         uint4 v[SB];
@@ -624,7 +714,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           v[k] = make_uint4(0, 0, 0, 0);
           if (it < WITEMS) {
             const int row = it / R8, c8 = it - row * R8;
-            if (row < 9 * BN) v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * 8);
+            if (row < 9 * BN) v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * WV);
           }
         }
 #pragma unroll
@@ -632,7 +722,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           const int it = base + k * 256 + tid;
           if (it < WITEMS) {
             const int row = it / R8, c8 = it - row * R8;
-            *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * 8) = v[k];
+            *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * WV) = v[k];
           }
         }
       }
@@ -658,18 +748,18 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
               acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
         }
       } else if constexpr (!TWO_TAP) {
-        bf16x8 av[MW], bv[NW];
+        using Frag = typename P::Frag;
+        Frag av[MW], bv[NW];
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
-          av[mi] = *reinterpret_cast<const bf16x8 *>(patch + (bp[mi] + toff) * PSTR + lg * 8);
+          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + toff) * PSTR + lg * 8);
 #pragma unroll
         for (int ni = 0; ni < NW; ++ni)
-          bv[ni] = *reinterpret_cast<const bf16x8 *>(wl + (tap * BN + ni * 16 + lr) * KCP + lg * 8);
+          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tap * BN + ni * 16 + lr) * KCP + lg * 8);
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < NW; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(av[mi], bv[ni], acc[mi][ni]);
       } else {
         if (tap & 1) continue;  // taps handled in pairs (tap, tap + 1)
         // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
@@ -677,18 +767,18 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         const int tl = tap + (lg >> 1);
         const int tofl = tl < 9 ? (tl / 3) * PW + (tl % 3) : 0;
         const int cofs = (lg & 1) * 8;
-        bf16x8 av[MW], bv[NW];
+        using Frag = typename P::Frag;
+        Frag av[MW], bv[NW];
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
-          av[mi] = *reinterpret_cast<const bf16x8 *>(patch + (bp[mi] + tofl) * PSTR + cofs);
+          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + tofl) * PSTR + cofs);
 #pragma unroll
         for (int ni = 0; ni < NW; ++ni)
-          bv[ni] = *reinterpret_cast<const bf16x8 *>(wl + (tl * BN + ni * 16 + lr) * KCP + cofs);
+          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tl * BN + ni * 16 + lr) * KCP + cofs);
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < NW; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(av[mi], bv[ni], acc[mi][ni]);
       }
     }
     __syncthreads();
@@ -706,6 +796,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     float *dl = reinterpret_cast<float *>(smem);  // [BM] densities
     const AS bn = (AS)a.bias[lr];
     const AS hw = (AS)a.head_w[lr];
+    AS ws = (AS)1;
+    if constexpr (P::Q8) ws = (AS)a.wsc[lr];
     // after the 16-lane reductions every lane of group lg holds the sum of
     // pixel (mi, r); lane lr keeps pixel (lr / 4, lr % 4) so one softplus per
     // lane covers the wavefront's pixels
@@ -715,8 +807,15 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // the value the unfused path would store (type T) feeds the head
-        const AS v0 = acc[mi][0][r] + bn;
-        const double act = to_d<T>(from_d<T>((double)(v0 > (AS)0 ? v0 : (AS)0)));
+        AS v0;
+        double act;
+        if constexpr (P::Q8) {
+          v0 = acc[mi][0][r] * ws + bn;
+          act = (double)(e4m3_dec(e4m3_enc((v0 > (AS)0 ? v0 : (AS)0) * a.oinv)) * a.asc);
+        } else {
+          v0 = acc[mi][0][r] + bn;
+          act = to_d<T>(from_d<T>((double)(v0 > (AS)0 ? v0 : (AS)0)));
+        }
         AS v = (AS)act * hw;
         v += __shfl_xor(v, 1);
         v += __shfl_xor(v, 2);
@@ -742,13 +841,20 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   for (int ni = 0; ni < NW; ++ni) {
     const int n = ni * 16 + lr;
     const AS bn = (AS)a.bias[n];
+    AS ws = (AS)1;
+    if constexpr (P::Q8) ws = (AS)a.wsc[n];
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
-        const AS v = acc[mi][ni][r] + bn;
-        ol[m * BN + n] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));
+        if constexpr (P::Q8) {
+          const AS v = acc[mi][ni][r] * ws + bn;
+          ol[m * BN + n] = e4m3_enc((v > (AS)0 ? v : (AS)0) * a.oinv);
+        } else {
+          const AS v = acc[mi][ni][r] + bn;
+          ol[m * BN + n] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));
+        }
       }
   }
   __syncthreads();
@@ -776,7 +882,7 @@ size_t conv_lds_bytes(const Tiling &t) {
   size_t wts;
   using WT = typename P::WT;
   if (P::F64) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
-  else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * (P::KC + 8) * sizeof(WT);
+  else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
   const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
   return std::max(patch + wts, epi);
 }
@@ -859,6 +965,8 @@ struct Runner {
   int mw_all = 4;                            // cap for every call (autotuner probes)
   std::vector<hipEvent_t> *ev = nullptr;     // per-call begin/end events (autotuner)
   int call = 0;                              // conv call index within a chunk
+  unsigned *amax = nullptr;                  // calibration: per-call max of the stored output
+                                             // (float bits); the head is then not fused
 
   int cap() const {
     int c = mw_all;
@@ -867,8 +975,20 @@ struct Runner {
   }
   bool tiling(const LayerDev &y, int H, int W, Tiling *t) const {
     if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t, cap());
+    if (prec == NPG_FP8) {
+      if (y.cin % KC8 == 0) return pick_tiling<FP8P>(y.cout, H, W, t, cap());
+      return pick_tiling<FP8S>(y.cout, H, W, t, cap());
+    }
     if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t, cap());
     return pick_tiling<BF16S>(y.cout, H, W, t, cap());
+  }
+  // channel granularity of the tiled kernel's 16-byte input loads
+  int vec() const { return prec == NPG_FP32 ? 2 : prec == NPG_FP8 ? 16 : 8; }
+  bool mfma_fits(const LayerDev &y, const Src &src, int H, int W, Tiling *t) const {
+    const int v = vec();
+    if (force_direct || y.k != 3 || src.mode == SRC_ENERGY || y.cin % v) return false;
+    if (src.mode == SRC_UPCAT && (src.C0 % v || src.C1 % v)) return false;
+    return tiling(y, H, W, t);
   }
 
   int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
@@ -880,6 +1000,16 @@ struct Runner {
     if (ev && !rc) {
       if (hipEventRecord((*ev)[2 * call + 1], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
     }
+    if (amax && !rc && act == ACT_RELU && !head) {
+      const size_t n = (size_t)Lc * H * W * y.cout;
+      const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+      if (prec == NPG_FP32)
+        hipLaunchKernelGGL(amax_kernel<double>, dim3(blocks), dim3(256), 0, s, static_cast<const double *>(out), n,
+                           amax + call);
+      else
+        return npg_fail(ctx, NPG_E_ARG, "internal: calibration runs in FP32");
+      if (hipGetLastError() != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "amax launch");
+    }
     ++call;
     return rc;
   }
@@ -888,8 +1018,7 @@ struct Runner {
   int conv_impl(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
                 int act) {
     Tiling t;
-    const bool mfma_ok = !force_direct && y.k == 3 && src.mode != SRC_ENERGY && act == ACT_RELU &&
-                         (y.cin % 8 == 0) && tiling(y, H, W, &t) && (!head || y.cout == 16);
+    const bool mfma_ok = act == ACT_RELU && mfma_fits(y, src, H, W, &t) && (!head || y.cout == 16);
     if (mfma_ok) {
       ConvArgs a;
       a.src = src;
@@ -908,6 +1037,9 @@ struct Runner {
       a.bias = y.b;
       a.head_w = head ? head->w : nullptr;
       a.head_b = head ? m->host_b[&*head - &m->layer[0]][0] : 0.0f;
+      a.wsc = y.wsc8;
+      a.oinv = 1.0f / y.a8;
+      a.asc = y.a8;
       a.out = out;
       const unsigned tiles = (unsigned)((Lc + t.TL - 1) / t.TL) * a.tiles_per_leaf;
       hipError_t e;
@@ -915,6 +1047,14 @@ struct Runner {
         a.nchunk = (y.cin + KC32 - 1) / KC32;
         a.wpk = y.pk32;
         e = launch_mfma<F32P>(a, t, tiles, s);
+      } else if (prec == NPG_FP8 && y.cin % KC8 == 0) {
+        a.nchunk = y.cin / KC8;
+        a.wpk = y.pk8;
+        e = launch_mfma<FP8P>(a, t, tiles, s);
+      } else if (prec == NPG_FP8) {
+        a.nchunk = (y.cin + KC8S - 1) / KC8S;
+        a.wpk = y.pk8s;
+        e = launch_mfma<FP8S>(a, t, tiles, s);
       } else if (y.cin % KC16 == 0) {
         a.nchunk = y.cin / KC16;
         a.wpk = y.pk16;
@@ -934,10 +1074,16 @@ struct Runner {
         const unsigned blocks = (unsigned)Lc * (H / TR) * (W / TW);
         if (prec == NPG_FP32)
           hipLaunchKernelGGL((conv_first_kernel<double, double>), dim3(blocks), dim3(256), 0, s,
-                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, out);
+                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, 1.0f,
+                             out);
+        else if (prec == NPG_FP8)
+          hipLaunchKernelGGL((conv_first_kernel<uint8_t, float>), dim3(blocks), dim3(256), 0, s,
+                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR,
+                             1.0f / y.a8, out);
         else
           hipLaunchKernelGGL((conv_first_kernel<uint16_t, float>), dim3(blocks), dim3(256), 0, s,
-                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, out);
+                             static_cast<const uint64_t *>(src.s0), src.tot, y.w, y.b, y.cout, H, W, TW, TR, 1.0f,
+                             out);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "first conv launch: %s", hipGetErrorString(e));
         return NPG_OK;
@@ -954,19 +1100,24 @@ struct Runner {
     const unsigned blocks = (unsigned)((npix + 255) / 256);
     if (prec == NPG_FP32)
       hipLaunchKernelGGL(conv_direct_kernel<double>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
-                         y.cout, y.k, H, W, npix, act, dst);
+                         y.cout, y.k, H, W, npix, act, 1.0f, dst);
+    else if (prec == NPG_FP8)
+      hipLaunchKernelGGL(conv_direct_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
+                         y.cout, y.k, H, W, npix, act, 1.0f / y.a8, dst);
     else
       hipLaunchKernelGGL(conv_direct_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b,
-                         y.cin, y.cout, y.k, H, W, npix, act, dst);
+                         y.cin, y.cout, y.k, H, W, npix, act, 1.0f, dst);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "direct conv launch: %s", hipGetErrorString(e));
     return NPG_OK;
   }
 };
 
-Src plain(const void *p, int C) { return Src{SRC_PLAIN, p, nullptr, nullptr, C, 0}; }
-Src pooled(const void *p, int C) { return Src{SRC_POOL, p, nullptr, nullptr, C, 0}; }
-Src upcat(const void *lo, int Cu, const void *skip, int Cs) { return Src{SRC_UPCAT, lo, skip, nullptr, Cu, Cs}; }
+Src plain(const void *p, int C, float q) { return Src{SRC_PLAIN, p, nullptr, nullptr, C, 0, q, 1.0f}; }
+Src pooled(const void *p, int C, float q) { return Src{SRC_POOL, p, nullptr, nullptr, C, 0, q, 1.0f}; }
+Src upcat(const void *lo, int Cu, const void *skip, int Cs, float qlo, float qskip) {
+  return Src{SRC_UPCAT, lo, skip, nullptr, Cu, Cs, qlo, qskip};
+}
 
 }  // namespace
 
@@ -1023,6 +1174,8 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
   const npg_model *m = R.m;
   int rc;
   R.call = 0;
+  // FP8: value of one stored unit of a layer's output
+  auto dq = [&](const LayerDev &y) { return R.prec == NPG_FP8 ? y.a8 : 1.0f; };
   if (m->arch == 1) {
     const int n = (int)m->layer.size();
     Src cur = in;
@@ -1033,7 +1186,7 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
       void *dst = last ? (void *)dens : (void *)bufs[i & 1];
       rc = R.conv(y, cur, Lc, H, W, dst, nullptr, last ? ACT_SOFTPLUS : ACT_RELU);
       if (rc) return rc;
-      cur = plain(dst, y.cout);
+      cur = plain(dst, y.cout, dq(y));
     }
     return NPG_OK;
   }
@@ -1041,21 +1194,23 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
   int h = H, w = W;
   const void *prev = nullptr;
   int prevC = 0;
+  float prevQ = 1.0f;
   for (int d = 0; d < D; ++d) {  // encoder
     const LayerDev &la = m->layer[2 * d], &lb = m->layer[2 * d + 1];
     Src sa = in;
     if (d > 0) {
       h /= 2;
       w /= 2;
-      sa = pooled(prev, prevC);
+      sa = pooled(prev, prevC, prevQ);
     }
     rc = R.conv(la, sa, Lc, h, w, B.tA, nullptr, ACT_RELU);
     if (rc) return rc;
     void *ob = d < D - 1 ? (void *)B.skip[d] : (void *)B.tB;
-    rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, ob, nullptr, ACT_RELU);
+    rc = R.conv(lb, plain(B.tA, la.cout, dq(la)), Lc, h, w, ob, nullptr, ACT_RELU);
     if (rc) return rc;
     prev = ob;
     prevC = lb.cout;
+    prevQ = dq(lb);
   }
   int li = 2 * D;
   for (int d = D - 2; d >= 0; --d) {  // decoder
@@ -1064,31 +1219,34 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
     h *= 2;
     w *= 2;
     const int cs = m->layer[2 * d].cout;
-    rc = R.conv(la, upcat(prev, prevC, B.skip[d], cs), Lc, h, w, B.tA, nullptr, ACT_RELU);
+    rc = R.conv(la, upcat(prev, prevC, B.skip[d], cs, prevQ, dq(m->layer[2 * d + 1])), Lc, h, w, B.tA, nullptr,
+                ACT_RELU);
     if (rc) return rc;
+    const Src sb = plain(B.tA, la.cout, dq(la));
     if (d == 0) {
       const LayerDev &hd = m->layer[li];
       Tiling t;
-      const bool fuse = !R.force_direct && R.tiling(lb, h, w, &t) && lb.cout == 16 && lb.cin % 8 == 0;
+      const bool fuse = !R.amax && lb.cout == 16 && R.mfma_fits(lb, sb, h, w, &t);
       if (fuse) {
-        rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, dens, &hd, ACT_RELU);
+        rc = R.conv(lb, sb, Lc, h, w, dens, &hd, ACT_RELU);
         if (rc) return rc;
       } else {
-        rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, B.tB, nullptr, ACT_RELU);
+        rc = R.conv(lb, sb, Lc, h, w, B.tB, nullptr, ACT_RELU);
         if (rc) return rc;
-        rc = R.conv(hd, plain(B.tB, lb.cout), Lc, h, w, dens, nullptr, ACT_SOFTPLUS);
+        rc = R.conv(hd, plain(B.tB, lb.cout, dq(lb)), Lc, h, w, dens, nullptr, ACT_SOFTPLUS);
         if (rc) return rc;
       }
     } else {
-      rc = R.conv(lb, plain(B.tA, la.cout), Lc, h, w, B.tB, nullptr, ACT_RELU);
+      rc = R.conv(lb, sb, Lc, h, w, B.tB, nullptr, ACT_RELU);
       if (rc) return rc;
       prev = B.tB;
       prevC = lb.cout;
+      prevQ = dq(lb);
     }
   }
   if (D == 1) {
     const LayerDev &hd = m->layer[2];
-    rc = R.conv(hd, plain(prev, prevC), Lc, H, W, dens, nullptr, ACT_SOFTPLUS);
+    rc = R.conv(hd, plain(prev, prevC, prevQ), Lc, H, W, dens, nullptr, ACT_SOFTPLUS);
     if (rc) return rc;
   }
   return NPG_OK;
@@ -1102,7 +1260,6 @@ int check_net_args(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision
     return npg_fail(ctx, NPG_E_ARG, "reconstruct: bad precision %d", (int)precision);
   if (precision == NPG_FP8 && !m->fp8_ready)
     return npg_fail(ctx, NPG_E_ARG, "reconstruct: FP8 needs npg_model_calibrate_fp8 first");
-  if (precision == NPG_FP8) return npg_fail(ctx, NPG_E_ARG, "reconstruct: FP8 not available");
   if (m->arch == 2) {
     const int f = 1 << (m->levels - 1);
     if (H % f || W % f) return npg_fail(ctx, NPG_E_ARG, "reconstruct: %dx%d not divisible by 2^%d", H, W, m->levels - 1);
@@ -1117,7 +1274,7 @@ std::string tune_key(const npg_model *m, npg_precision p, int H, int W) {
 }
 
 Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStream_t s) {
-  Runner R{ctx, m, prec, s, prec == NPG_FP32 ? sizeof(double) : (size_t)2};
+  Runner R{ctx, m, prec, s, prec == NPG_FP32 ? sizeof(double) : prec == NPG_FP8 ? (size_t)1 : (size_t)2};
   R.force_direct = (int)ctx->opt("force_direct", 0);
   return R;
 }
@@ -1152,26 +1309,19 @@ void apply_tune(npg_ctx *ctx, Runner &R, int H, int W, std::vector<int> *hold) {
 
 }  // namespace
 
-extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
-                                       const uint32_t *count_dev, uint32_t L, int H, int W,
-                                       npg_precision precision, float *density_dev, void *stream) {
-  (void)count_dev;
-  if (!ctx) return NPG_E_ARG;
-  int rc = check_net_args(ctx, m, H, W, precision);
-  if (rc) return rc;
-  if (L == 0) return NPG_OK;
-  if (!energy_dev || !density_dev) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null pointer");
-  rc = npg_set_device(ctx);
-  if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+// The network over L energy maps, chunk by chunk.  `amax` (calibration):
+// per-layer output maxima are recorded, with the head left unfused.
+static int run_density(npg_ctx *ctx, const npg_model *m, npg_precision precision, const uint64_t *energy_dev,
+                       uint32_t L, int H, int W, float *density_dev, hipStream_t s, unsigned *amax) {
   Runner R = make_runner(ctx, m, precision, s);
+  R.amax = amax;
   std::vector<int> caps;
   apply_tune(ctx, R, H, W, &caps);
   const size_t HW = (size_t)H * W;
   const NetPlan plan = plan_net(m, H, W, R.esz);
   const size_t fixed = npg_align(sizeof(double) * L) + (16u << 20);
   size_t chunk = 0;
-  rc = chunk_for(ctx, m, precision, H, W, L, plan.per_leaf, fixed, &chunk);
+  int rc = chunk_for(ctx, m, precision, H, W, L, plan.per_leaf, fixed, &chunk);
   if (rc) return rc;
   void *scr = nullptr;
   rc = npg_scratch(ctx, fixed + net_bufs_bytes(plan, chunk, R.esz), s, &scr);
@@ -1187,6 +1337,21 @@ extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const u
     if (rc) return rc;
   }
   return NPG_OK;
+}
+
+extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
+                                       const uint32_t *count_dev, uint32_t L, int H, int W,
+                                       npg_precision precision, float *density_dev, void *stream) {
+  (void)count_dev;
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_net_args(ctx, m, H, W, precision);
+  if (rc) return rc;
+  if (L == 0) return NPG_OK;
+  if (!energy_dev || !density_dev) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null pointer");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  return run_density(ctx, m, precision, energy_dev, L, H, W, density_dev, static_cast<hipStream_t>(stream),
+                     nullptr);
 }
 
 // ----------------------------------------------------------- fused path
@@ -1284,6 +1449,8 @@ extern "C" int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *m, const flo
   NPG_HIP_CHECK(ctx, hipGraphLaunch(exec, s));
   return NPG_OK;
 }
+
+bool npg_model_fp8_ready(const npg_model *m) { return m && m->fp8_ready; }
 
 bool npg_model_fits(const npg_model *m, int H, int W) {
   if (m->arch != 2) return true;
@@ -1436,9 +1603,119 @@ extern "C" int npg_tune_table(const npg_ctx *ctx, const npg_model *m, int H, int
   return n;
 }
 
-extern "C" int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *model, const uint64_t *energy_dev,
-                                       uint32_t L, int H, int W, void *stream) {
-  (void)model; (void)energy_dev; (void)L; (void)H; (void)W; (void)stream;
+// Layer whose output feeds each input channel of layer i (-1: the energy
+// map), following the CNN chain and the U-Net schedule of net_chunk.
+static std::vector<int> channel_producers(const npg_model *m, int i) {
+  const int cin = m->layer[i].cin;
+  std::vector<int> p(cin, i - 1);
+  if (i == 0) {
+    p.assign(cin, -1);
+    return p;
+  }
+  if (m->arch != 2) return p;
+  const int D = m->levels, j = i - 2 * D;  // j: index among decoder layers and head
+  if (j < 0 || j == 2 * (D - 1) || j % 2 == 1) return p;
+  // first conv of decoder level d: [upsampled previous output, skip of level d]
+  const int d = D - 2 - j / 2;
+  const int cu = m->layer[i - 1].cout;
+  for (int c = cu; c < cin; ++c) p[c] = 2 * d + 1;
+  return p;
+}
+
+extern "C" int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *m, const uint64_t *energy_dev, uint32_t L, int H,
+                                       int W, void *stream) {
   if (!ctx) return NPG_E_ARG;
-  return npg_fail(ctx, NPG_E_ARG, "calibrate_fp8: FP8 path not built yet");
+  int rc = check_net_args(ctx, m, H, W, NPG_FP32);
+  if (rc) return rc;
+  if (L == 0 || !energy_dev) return npg_fail(ctx, NPG_E_ARG, "calibrate_fp8: empty calibration batch");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = (int)m->layer.size();
+  // 1. FP32 forward pass recording the largest stored value of every layer
+  void *tmp = nullptr;
+  const size_t dens_bytes = npg_align((size_t)L * H * W * sizeof(float));
+  const size_t tmp_bytes = dens_bytes + npg_align(sizeof(unsigned) * n);
+  rc = npg_device_alloc(ctx, tmp_bytes, &tmp);
+  if (rc) return rc;
+  float *dens = static_cast<float *>(tmp);
+  unsigned *amax_dev = reinterpret_cast<unsigned *>(static_cast<char *>(tmp) + dens_bytes);
+  std::vector<unsigned> amax(n, 0u);
+  rc = hipMemsetAsync(amax_dev, 0, sizeof(unsigned) * n, s) == hipSuccess ? NPG_OK
+                                                                          : npg_fail(ctx, NPG_E_HIP, "memset");
+  if (!rc) rc = run_density(ctx, m, NPG_FP32, energy_dev, L, H, W, dens, s, amax_dev);
+  if (!rc && (hipMemcpyAsync(amax.data(), amax_dev, sizeof(unsigned) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess))
+    rc = npg_fail(ctx, NPG_E_HIP, "calibrate_fp8: readback failed");
+  npg_device_free(ctx, tmp, tmp_bytes);
+  if (rc) return rc;
+  // 2. activation scales: the largest stored value maps to the largest e4m3
+  std::vector<float> a8(n, 1.0f);
+  for (int i = 0; i < n; ++i) {
+    float v;
+    memcpy(&v, &amax[i], 4);
+    if (v > 0.0f && std::isfinite(v)) a8[i] = v / E4M3_MAX;
+  }
+  // 3. weights of every 3x3 layer fed by stored activations: fold the input
+  // channels' scales in, one scale per output channel, pack as the BF16 tiles
+  std::vector<char> blob;
+  struct Off { size_t p8, p8s, sc; };
+  std::vector<Off> offs(n, Off{(size_t)-1, (size_t)-1, (size_t)-1});
+  auto put = [&](const void *src, size_t bytes) {
+    size_t at = npg_align(blob.size());
+    blob.resize(at + npg_align(bytes));
+    memcpy(blob.data() + at, src, bytes);
+    return at;
+  };
+  for (int i = 1; i < n; ++i) {
+    const LayerDev &y = m->layer[i];
+    if (y.k != 3) continue;
+    const std::vector<int> prod = channel_producers(m, i);
+    const std::vector<float> &w = m->host_w[i];
+    std::vector<float> wf(w.size()), sc(y.cout, 1.0f);
+    for (int co = 0; co < y.cout; ++co) {
+      float mx = 0.0f;
+      for (int ci = 0; ci < y.cin; ++ci)
+        for (int t = 0; t < 9; ++t) {
+          const size_t k = ((size_t)co * y.cin + ci) * 9 + t;
+          wf[k] = w[k] * (prod[ci] >= 0 ? a8[prod[ci]] : 1.0f);
+          mx = std::max(mx, std::fabs(wf[k]));
+        }
+      if (mx > 0.0f) sc[co] = mx / E4M3_MAX;
+    }
+    const int nch = (y.cin + KC8 - 1) / KC8, nchs = (y.cin + KC8S - 1) / KC8S;
+    std::vector<uint8_t> p8((size_t)nch * 9 * y.cout * KC8, 0), p8s((size_t)nchs * 9 * y.cout * KC8S, 0);
+    for (int co = 0; co < y.cout; ++co)
+      for (int ci = 0; ci < y.cin; ++ci)
+        for (int t = 0; t < 9; ++t) {
+          const uint8_t q = e4m3_enc(wf[((size_t)co * y.cin + ci) * 9 + t] / sc[co]);
+          p8[(((size_t)(ci / KC8) * 9 + t) * y.cout + co) * KC8 + ci % KC8] = q;
+          p8s[(((size_t)(ci / KC8S) * 9 + t) * y.cout + co) * KC8S + ci % KC8S] = q;
+        }
+    offs[i].p8 = put(p8.data(), p8.size());
+    offs[i].p8s = put(p8s.data(), p8s.size());
+    offs[i].sc = put(sc.data(), 4 * sc.size());
+  }
+  void *dev = nullptr;
+  if (!blob.empty()) {
+    rc = npg_device_alloc(ctx, blob.size(), &dev);
+    if (rc) return rc;
+    if (hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      npg_device_free(ctx, dev, blob.size());
+      return npg_fail(ctx, NPG_E_HIP, "calibrate_fp8: upload failed");
+    }
+  }
+  if (m->blob8) npg_device_free(ctx, m->blob8, m->blob8_bytes);
+  m->blob8 = dev;
+  m->blob8_bytes = blob.size();
+  char *base = static_cast<char *>(dev);
+  for (int i = 0; i < n; ++i) {
+    LayerDev &y = m->layer[i];
+    y.a8 = a8[i];
+    y.pk8 = offs[i].p8 == (size_t)-1 ? nullptr : reinterpret_cast<uint8_t *>(base + offs[i].p8);
+    y.pk8s = offs[i].p8s == (size_t)-1 ? nullptr : reinterpret_cast<uint8_t *>(base + offs[i].p8s);
+    y.wsc8 = offs[i].sc == (size_t)-1 ? nullptr : reinterpret_cast<float *>(base + offs[i].sc);
+  }
+  m->fp8_ready = true;
+  return NPG_OK;
 }

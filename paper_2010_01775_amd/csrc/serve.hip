@@ -19,6 +19,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 
 #include "npg_internal.h"
@@ -43,7 +44,7 @@ struct Req {
   int state = QUEUED;
   int rc = NPG_OK;
   bool release_on_done = false;
-  int users = 0;               // launched sampling requests still reading the tables
+  int users = 0;               // sampling requests submitted against the tables, not yet done
   double t_submit = 0, t_start = 0, t_done = 0;
   // reconstruction
   const float *dir = nullptr;
@@ -148,6 +149,11 @@ struct npg_server {
   int launch_recon(Slot &sl, std::vector<uint64_t> &batch);
   int run_sample(Slot &sl, Req &r);
   void free_tables(Req &r);
+  void drop_user(uint64_t recon);
+  int unknown(uint64_t ticket) {
+    error = "serve: unknown or released ticket " + std::to_string(ticket);
+    return NPG_E_ARG;
+  }
 };
 
 void npg_server::free_tables(Req &r) {
@@ -158,6 +164,18 @@ void npg_server::free_tables(Req &r) {
   if (r.ready) {
     (void)hipEventDestroy(r.ready);
     r.ready = nullptr;
+  }
+}
+
+// A sampling request against `recon` has finished (or failed, or was
+// released before it ran): the tables go once they are released and unused.
+void npg_server::drop_user(uint64_t recon) {
+  auto rr = reqs.find(recon);
+  if (rr == reqs.end()) return;
+  Req &rc = rr->second;
+  if (--rc.users == 0 && rc.release_on_done && (rc.state == DONE || rc.state == FAILED)) {
+    free_tables(rc);
+    reqs.erase(rr);
   }
 }
 
@@ -173,18 +191,14 @@ bool npg_server::completions() {
       if (it == reqs.end()) continue;
       Req &r = it->second;
       r.state = q == hipSuccess ? DONE : FAILED;
-      if (q != hipSuccess) r.rc = NPG_E_HIP;
+      if (q != hipSuccess) {
+        r.rc = NPG_E_HIP;
+        error = std::string("serve: batch failed on the device: ") + hipGetErrorString(q);
+      }
       r.t_done = t;
       ++stats.completed;
       if (r.kind == SAMPLE) {
-        auto rr = reqs.find(r.recon);
-        if (rr != reqs.end()) {
-          Req &rc = rr->second;
-          if (--rc.users == 0 && rc.release_on_done && rc.state != RUNNING) {
-            free_tables(rc);
-            reqs.erase(rr);
-          }
-        }
+        drop_user(r.recon);
         it = reqs.find(id);
       }
       if (it != reqs.end() && it->second.release_on_done && it->second.users == 0) {
@@ -283,14 +297,16 @@ void npg_server::admit() {
         const uint64_t id = head.id;
         pending.erase(pit);
         head.t_start = t;
-        const int rc = (rr == reqs.end() || rr->second.state == FAILED) ? NPG_E_ARG : run_sample(sl, head);
+        const bool orphan = rr == reqs.end() || rr->second.state == FAILED;
+        const int rc = orphan ? NPG_E_ARG : run_sample(sl, head);
         if (rc) {
+          error = orphan ? "serve: sampling request against a failed reconstruction" : sl.ctx->last_error;
           head.state = FAILED;
           head.rc = rc;
           head.t_done = t;
+          drop_user(head.recon);
           break;  // iterator invalidated; the next round retries
         }
-        ++rr->second.users;
         head.state = RUNNING;
         sl.tickets = {id};
         sl.busy = true;
@@ -379,8 +395,10 @@ int npg_serve_create(npg_ctx *ctx, const npg_model *model, const npg_serve_param
   *out = nullptr;
   if (prm->n_slots < 1 || prm->n_slots > 16 || prm->table_bytes == 0)
     return npg_fail(ctx, NPG_E_ARG, "serve: n_slots in [1,16] and table_bytes > 0 required");
-  if (prm->precision != NPG_FP32 && prm->precision != NPG_BF16)
-    return npg_fail(ctx, NPG_E_ARG, "serve: precision must be FP32 or BF16");
+  if (prm->precision != NPG_FP32 && prm->precision != NPG_BF16 && prm->precision != NPG_FP8)
+    return npg_fail(ctx, NPG_E_ARG, "serve: bad precision %d", (int)prm->precision);
+  if (prm->precision == NPG_FP8 && !npg_model_fp8_ready(model))
+    return npg_fail(ctx, NPG_E_ARG, "serve: FP8 needs npg_model_calibrate_fp8 first");
   int rc = npg_set_device(ctx);
   if (rc) return rc;
   npg_server *sv = new npg_server();
@@ -486,6 +504,7 @@ int npg_serve_submit_sample(npg_server *sv, uint64_t recon_ticket, const uint32_
     auto it = sv->reqs.find(recon_ticket);
     if (it == sv->reqs.end() || it->second.kind != RECON)
       return npg_fail(sv->parent, NPG_E_ARG, "serve: unknown reconstruction ticket");
+    ++it->second.users;  // the tables stay until this request is done
     r.id = sv->next_id++;
     *ticket = r.id;
     sv->pending.push_back(r.id);
@@ -500,7 +519,7 @@ int npg_serve_poll(npg_server *sv, uint64_t ticket, double *latency_us) {
   if (!sv) return NPG_E_ARG;
   std::lock_guard<std::mutex> lk(sv->mu);
   auto it = sv->reqs.find(ticket);
-  if (it == sv->reqs.end()) return NPG_E_ARG;
+  if (it == sv->reqs.end()) return sv->unknown(ticket);
   const Req &r = it->second;
   if (r.state == FAILED) return r.rc ? r.rc : NPG_E_HIP;
   if (r.state != DONE) return 0;
@@ -513,7 +532,7 @@ int npg_serve_wait(npg_server *sv, uint64_t ticket, double *latency_us) {
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
     auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end()) return NPG_E_ARG;
+    if (it == sv->reqs.end()) return sv->unknown(ticket);
     const Req &r = it->second;
     if (r.state == FAILED) return r.rc ? r.rc : NPG_E_HIP;
     if (r.state == DONE) {
@@ -528,10 +547,22 @@ int npg_serve_tables(npg_server *sv, uint64_t ticket, npg_tables *out) {
   if (!sv || !out) return NPG_E_ARG;
   std::lock_guard<std::mutex> lk(sv->mu);
   auto it = sv->reqs.find(ticket);
-  if (it == sv->reqs.end() || it->second.kind != RECON || it->second.state != DONE) return NPG_E_ARG;
+  if (it == sv->reqs.end()) return sv->unknown(ticket);
+  if (it->second.kind != RECON || it->second.state != DONE) {
+    sv->error = "serve: tables of a request that is not a finished reconstruction";
+    return NPG_E_ARG;
+  }
   const Req &r = it->second;
   *out = npg_tables{r.pdf, r.marg, r.cond, r.total, r.L, r.H, r.W};
   return NPG_OK;
+}
+
+const char *npg_serve_last_error(npg_server *sv) {
+  thread_local std::string copy;
+  if (!sv) return "";
+  std::lock_guard<std::mutex> lk(sv->mu);
+  copy = sv->error;
+  return copy.c_str();
 }
 
 int npg_serve_release(npg_server *sv, uint64_t ticket) {
@@ -539,7 +570,7 @@ int npg_serve_release(npg_server *sv, uint64_t ticket) {
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end()) return NPG_E_ARG;
+    if (it == sv->reqs.end()) return sv->unknown(ticket);
     Req &r = it->second;
     if (r.state == RUNNING || r.users > 0) {
       r.release_on_done = true;
@@ -550,8 +581,11 @@ int npg_serve_release(npg_server *sv, uint64_t ticket) {
             sv->pending.erase(p);
             break;
           }
+      const bool queued_sample = r.kind == SAMPLE && r.state == QUEUED;
+      const uint64_t recon = r.recon;
       sv->free_tables(r);
       sv->reqs.erase(it);
+      if (queued_sample) sv->drop_user(recon);
     }
   }
   sv->cv_work.notify_all();

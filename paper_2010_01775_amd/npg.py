@@ -28,7 +28,7 @@ SYMBOLS = [
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
     "npg_serve_create", "npg_serve_destroy", "npg_serve_submit_recon", "npg_serve_submit_sample",
     "npg_serve_poll", "npg_serve_wait", "npg_serve_tables", "npg_serve_copy_tables", "npg_serve_release",
-    "npg_serve_get_stats",
+    "npg_serve_get_stats", "npg_serve_last_error",
 ]
 
 
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "npg_serve_copy_tables": (I, [P, U64, P, P, P, P, P]),
         "npg_serve_release": (I, [P, U64]),
         "npg_serve_get_stats": (None, [P, C.POINTER(ServeStats)]),
+        "npg_serve_last_error": (C.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -365,6 +366,9 @@ class Server:
         self.h = h
         self.lib = ctx.lib
 
+    def _raise(self, rc, what):
+        raise NpgError(rc, f"{what}: {self.lib.npg_serve_last_error(self.h).decode()}")
+
     def submit_recon(self, dirs, w, begin, count, H: int, W: int) -> int:
         import numpy as np
         b = np.ascontiguousarray(begin, dtype=np.uint32)
@@ -384,27 +388,27 @@ class Server:
         lat = C.c_double()
         rc = self.lib.npg_serve_poll(self.h, ticket, C.byref(lat))
         if rc < 0:
-            raise NpgError(rc, "request failed")
+            self._raise(rc, "request failed")
         return (lat.value if rc == 1 else None)
 
     def wait(self, ticket: int) -> float:
         lat = C.c_double()
         rc = self.lib.npg_serve_wait(self.h, ticket, C.byref(lat))
         if rc < 0:
-            raise NpgError(rc, "request failed")
+            self._raise(rc, "request failed")
         return lat.value
 
     def copy_tables(self, ticket: int, out: CdfTables, stream=None):
         rc = self.lib.npg_serve_copy_tables(self.h, ticket, _ptr(out.pdf), _ptr(out.marg), _ptr(out.cond),
                                             _ptr(out.total), _stream(stream))
         if rc:
-            raise NpgError(rc, "copy_tables failed")
+            self._raise(rc, "copy_tables failed")
         return out
 
     def release(self, ticket: int):
         rc = self.lib.npg_serve_release(self.h, ticket)
         if rc:
-            raise NpgError(rc, "release failed")
+            self._raise(rc, "release failed")
 
     def stats(self) -> dict:
         st = ServeStats()

@@ -50,10 +50,15 @@ def _same(a, b):
     return all(torch.equal(x, y) for x, y in ((a.pdf, b.pdf), (a.marg, b.marg), (a.cond, b.cond), (a.total, b.total)))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp8"])
 def test_alone_equals_mix(ctx, npg, pool, prec):
     dirs, w, n_pool = pool
     m = npg.Model(ctx, synth.unet_model(9, random_bias=True))
+    if prec == "fp8":
+        for H in (64, 128):   # calibration is per model; the last one holds for both map sizes
+            b = synth.uniform_batch(seed=90, L=16, per_leaf=4096, H=H, W=H, n_queries=8, model=b"")
+            e, _ = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), H, H, want_count=False)
+        m.calibrate_fp8(e)
     srv = npg.Server(ctx, m, n_slots=2, max_batch_leaves=4096, table_bytes=4 << 30, precision=prec)
     reqs = [(_request(100 + i, n_pool, L), H) for i, (L, H) in
             enumerate([(5, 64), (40, 128), (1, 64), (17, 64), (60, 64), (3, 128), (25, 64), (8, 128), (33, 64)])]
@@ -134,5 +139,34 @@ def test_served_sampling_equals_direct(ctx, npg, pool):
     assert torch.equal(d, d2) and torch.equal(p, p2)
     srv.release(ts)
     srv.release(t)
+    srv.close()
+    m.free()
+
+
+def test_release_with_queued_sampling(ctx, npg, pool):
+    """Releasing a reconstruction while sampling requests against it are
+    still queued keeps its tables until they are done."""
+    dirs, w, n_pool = pool
+    m = npg.Model(ctx, synth.unet_model(4))
+    srv = npg.Server(ctx, m, n_slots=1, precision="bf16", table_bytes=1 << 30)
+    ref = srv.submit_recon(dirs, w, *_request(6, n_pool, 20), 64, 64)
+    n = 100000
+    leaf = t32(np.random.default_rng(3).integers(0, 20, n).astype(np.uint32))
+    u = tf(synth.uniforms(synth.rng_for(4), 2 * n).reshape(n, 2))
+    outs = [(torch.empty((n, 3), device=DEV), torch.empty(n, device=DEV)) for _ in range(3)]
+    srv.wait(ref)
+    want = srv.copy_tables(ref, _tables(npg, 20, 64, 64))
+    d0, p0, _ = npg.sample_dirs(ctx, want, leaf, u, want_bin=False)
+    torch.cuda.synchronize()
+    t = srv.submit_recon(dirs, w, *_request(6, n_pool, 20), 64, 64)
+    ts = [srv.submit_sample(t, leaf, u, *o) for o in outs]
+    srv.release(t)
+    for k, o in zip(ts, outs):
+        srv.wait(k)
+        torch.cuda.synchronize()
+        assert torch.equal(o[0], d0) and torch.equal(o[1], p0)
+        srv.release(k)
+    srv.release(ref)
+    assert srv.stats()["table_bytes_free"] == 1 << 30
     srv.close()
     m.free()

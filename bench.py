@@ -237,6 +237,7 @@ def main():
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -346,6 +347,10 @@ def main():
         else:
             npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
         model.calibrate_fp8(energy[::16][:256].contiguous())
+    tune = None
+    if not args.no_autotune:
+        # per-layer pixel tiles and leaf-chunk size, chosen once before timing
+        tune = npg.autotune(ctx, model, H, W, args.precision, probe_leaves=min(L, 1024))
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -403,7 +408,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f64", "bf16": "bf16", "fp8": "fp8-e4m3"}[args.precision],
         "data": "synthetic (seeded vMF-mixture photons, He-init weights)",
-        "config": {"workload": desc, "leaves": L, "H": H, "W": W, "queries": nq,
+        "config": {"workload": desc, "leaves": L, "H": H, "W": W, "queries": nq, "autotuned": tune,
                    "precision": {"fp32": "fp32 weights, f64 activations and conv accumulation",
                                  "bf16": "bf16 conv, f32 accumulation",
                                  "fp8": "fp8 e4m3 conv (static per-layer activation scales, "

@@ -120,6 +120,15 @@ __host__ __device__ inline float e4m3_dec(uint8_t v) {
   return (v & 0x80) ? -mag : mag;
 }
 
+// Device forms on the conversion instructions (gfx950 converts to OCP e4m3
+// with round to nearest even; out-of-range inputs, which would give NaN,
+// are clamped first so that both forms saturate alike).
+__device__ __forceinline__ uint8_t e4m3_enc_d(float x) {
+  const float c = x != x ? x : fminf(fmaxf(x, -E4M3_MAX), E4M3_MAX);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(c, c, 0, false) & 0xff);
+}
+__device__ __forceinline__ float e4m3_dec_d(uint8_t v) { return __builtin_amdgcn_cvt_f32_fp8((int)v, 0); }
+
 // Parses the NPGW v1 file and checks the declared topology.
 static int parse_model(npg_ctx *ctx, const unsigned char *buf, size_t len, npg_model *m) {
   if (len < 20 || memcmp(buf, "NPGW", 4) != 0 || rd32(buf + 4) != 1)
@@ -294,12 +303,12 @@ template <class T> __device__ __forceinline__ double to_d(T v);
 template <> __device__ __forceinline__ double to_d<double>(double v) { return v; }
 template <> __device__ __forceinline__ double to_d<float>(float v) { return v; }
 template <> __device__ __forceinline__ double to_d<uint16_t>(uint16_t v) { return bf2f(v); }
-template <> __device__ __forceinline__ double to_d<uint8_t>(uint8_t v) { return e4m3_dec(v); }
+template <> __device__ __forceinline__ double to_d<uint8_t>(uint8_t v) { return e4m3_dec_d(v); }
 template <class T> __device__ __forceinline__ T from_d(double v);
 template <> __device__ __forceinline__ double from_d<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_d<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ uint16_t from_d<uint16_t>(double v) { return f2bf((float)v); }
-template <> __device__ __forceinline__ uint8_t from_d<uint8_t>(double v) { return e4m3_enc((float)v); }
+template <> __device__ __forceinline__ uint8_t from_d<uint8_t>(double v) { return e4m3_enc_d((float)v); }
 
 // Source tensors of one convolution's (virtual) input.
 struct Src {
@@ -575,9 +584,28 @@ __device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, 
   const uint4 b = *reinterpret_cast<const uint4 *>(p + s.C0);
   const uint4 cc = *reinterpret_cast<const uint4 *>(p + dr);
   const uint4 d = *reinterpret_cast<const uint4 *>(p + dr + s.C0);
+  uint4 r;
+  if constexpr (sizeof(T) == 1) {
+    // sums of four e4m3 values are exact in float32; two bytes per conversion
+    const uint32_t *wa = &a.x, *wb = &b.x, *wc = &cc.x, *wd = &d.x;
+    uint32_t *wr = &r.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // means of e4m3 values stay in range: no clamp needed
+      const auto la = __builtin_amdgcn_cvt_pk_f32_fp8((int)wa[k], false), lb = __builtin_amdgcn_cvt_pk_f32_fp8((int)wb[k], false);
+      const auto lc = __builtin_amdgcn_cvt_pk_f32_fp8((int)wc[k], false), ld = __builtin_amdgcn_cvt_pk_f32_fp8((int)wd[k], false);
+      const auto ha = __builtin_amdgcn_cvt_pk_f32_fp8((int)wa[k], true), hb = __builtin_amdgcn_cvt_pk_f32_fp8((int)wb[k], true);
+      const auto hc = __builtin_amdgcn_cvt_pk_f32_fp8((int)wc[k], true), hd = __builtin_amdgcn_cvt_pk_f32_fp8((int)wd[k], true);
+      int o = __builtin_amdgcn_cvt_pk_fp8_f32((la[0] + lb[0] + lc[0] + ld[0]) * 0.25f,
+                                              (la[1] + lb[1] + lc[1] + ld[1]) * 0.25f, 0, false);
+      o = __builtin_amdgcn_cvt_pk_fp8_f32((ha[0] + hb[0] + hc[0] + hd[0]) * 0.25f,
+                                          (ha[1] + hb[1] + hc[1] + hd[1]) * 0.25f, o, true);
+      wr[k] = (uint32_t)o;
+    }
+    return r;
+  }
   const T *ta = reinterpret_cast<const T *>(&a), *tb = reinterpret_cast<const T *>(&b);
   const T *tc = reinterpret_cast<const T *>(&cc), *td = reinterpret_cast<const T *>(&d);
-  uint4 r;
   T *tr = reinterpret_cast<T *>(&r);
 #pragma unroll
   for (int i = 0; i < VEC; ++i)
@@ -811,7 +839,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         double act;
         if constexpr (P::Q8) {
           v0 = acc[mi][0][r] * ws + bn;
-          act = (double)(e4m3_dec(e4m3_enc((v0 > (AS)0 ? v0 : (AS)0) * a.oinv)) * a.asc);
+          act = (double)(e4m3_dec_d(e4m3_enc_d((v0 > (AS)0 ? v0 : (AS)0) * a.oinv)) * a.asc);
         } else {
           v0 = acc[mi][0][r] + bn;
           act = to_d<T>(from_d<T>((double)(v0 > (AS)0 ? v0 : (AS)0)));
@@ -850,7 +878,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         const int m = wave * 16 * MW + mi * 16 + P::row(lg, r);
         if constexpr (P::Q8) {
           const AS v = acc[mi][ni][r] * ws + bn;
-          ol[m * BN + n] = e4m3_enc((v > (AS)0 ? v : (AS)0) * a.oinv);
+          ol[m * BN + n] = e4m3_enc_d((v > (AS)0 ? v : (AS)0) * a.oinv);
         } else {
           const AS v = acc[mi][ni][r] + bn;
           ol[m * BN + n] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));

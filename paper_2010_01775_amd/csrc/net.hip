@@ -480,7 +480,9 @@ struct F32P {
   using Acc = f64x4;
   static constexpr bool F64 = true, Q8 = false;
   static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, KCP = 0, MAX_TILES = 8;
-  static constexpr int SB = 1;  // matrix-bound: keep registers for occupancy
+  // global loads in flight per thread while staging (LDS, not registers,
+  // bounds this kernel's occupancy)
+  static constexpr int SB = 8, SBP = 4;
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
 };
 // 8-bit and 16-bit traits: a lane's A or B fragment is 8 consecutive K
@@ -493,7 +495,7 @@ struct BF16P {
   using Frag = bf16x8;
   static constexpr bool F64 = false, Q8 = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
-  static constexpr int SB = 4;
+  static constexpr int SB = 4, SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
@@ -507,7 +509,7 @@ struct FP8P {
   using Frag = fp8x8;
   static constexpr bool F64 = false, Q8 = true;
   static constexpr int KC = KC8, VEC = 16, PSTR = KC + 16, KCP = KC + 16, MAX_TILES = 16;
-  static constexpr int SB = 4;
+  static constexpr int SB = 4, SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
 };
@@ -555,35 +557,21 @@ __device__ __forceinline__ const uint4 *vec_ptr(const Src &s, int leaf, int y, i
   return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) + (((size_t)leaf * H + y) * W + x) * s.C0 + c);
 }
 
-// 16 bytes of VEC channels starting at c, as raw bits.
+// Address of the top-left input of the 2x2 pooling window of output pixel
+// (y, x), channels c..c+VEC-1, or nullptr where the channels are padding.
 template <class P>
-__device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, int c, int H, int W) {
+__device__ __forceinline__ const typename P::T *pool_ptr(const Src &s, int leaf, int y, int x, int c, int H,
+                                                         int W) {
+  using T = typename P::T;
+  if (c >= s.C0) return nullptr;
+  return static_cast<const T *>(s.s0) + (((size_t)leaf * 2 * H + 2 * y) * (2 * W) + 2 * x) * s.C0 + c;
+}
+
+// Mean of four 16-byte pieces (the pooling window), rounded to storage.
+template <class P>
+__device__ __forceinline__ uint4 pool_combine(const uint4 &a, const uint4 &b, const uint4 &cc, const uint4 &d) {
   using T = typename P::T;
   constexpr int VEC = P::VEC;
-  uint4 z = make_uint4(0, 0, 0, 0);
-  if (s.mode == SRC_PLAIN) {
-    if (c >= s.C0) return z;
-    return *reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) +
-                                            (((size_t)leaf * H + y) * W + x) * s.C0 + c);
-  }
-  if (s.mode == SRC_UPCAT) {
-    if (c < s.C0)
-      return *reinterpret_cast<const uint4 *>(
-          static_cast<const T *>(s.s0) + (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c);
-    if (c - s.C0 < s.C1)
-      return *reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s1) +
-                                              (((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0));
-    return z;
-  }
-  // SRC_POOL
-  if (c >= s.C0) return z;
-  const int W2 = 2 * W;
-  const T *p = static_cast<const T *>(s.s0) + (((size_t)leaf * 2 * H + 2 * y) * W2 + 2 * x) * s.C0 + c;
-  const size_t dr = (size_t)W2 * s.C0;
-  const uint4 a = *reinterpret_cast<const uint4 *>(p);
-  const uint4 b = *reinterpret_cast<const uint4 *>(p + s.C0);
-  const uint4 cc = *reinterpret_cast<const uint4 *>(p + dr);
-  const uint4 d = *reinterpret_cast<const uint4 *>(p + dr + s.C0);
   uint4 r;
   if constexpr (sizeof(T) == 1) {
     // sums of four e4m3 values are exact in float32; two bytes per conversion
@@ -618,7 +606,7 @@ __device__ __forceinline__ uint4 load_vec(const Src &s, int leaf, int y, int x, 
 // channels.  A tile is TR rows x TW columns of one leaf, or TL whole leaves
 // when a map has fewer than BM pixels (the weights staged for a chunk are
 // then shared by TL leaves).
-template <class P, int MW, int NW>
+template <class P, int MW, int NW, bool POOLED>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
   using AccV = typename P::Acc;
@@ -668,15 +656,40 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     const int c0 = ch * KC;
     // input patch with halo: batches of SB loads per thread, then the
     // stores; pooled inputs (four loads per piece) go one piece at a time
-    if (a.src.mode == SRC_POOL) {
-      for (int it = tid; it < items; it += 256) {
-        const int pp = it / G, g = it - pp * G;
-        const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
-        const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-        const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) v = load_vec<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
-        *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v;
+    if constexpr (POOLED) {
+      constexpr int SBP = P::SBP;  // pooling windows (four loads each) in flight per thread
+      const size_t dr = (size_t)2 * W * a.src.C0;
+      for (int base = 0; base < items; base += 256 * SBP) {
+        uint4 q[SBP][4];
+#pragma unroll
+        for (int k = 0; k < SBP; ++k) {
+          const int it = base + k * 256 + tid;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) q[k][j] = make_uint4(0, 0, 0, 0);
+          if (it < items) {
+            const int pp = it / G, g = it - pp * G;
+            const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+            const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+            const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
+            if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
+              const T *p = pool_ptr<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
+              if (p) {
+                q[k][0] = *reinterpret_cast<const uint4 *>(p);
+                q[k][1] = *reinterpret_cast<const uint4 *>(p + a.src.C0);
+                q[k][2] = *reinterpret_cast<const uint4 *>(p + dr);
+                q[k][3] = *reinterpret_cast<const uint4 *>(p + dr + a.src.C0);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < SBP; ++k) {
+          const int it = base + k * 256 + tid;
+          if (it < items) {
+            const int pp = it / G, g = it - pp * G;
+            *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = pool_combine<P>(q[k][0], q[k][1], q[k][2], q[k][3]);
+          }
+        }
       }
     } else {
       for (int base = 0; base < items; base += 256 * SB) {
@@ -716,6 +729,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
           const int it = base + k * 256 + tid;
+          v[k] = make_uint4(0, 0, 0, 0);
           if (it < WITEMS) {
             const int row = it / R4, c4 = it - row * R4;
             v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * BN + c4 * 4);
@@ -945,17 +959,23 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
   return false;
 }
 
-template <class P, int MW, int NW>
-hipError_t launch_mfma_t(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
+template <class P, int MW, int NW, bool POOLED>
+hipError_t launch_mfma_k(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW>,
+    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW, POOLED>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW>), dim3(tiles), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW, POOLED>), dim3(tiles), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+template <class P, int MW, int NW>
+hipError_t launch_mfma_t(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
+  if (a.src.mode == SRC_POOL) return launch_mfma_k<P, MW, NW, true>(a, lds, tiles, s);
+  return launch_mfma_k<P, MW, NW, false>(a, lds, tiles, s);
 }
 
 template <class P>

@@ -480,9 +480,12 @@ struct F32P {
   using Acc = f64x4;
   static constexpr bool F64 = true, Q8 = false;
   static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, KCP = 0, MAX_TILES = 8;
-  // global loads in flight per thread while staging (LDS, not registers,
-  // bounds this kernel's occupancy)
-  static constexpr int SB = 8, SBP = 4;
+  // global loads in flight per thread while staging
+  static constexpr int SB = 4, SBP = 2;
+  // B fragments straight from the packed weights in global memory (L2/L1
+  // resident, shared by every workgroup), one tap ahead in registers; the
+  // LDS then holds the patch only, which leaves room for more workgroups
+  static constexpr bool WGLB = true;
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
 };
 // 8-bit and 16-bit traits: a lane's A or B fragment is 8 consecutive K
@@ -493,7 +496,7 @@ struct BF16P {
   using WT = uint16_t;
   using Acc = f32x4;
   using Frag = bf16x8;
-  static constexpr bool F64 = false, Q8 = false;
+  static constexpr bool F64 = false, Q8 = false, WGLB = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
   static constexpr int SB = 4, SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
@@ -507,7 +510,7 @@ struct FP8P {
   using WT = uint8_t;
   using Acc = f32x4;
   using Frag = fp8x8;
-  static constexpr bool F64 = false, Q8 = true;
+  static constexpr bool F64 = false, Q8 = true, WGLB = false;
   static constexpr int KC = KC8, VEC = 16, PSTR = KC + 16, KCP = KC + 16, MAX_TILES = 16;
   static constexpr int SB = 4, SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
@@ -616,6 +619,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   constexpr int BN = 16 * NW;
   using WT = typename P::WT;
   constexpr bool IS_F32 = P::F64;                // FP32 weights, FP64 activations and sums
+  constexpr bool WGLB = P::WGLB;                 // B fragments from global memory
   constexpr bool TWO_TAP = !IS_F32 && KC == 16;  // K slice = 2 taps x 16 channels
   constexpr int NTAPW = TWO_TAP ? 10 : 9;        // weight taps in LDS (10th = zeros)
   // FP32 B tile: [tap][kc][BNP], row stride chosen so the four k-rows a
@@ -721,7 +725,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     }
     // weights of this chunk
     const WT *wg = static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN;
-    if (IS_F32) {
+    if constexpr (WGLB) {
+    } else if (IS_F32) {
       constexpr int R4 = BN / 4;  // float4 per row
       constexpr int WITEMS = 9 * KC * R4;
       for (int base = 0; base < WITEMS; base += 256 * SB) {
@@ -770,9 +775,26 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     }
     __syncthreads();
+    // WGLB: this lane's B values of a tap, [k step][n tile]
+    float wcur[WGLB ? KC / 4 : 1][WGLB ? NW : 1], wnxt[WGLB ? KC / 4 : 1][WGLB ? NW : 1];
+    if constexpr (WGLB) {
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+        for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wg[(ks * 4 + lg) * BN + ni * 16 + lr];
+    }
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int toff = (tap / 3) * PW + (tap % 3);
+      if constexpr (WGLB) {
+        if (tap < 8) {
+#pragma unroll
+          for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+            for (int ni = 0; ni < NW; ++ni)
+              wnxt[ks][ni] = wg[((tap + 1) * KC + ks * 4 + lg) * BN + ni * 16 + lr];
+        }
+      }
       if constexpr (IS_F32) {
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ++ks) {
@@ -782,7 +804,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
             av[mi] = (double)patch[(bp[mi] + toff) * PSTR + ks * 4 + lg];
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni)
-            bv[ni] = (double)wl[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
+            bv[ni] = WGLB ? (double)wcur[WGLB ? ks : 0][WGLB ? ni : 0]
+                          : (double)wl[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
@@ -821,6 +844,12 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(av[mi], bv[ni], acc[mi][ni]);
+      }
+      if constexpr (WGLB) {
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wnxt[ks][ni];
       }
     }
     __syncthreads();
@@ -923,7 +952,7 @@ size_t conv_lds_bytes(const Tiling &t) {
   const size_t patch = npg_align((size_t)t.TL * (t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
   size_t wts;
   using WT = typename P::WT;
-  if (P::F64) wts = (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
+  if (P::F64) wts = P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
   else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
   const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
   return std::max(patch + wts, epi);

@@ -110,6 +110,9 @@ void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak);
  *                  non-default stream and replays it afterwards (default 0)
  *   "chunk_leaves" leaves per network chunk; 0 = autotuned or 1024
  *   "force_direct" 1: direct convolutions only (testing; default 0)
+ *   "fuse_first"   0: store the first layer's activations instead of
+ *                  computing them inside the second layer's input staging
+ *                  (default 1; the results are identical)
  * NPG_E_ARG for an unknown name or a negative value. */
 int npg_set_option(npg_ctx *ctx, const char *name, int64_t value);
 

@@ -540,6 +540,11 @@ struct ConvArgs {
   const float *wsc;      // FP8: per-output-channel weight scales
   float oinv, asc;       // FP8: output quantisation multiplier (1/asc) and unit value
   void *out;
+  // first layer fused into the patch (staging mode 2): its weights [16][9],
+  // biases [16] and FP8 output quantisation multiplier; src is the energy
+  const float *w0, *b0;
+  float oinv0;
+  int wbytes;            // LDS bytes of the weight tile (the energy tile follows it)
 };
 
 // Address of the 16 bytes of VEC channels at c of a plain or concatenated
@@ -609,7 +614,10 @@ __device__ __forceinline__ uint4 pool_combine(const uint4 &a, const uint4 &b, co
 // channels.  A tile is TR rows x TW columns of one leaf, or TL whole leaves
 // when a map has fewer than BM pixels (the weights staged for a chunk are
 // then shared by TL leaves).
-template <class P, int MW, int NW, bool POOLED>
+// Staging modes: 0 plain or upsampled+concatenated input, 1 2x2-pooled
+// input, 2 the first layer (one input channel, 16 outputs, ReLU) computed
+// into the patch from the energy map, as conv_first_kernel would store it.
+template <class P, int MW, int NW, int MODE>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
   using AccV = typename P::Acc;
@@ -660,7 +668,54 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     const int c0 = ch * KC;
     // input patch with halo: batches of SB loads per thread, then the
     // stores; pooled inputs (four loads per piece) go one piece at a time
-    if constexpr (POOLED) {
+    if constexpr (MODE == 2) {
+      // normalised energy x = HW*E/total (float32, zero outside the map) on
+      // the patch plus one more pixel of border, then the first layer's 16
+      // outputs per patch pixel (zero where the pixel is outside the map:
+      // the second layer's zero padding)
+      using A0 = std::conditional_t<P::F64, double, float>;
+      const int EW = TW + 4, EH = TR + 4;
+      float *xt = reinterpret_cast<float *>(smem + npg_align(patch_bytes + (size_t)a.wbytes, 16));
+      const int ne = TL * EH * EW;
+      const double hw = (double)H * (double)W;
+      for (int i = tid; i < ne; i += 256) {
+        const int ls = i / (EH * EW), r = i - ls * EH * EW;
+        const int ey = r / EW, ex = r - ey * EW;
+        const int y = ty0 - 2 + ey, x = tx0 - 2 + ex, leaf = leaf0 + ls;
+        float v = 0.0f;
+        if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
+          const double tl = a.src.tot[leaf];
+          if (tl > 0.0)
+            v = (float)(hw * (double)static_cast<const uint64_t *>(a.src.s0)[((size_t)leaf * H + y) * W + x] / tl);
+        }
+        xt[i] = v;
+      }
+      __syncthreads();
+      const int np = TL * PH * PW;
+      for (int pp = tid; pp < np; pp += 256) {
+        const int ls = pp / (PH * PW), r = pp - ls * PH * PW;
+        const int py = r / PW, px = r - py * PW;
+        const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
+        T *dst = patch + pp * PSTR;
+        if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
+          const float *xp = xt + ls * EH * EW + py * EW + px;
+          A0 xv[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) xv[k] = (A0)xp[(k / 3) * EW + k % 3];
+#pragma unroll
+          for (int c = 0; c < KC; ++c) {
+            A0 acc0 = (A0)a.b0[c];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc0 = fma((A0)a.w0[c * 9 + k], xv[k], acc0);
+            const A0 rl = acc0 > (A0)0 ? acc0 : (A0)0;
+            dst[c] = from_d<T>(sizeof(T) == 1 ? (double)(rl * (A0)a.oinv0) : (double)rl);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < KC; ++c) dst[c] = from_d<T>(0.0);
+        }
+      }
+    } else if constexpr (MODE == 1) {
       constexpr int SBP = P::SBP;  // pooling windows (four loads each) in flight per thread
       const size_t dr = (size_t)2 * W * a.src.C0;
       for (int base = 0; base < items; base += 256 * SBP) {
@@ -945,8 +1000,18 @@ struct Tiling {
   int MW, NW, TW, TR, TL;
 };
 
+// Bytes of the weight tile a workgroup stages in LDS.
 template <class P>
-size_t conv_lds_bytes(const Tiling &t) {
+size_t conv_wts_bytes(const Tiling &t) {
+  using WT = typename P::WT;
+  const int BN = 16 * t.NW;
+  if (P::F64) return P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
+  return (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
+}
+
+// first: the energy tile of a fused first layer follows the weights
+template <class P>
+size_t conv_lds_bytes(const Tiling &t, bool first = false) {
   using T = typename P::T;
   const int BN = 16 * t.NW;
   const size_t patch = npg_align((size_t)t.TL * (t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
@@ -955,7 +1020,10 @@ size_t conv_lds_bytes(const Tiling &t) {
   if (P::F64) wts = P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
   else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
   const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
-  return std::max(patch + wts, epi);
+  const size_t xt = first ? npg_align(patch + wts, 16) - patch - wts +
+                                (size_t)t.TL * (t.TR + 4) * (t.TW + 4) * sizeof(float)
+                          : 0;
+  return std::max(patch + wts + xt, epi);
 }
 
 // Largest pixel tile (64*MW pixels) whose accumulators and LDS fit; maps
@@ -988,28 +1056,36 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
   return false;
 }
 
-template <class P, int MW, int NW, bool POOLED>
+template <class P, int MW, int NW, int MODE>
 hipError_t launch_mfma_k(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW, POOLED>,
+    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW, POOLED>), dim3(tiles), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW, MODE>), dim3(tiles), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
 template <class P, int MW, int NW>
 hipError_t launch_mfma_t(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
-  if (a.src.mode == SRC_POOL) return launch_mfma_k<P, MW, NW, true>(a, lds, tiles, s);
-  return launch_mfma_k<P, MW, NW, false>(a, lds, tiles, s);
+  if (a.src.mode == SRC_POOL) return launch_mfma_k<P, MW, NW, 1>(a, lds, tiles, s);
+  if (a.src.mode == SRC_ENERGY) {
+    if constexpr (NW == 1 && P::KC == 16) return launch_mfma_k<P, MW, NW, 2>(a, lds, tiles, s);
+    return hipErrorInvalidValue;
+  }
+  return launch_mfma_k<P, MW, NW, 0>(a, lds, tiles, s);
 }
 
 template <class P>
-hipError_t launch_mfma(const ConvArgs &a, const Tiling &t, unsigned tiles, hipStream_t s) {
-  const size_t lds = conv_lds_bytes<P>(t);
+hipError_t launch_mfma(const ConvArgs &a0, const Tiling &t, unsigned tiles, hipStream_t s) {
+  const bool first = a0.src.mode == SRC_ENERGY;
+  const size_t lds = conv_lds_bytes<P>(t, first);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  ConvArgs a = a0;
+  a.wbytes = (int)conv_wts_bytes<P>(t);
   switch (t.NW * 10 + t.MW) {
     case 11: return launch_mfma_t<P, 1, 1>(a, lds, tiles, s);
     case 12: return launch_mfma_t<P, 2, 1>(a, lds, tiles, s);
@@ -1042,6 +1118,7 @@ struct Runner {
   int mw_all = 4;                            // cap for every call (autotuner probes)
   std::vector<hipEvent_t> *ev = nullptr;     // per-call begin/end events (autotuner)
   int call = 0;                              // conv call index within a chunk
+  int fuse_first = 1;                        // first layer inside the second layer's staging
   unsigned *amax = nullptr;                  // calibration: per-call max of the stored output
                                              // (float bits); the head is then not fused
 
@@ -1066,6 +1143,69 @@ struct Runner {
     if (force_direct || y.k != 3 || src.mode == SRC_ENERGY || y.cin % v) return false;
     if (src.mode == SRC_UPCAT && (src.C0 % v || src.C1 % v)) return false;
     return tiling(y, H, W, t);
+  }
+
+  // The first layer (energy -> 16 channels, 3x3, ReLU) can be computed inside
+  // the second layer's patch staging (16 -> 16, 3x3, ReLU) when the tiles fit.
+  bool first_fusable(const LayerDev &l0, const LayerDev &l1, int H, int W, Tiling *t) const {
+    if (force_direct || amax || !fuse_first) return false;
+    if (l0.k != 3 || l0.cin != 1 || l0.cout != 16 || l1.k != 3 || l1.cin != 16 || l1.cout != 16) return false;
+    if (!tiling(l1, H, W, t)) return false;
+    const size_t lds = prec == NPG_FP32  ? conv_lds_bytes<F32P>(*t, true)
+                       : prec == NPG_FP8 ? conv_lds_bytes<FP8S>(*t, true)
+                                         : conv_lds_bytes<BF16S>(*t, true);
+    return lds <= 160 * 1024;
+  }
+
+  int conv_first_fused(const LayerDev &l0, const LayerDev &l1, const Src &energy, int Lc, int H, int W,
+                       void *out) {
+    if (ev) {
+      if (hipEventRecord((*ev)[2 * call], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
+    }
+    Tiling t;
+    if (!first_fusable(l0, l1, H, W, &t)) return npg_fail(ctx, NPG_E_ARG, "internal: first layer not fusable");
+    ConvArgs a{};
+    a.src = energy;
+    a.Cin = 16;
+    a.Cout = 16;
+    a.H = H;
+    a.W = W;
+    a.TW = t.TW;
+    a.TR = t.TR;
+    a.TL = t.TL;
+    a.Lc = Lc;
+    a.fPW = make_fastdiv((uint32_t)(t.TW + 2));
+    a.fPP = make_fastdiv((uint32_t)((t.TW + 2) * (t.TR + 2)));
+    a.tiles_x = W / t.TW;
+    a.tiles_per_leaf = (H / t.TR) * a.tiles_x;
+    a.nchunk = 1;
+    a.bias = l1.b;
+    a.head_w = nullptr;
+    a.wsc = l1.wsc8;
+    a.oinv = 1.0f / l1.a8;
+    a.asc = l1.a8;
+    a.w0 = l0.w;
+    a.b0 = l0.b;
+    a.oinv0 = prec == NPG_FP8 ? 1.0f / l0.a8 : 1.0f;
+    a.out = out;
+    const unsigned tiles = (unsigned)((Lc + t.TL - 1) / t.TL) * a.tiles_per_leaf;
+    hipError_t e;
+    if (prec == NPG_FP32) {
+      a.wpk = l1.pk32;
+      e = launch_mfma<F32P>(a, t, tiles, s);
+    } else if (prec == NPG_FP8) {
+      a.wpk = l1.pk8s;
+      e = launch_mfma<FP8S>(a, t, tiles, s);
+    } else {
+      a.wpk = l1.pk16s;
+      e = launch_mfma<BF16S>(a, t, tiles, s);
+    }
+    if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "fused first conv launch: %s", hipGetErrorString(e));
+    if (ev) {
+      if (hipEventRecord((*ev)[2 * call + 1], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
+    }
+    ++call;
+    return NPG_OK;
   }
 
   int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
@@ -1257,7 +1397,15 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
     const int n = (int)m->layer.size();
     Src cur = in;
     char *bufs[2] = {B.tA, B.tB};
-    for (int i = 0; i < n; ++i) {
+    int i0 = 0;
+    Tiling tf;
+    if (n > 2 && R.first_fusable(m->layer[0], m->layer[1], H, W, &tf)) {
+      rc = R.conv_first_fused(m->layer[0], m->layer[1], in, Lc, H, W, bufs[1]);
+      if (rc) return rc;
+      cur = plain(bufs[1], 16, dq(m->layer[1]));
+      i0 = 2;
+    }
+    for (int i = i0; i < n; ++i) {
       const LayerDev &y = m->layer[i];
       const bool last = i == n - 1;
       void *dst = last ? (void *)dens : (void *)bufs[i & 1];
@@ -1280,11 +1428,17 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
       w /= 2;
       sa = pooled(prev, prevC, prevQ);
     }
-    rc = R.conv(la, sa, Lc, h, w, B.tA, nullptr, ACT_RELU);
-    if (rc) return rc;
     void *ob = d < D - 1 ? (void *)B.skip[d] : (void *)B.tB;
-    rc = R.conv(lb, plain(B.tA, la.cout, dq(la)), Lc, h, w, ob, nullptr, ACT_RELU);
-    if (rc) return rc;
+    Tiling tf;
+    if (d == 0 && R.first_fusable(la, lb, h, w, &tf)) {
+      rc = R.conv_first_fused(la, lb, sa, Lc, h, w, ob);
+      if (rc) return rc;
+    } else {
+      rc = R.conv(la, sa, Lc, h, w, B.tA, nullptr, ACT_RELU);
+      if (rc) return rc;
+      rc = R.conv(lb, plain(B.tA, la.cout, dq(la)), Lc, h, w, ob, nullptr, ACT_RELU);
+      if (rc) return rc;
+    }
     prev = ob;
     prevC = lb.cout;
     prevQ = dq(lb);
@@ -1353,6 +1507,7 @@ std::string tune_key(const npg_model *m, npg_precision p, int H, int W) {
 Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStream_t s) {
   Runner R{ctx, m, prec, s, prec == NPG_FP32 ? sizeof(double) : prec == NPG_FP8 ? (size_t)1 : (size_t)2};
   R.force_direct = (int)ctx->opt("force_direct", 0);
+  R.fuse_first = ctx->opt("fuse_first", 1) ? 1 : 0;
   return R;
 }
 

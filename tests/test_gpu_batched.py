@@ -157,3 +157,27 @@ def test_clustered_full_size_sampled_leaves(ctx, npg, orc, clustered):
     assert rel.max() < 1e-5
     assert small_err.size == 0 or small_err.max() < 1e-5
     m.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("H,L,arch", [(64, 37, "unet"), (16, 21, "unet"), (128, 5, "unet"), (8, 13, "unet"),
+                                      (32, 9, "cnn")])
+def test_fused_first_layer_equals_separate(ctx, npg, prec, H, L, arch):
+    """The first layer computed inside the second layer's patch staging gives
+    the same bits as the stored first-layer activations."""
+    model = synth.unet_model(21, random_bias=True) if arch == "unet" else synth.cnn_model(22)
+    m = npg.Model(ctx, model)
+    b = synth.uniform_batch(seed=31 + H, L=L, per_leaf=3000, H=H, W=H, n_queries=8, model=b"")
+    e, _ = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), H, H, want_count=False)
+    e[L // 2].zero_()                                # an empty leaf
+    if prec == "fp8":
+        m.calibrate_fp8(e)
+    ctx.set_option("fuse_first", 0)
+    try:
+        ref = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    finally:
+        ctx.set_option("fuse_first", 1)
+    got = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    assert npg.sync_status(ctx) == 0
+    assert torch.equal(ref, got)
+    m.free()

@@ -233,7 +233,7 @@ int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *model, const float *dir
                           double *total_dev, void *stream);
 
 /* Autotuner: times each convolution of the network on `probe_leaves`
- * synthetic leaves of H x W under each pixel-tile size (64, 128, 256 pixels
+ * synthetic leaves of H x W under each pixel-tile size (64, 128, 256, 512 pixels
  * per workgroup) and then the leaf-chunk size, and keeps the fastest choices
  * in ctx for (model, precision, H, W); later reconstruct calls of that shape
  * use them.  The choice never changes a result (every output sums its terms

@@ -498,7 +498,7 @@ struct BF16P {
   using Frag = bf16x8;
   static constexpr bool F64 = false, Q8 = false, WGLB = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 2;
+  static constexpr int SB = 4, SBP = 1;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
@@ -666,6 +666,24 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   const int items = TL * PH * PW * G;
   for (int ch = 0; ch < a.nchunk; ++ch) {
     const int c0 = ch * KC;
+    // 8/16-bit weights: the first batch is loaded before the patch so that
+    // both arrive in one global round trip
+    const WT *wg = static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN;
+    constexpr int WV = 16 / (int)sizeof(WT);  // weights per 16-byte piece
+    constexpr int R8 = IS_F32 ? 1 : KC / WV;
+    constexpr int WITEMS8 = NTAPW * BN * R8;
+    uint4 wv[IS_F32 ? 1 : SB];
+    if constexpr (!IS_F32) {
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int it = k * 256 + tid;
+        wv[k] = make_uint4(0, 0, 0, 0);
+        if (it < WITEMS8) {
+          const int row = it / R8, c8 = it - row * R8;
+          if (row < 9 * BN) wv[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * WV);
+        }
+      }
+    }
     // input patch with halo: batches of SB loads per thread, then the
     // stores; pooled inputs (four loads per piece) go one piece at a time
     if constexpr (MODE == 2) {
@@ -696,7 +714,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         const int ls = pp / (PH * PW), r = pp - ls * PH * PW;
         const int py = r / PW, px = r - py * PW;
         const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
-        T *dst = patch + pp * PSTR;
+        T res[KC];  // the pixel's KC channels, written as 16-byte pieces
         if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
           const float *xp = xt + ls * EH * EW + py * EW + px;
           A0 xv[9];
@@ -708,12 +726,15 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc0 = fma((A0)a.w0[c * 9 + k], xv[k], acc0);
             const A0 rl = acc0 > (A0)0 ? acc0 : (A0)0;
-            dst[c] = from_d<T>(sizeof(T) == 1 ? (double)(rl * (A0)a.oinv0) : (double)rl);
+            res[c] = from_d<T>(sizeof(T) == 1 ? (double)(rl * (A0)a.oinv0) : (double)rl);
           }
         } else {
 #pragma unroll
-          for (int c = 0; c < KC; ++c) dst[c] = from_d<T>(0.0);
+          for (int c = 0; c < KC; ++c) res[c] = from_d<T>(0.0);
         }
+#pragma unroll
+        for (int v = 0; v < KC * (int)sizeof(T) / 16; ++v)
+          reinterpret_cast<uint4 *>(patch + pp * PSTR)[v] = reinterpret_cast<const uint4 *>(res)[v];
       }
     } else if constexpr (MODE == 1) {
       constexpr int SBP = P::SBP;  // pooling windows (four loads each) in flight per thread
@@ -779,7 +800,6 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     }
     // weights of this chunk
-    const WT *wg = static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN;
     if constexpr (WGLB) {
     } else if (IS_F32) {
       constexpr int R4 = BN / 4;  // float4 per row
@@ -805,10 +825,16 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
       }
     } else {
-      constexpr int WV = 16 / (int)sizeof(WT);  // weights per 16-byte piece
-      constexpr int R8 = KC / WV;
-      constexpr int WITEMS = NTAPW * BN * R8;
-      for (int base = 0; base < WITEMS; base += 256 * SB) {
+      constexpr int WITEMS = WITEMS8;
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int it = k * 256 + tid;
+        if (it < WITEMS) {
+          const int row = it / R8, c8 = it - row * R8;
+          *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * WV) = wv[k];
+        }
+      }
+      for (int base = 256 * SB; base < WITEMS; base += 256 * SB) {
         uint4 v[SB];
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
@@ -879,7 +905,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(av[mi], bv[ni], acc[mi][ni]);
+          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
       } else {
         if (tap & 1) continue;  // taps handled in pairs (tap, tap + 1)
         // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
@@ -898,7 +924,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(av[mi], bv[ni], acc[mi][ni]);
+          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
       }
       if constexpr (WGLB) {
 #pragma unroll
@@ -918,6 +944,96 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     if (leaf0 + ls >= a.Lc) return -1;
     return ((long)(leaf0 + ls) * H + ty0 + rem / TW) * W + tx0 + rem % TW;
   };
+  if constexpr (!P::F64) {
+    // 8/16-bit tiles hold the transposed product (weights as the A operand):
+    // lane (lr, lg) has channels 16 ni + 4 lg + r, r = 0..3, of pixel
+    // 16 mi + lr of its wavefront's block
+    if (a.head_w) {
+      float *dl = reinterpret_cast<float *>(smem);  // [BM] densities
+      AS bn[4], hw[4], ws[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        bn[r] = (AS)a.bias[4 * lg + r];
+        hw[r] = (AS)a.head_w[4 * lg + r];
+        ws[r] = (AS)1;
+        if constexpr (P::Q8) ws[r] = (AS)a.wsc[4 * lg + r];
+      }
+      AS mine = 0;
+#pragma unroll
+      for (int mi = 0; mi < MW; ++mi) {
+        AS v = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // the value the unfused path would store (type T) feeds the head
+          AS act;
+          if constexpr (P::Q8) {
+            const AS v0 = acc[mi][0][r] * ws[r] + bn[r];
+            act = (AS)(e4m3_dec_d(e4m3_enc_d((v0 > (AS)0 ? v0 : (AS)0) * a.oinv)) * a.asc);
+          } else {
+            const AS v0 = acc[mi][0][r] + bn[r];
+            act = (AS)to_d<T>(from_d<T>((double)(v0 > (AS)0 ? v0 : (AS)0)));
+          }
+          v += act * hw[r];
+        }
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lg == mi) mine = v;
+      }
+      if (lg < MW) dl[wave * 16 * MW + lg * 16 + lr] = (float)softplus_f(mine + (AS)a.head_b);
+      __syncthreads();
+      // four consecutive tile pixels are contiguous in the output (TW >= 4)
+      for (int i = tid; i < BM / 4; i += 256) {
+        const long g = gpix(i * 4);
+        if (g >= 0)
+          *reinterpret_cast<float4 *>(static_cast<float *>(a.out) + g) = *reinterpret_cast<const float4 *>(dl + i * 4);
+      }
+      return;
+    }
+    T *ol = reinterpret_cast<T *>(smem);  // [BM][BN]
+#pragma unroll
+    for (int ni = 0; ni < NW; ++ni) {
+      AS bn[4], ws[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        bn[r] = (AS)a.bias[16 * ni + 4 * lg + r];
+        ws[r] = (AS)1;
+        if constexpr (P::Q8) ws[r] = (AS)a.wsc[16 * ni + 4 * lg + r];
+      }
+#pragma unroll
+      for (int mi = 0; mi < MW; ++mi) {
+        const int m = wave * 16 * MW + mi * 16 + lr;
+        T q[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if constexpr (P::Q8) {
+            const AS v = acc[mi][ni][r] * ws[r] + bn[r];
+            q[r] = e4m3_enc_d((v > (AS)0 ? v : (AS)0) * a.oinv);
+          } else {
+            const AS v = acc[mi][ni][r] + bn[r];
+            q[r] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));
+          }
+        }
+        T *o = ol + m * BN + 16 * ni + 4 * lg;  // four consecutive channels: one store
+        if constexpr (sizeof(T) == 2)
+          *reinterpret_cast<uint2 *>(o) = make_uint2((uint32_t)q[0] | ((uint32_t)q[1] << 16),
+                                                     (uint32_t)q[2] | ((uint32_t)q[3] << 16));
+        else
+          *reinterpret_cast<uint32_t *>(o) = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) |
+                                             ((uint32_t)q[3] << 24);
+      }
+    }
+    __syncthreads();
+    constexpr int PPR = BN * (int)sizeof(T) / 16;  // 16-byte pieces per pixel
+    T *out = static_cast<T *>(a.out);
+    for (int i = tid; i < BM * PPR; i += 256) {
+      const int m = i / PPR, pc = i - m * PPR;
+      const long g = gpix(m);
+      if (g >= 0)
+        *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) =
+            *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+    }
+    return;
+  }
   if (a.head_w) {
     float *dl = reinterpret_cast<float *>(smem);  // [BM] densities
     const AS bn = (AS)a.bias[lr];
@@ -1034,9 +1150,9 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
   const int NW = Cout / 16;
   if (NW > P::MAX_TILES) return false;
   const int HW = H * W;
-  for (int MW = 4; MW >= 1; MW >>= 1) {
+  for (int MW = 8; MW >= 1; MW >>= 1) {
     if (MW > mw_max) continue;
-    if (MW * NW > P::MAX_TILES) continue;
+    if (MW * NW > P::MAX_TILES || (MW == 8 && NW > 2)) continue;
     const int BM = 64 * MW;
     Tiling c{MW, NW, 0, 0, 1};
     if (BM <= HW) {
@@ -1098,6 +1214,10 @@ hipError_t launch_mfma(const ConvArgs &a0, const Tiling &t, unsigned tiles, hipS
     case 44: return launch_mfma_t<P, 4, 4>(a, lds, tiles, s);
     case 81: return launch_mfma_t<P, 1, 8>(a, lds, tiles, s);
     case 82: return launch_mfma_t<P, 2, 8>(a, lds, tiles, s);
+    case 18: return launch_mfma_t<P, 8, 1>(a, lds, tiles, s);
+    case 28:
+      if constexpr (P::MAX_TILES >= 16) return launch_mfma_t<P, 8, 2>(a, lds, tiles, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -1127,22 +1247,25 @@ struct Runner {
     if (mw_cap && call < (int)mw_cap->size()) c = std::min(c, (*mw_cap)[call]);
     return c;
   }
-  bool tiling(const LayerDev &y, int H, int W, Tiling *t) const {
-    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t, cap());
+  // mw_lim: 4 for a fused head (its epilogue keeps one pixel per lane of a
+  // 16-lane group, 4*MW <= 16)
+  bool tiling(const LayerDev &y, int H, int W, Tiling *t, int mw_lim = 8) const {
+    const int c = std::min(cap(), mw_lim);
+    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t, c);
     if (prec == NPG_FP8) {
-      if (y.cin % KC8 == 0) return pick_tiling<FP8P>(y.cout, H, W, t, cap());
-      return pick_tiling<FP8S>(y.cout, H, W, t, cap());
+      if (y.cin % KC8 == 0) return pick_tiling<FP8P>(y.cout, H, W, t, c);
+      return pick_tiling<FP8S>(y.cout, H, W, t, c);
     }
-    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t, cap());
-    return pick_tiling<BF16S>(y.cout, H, W, t, cap());
+    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t, c);
+    return pick_tiling<BF16S>(y.cout, H, W, t, c);
   }
   // channel granularity of the tiled kernel's 16-byte input loads
   int vec() const { return prec == NPG_FP32 ? 2 : prec == NPG_FP8 ? 16 : 8; }
-  bool mfma_fits(const LayerDev &y, const Src &src, int H, int W, Tiling *t) const {
+  bool mfma_fits(const LayerDev &y, const Src &src, int H, int W, Tiling *t, int mw_lim = 8) const {
     const int v = vec();
     if (force_direct || y.k != 3 || src.mode == SRC_ENERGY || y.cin % v) return false;
     if (src.mode == SRC_UPCAT && (src.C0 % v || src.C1 % v)) return false;
-    return tiling(y, H, W, t);
+    return tiling(y, H, W, t, mw_lim);
   }
 
   // The first layer (energy -> 16 channels, 3x3, ReLU) can be computed inside
@@ -1235,7 +1358,7 @@ struct Runner {
   int conv_impl(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
                 int act) {
     Tiling t;
-    const bool mfma_ok = act == ACT_RELU && mfma_fits(y, src, H, W, &t) && (!head || y.cout == 16);
+    const bool mfma_ok = act == ACT_RELU && mfma_fits(y, src, H, W, &t, head ? 4 : 8) && (!head || y.cout == 16);
     if (mfma_ok) {
       ConvArgs a;
       a.src = src;
@@ -1457,7 +1580,7 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
     if (d == 0) {
       const LayerDev &hd = m->layer[li];
       Tiling t;
-      const bool fuse = !R.amax && lb.cout == 16 && R.mfma_fits(lb, sb, h, w, &t);
+      const bool fuse = !R.amax && lb.cout == 16 && R.mfma_fits(lb, sb, h, w, &t, 4);
       if (fuse) {
         rc = R.conv(lb, sb, Lc, h, w, dens, &hd, ACT_RELU);
         if (rc) return rc;
@@ -1731,7 +1854,7 @@ int npg_run_desc_batch(npg_ctx *ctx, const npg_model *m, npg_precision prec, con
 }
 
 // -------------------------------------------------------------- autotune
-// Times every convolution of the network under each tile cap (64, 128, 256
+// Times every convolution of the network under each tile cap (64, 128, 256, 512
 // pixels per workgroup) on `probe` zero-energy leaves and keeps the fastest
 // per call, then times leaf-chunk sizes with those tiles.  Tile and chunk
 // choices do not change any result: each output sums its terms in the same
@@ -1767,11 +1890,11 @@ extern "C" int npg_autotune(npg_ctx *ctx, const npg_model *m, int H, int W, npg_
   const int ncall = R.call;
   std::vector<hipEvent_t> ev(2 * ncall);
   for (auto &e : ev) NPG_HIP_CHECK(ctx, hipEventCreate(&e));
-  const int caps[3] = {4, 2, 1};
+  const int caps[4] = {8, 4, 2, 1};
   std::vector<float> best(ncall, 1e30f);
   std::vector<int> pick(ncall, 4);
   int err = NPG_OK;
-  for (int ci = 0; ci < 3 && !err; ++ci) {
+  for (int ci = 0; ci < 4 && !err; ++ci) {
     R.mw_all = caps[ci];
     R.ev = nullptr;
     err = net_chunk(R, in, (int)probe, H, W, dens, B);  // warm-up

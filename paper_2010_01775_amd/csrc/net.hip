@@ -480,8 +480,9 @@ struct F32P {
   using Acc = f64x4;
   static constexpr bool F64 = true, Q8 = false;
   static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, KCP = 0, MAX_TILES = 8;
-  // global loads in flight per thread while staging
-  static constexpr int SB = 4, SBP = 2;
+  // global loads in flight per thread while staging: SB pieces (pooled: SBP
+  // windows; plain: SPX whole pixels of KC/VEC pieces)
+  static constexpr int SB = 4, SBP = 2, SPX = 1;
   // B fragments straight from the packed weights in global memory (L2/L1
   // resident, shared by every workgroup), one tap ahead in registers; the
   // LDS then holds the patch only, which leaves room for more workgroups
@@ -498,12 +499,12 @@ struct BF16P {
   using Frag = bf16x8;
   static constexpr bool F64 = false, Q8 = false, WGLB = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 1;
+  static constexpr int SB = 4, SBP = 1, SPX = 1;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 struct BF16S : BF16P {
-  static constexpr int KC = KC16S, PSTR = KC + 8, KCP = KC + 8;
+  static constexpr int KC = KC16S, PSTR = KC + 8, KCP = KC + 8, SPX = 2;
 };
 struct FP8P {
   using T = uint8_t;
@@ -512,12 +513,12 @@ struct FP8P {
   using Frag = fp8x8;
   static constexpr bool F64 = false, Q8 = true, WGLB = false;
   static constexpr int KC = KC8, VEC = 16, PSTR = KC + 16, KCP = KC + 16, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 2;
+  static constexpr int SB = 4, SBP = 2, SPX = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
 };
 struct FP8S : FP8P {
-  static constexpr int KC = KC8S, PSTR = KC + 32, KCP = KC + 32;
+  static constexpr int KC = KC8S, PSTR = KC + 32, KCP = KC + 32, SPX = 4;
 };
 
 // n / d for n, d < 2^16 as a multiply-high by m = ceil(2^32 / d).
@@ -772,29 +773,53 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
       }
     } else {
-      for (int base = 0; base < items; base += 256 * SB) {
-        uint4 v[SB];
+      // one address per patch pixel, then its G 16-byte pieces back to back
+      // (a chunk's channels come from one source: the concatenation boundary
+      // is a multiple of KC)
+      constexpr int SPX = P::SPX;  // pixels per thread per batch
+      const int npx = TL * PH * PW;
+      for (int base = 0; base < npx; base += 256 * SPX) {
+        uint4 v[SPX][G];
 #pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int it = base + k * 256 + tid;
-          v[k] = make_uint4(0, 0, 0, 0);
-          if (it < items) {
-            const int pp = it / G, g = it - pp * G;
+        for (int k = 0; k < SPX; ++k) {
+          const int pp = base + k * 256 + tid;
+#pragma unroll
+          for (int g = 0; g < G; ++g) v[k][g] = make_uint4(0, 0, 0, 0);
+          if (pp < npx) {
             const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
             const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
             const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
             if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
-              const uint4 *q = vec_ptr<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
-              if (q) v[k] = *q;
+              const T *q = nullptr;
+              int cleft = 0;  // channels of the source from c on
+              if (a.src.mode == SRC_UPCAT) {
+                if (c0 < a.src.C0) {
+                  q = static_cast<const T *>(a.src.s0) +
+                      (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * a.src.C0 + c0;
+                  cleft = a.src.C0 - c0;
+                } else if (c0 - a.src.C0 < a.src.C1) {
+                  q = static_cast<const T *>(a.src.s1) + (((size_t)leaf * H + y) * W + x) * a.src.C1 +
+                      (c0 - a.src.C0);
+                  cleft = a.src.C1 - (c0 - a.src.C0);
+                }
+              } else if (c0 < a.src.C0) {
+                q = static_cast<const T *>(a.src.s0) + (((size_t)leaf * H + y) * W + x) * a.src.C0 + c0;
+                cleft = a.src.C0 - c0;
+              }
+              if (q) {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                  if (g * VEC < cleft) v[k][g] = reinterpret_cast<const uint4 *>(q)[g];
+              }
             }
           }
         }
 #pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int it = base + k * 256 + tid;
-          if (it < items) {
-            const int pp = it / G, g = it - pp * G;
-            *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v[k];
+        for (int k = 0; k < SPX; ++k) {
+          const int pp = base + k * 256 + tid;
+          if (pp < npx) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v[k][g];
           }
         }
       }
@@ -1265,6 +1290,9 @@ struct Runner {
     const int v = vec();
     if (force_direct || y.k != 3 || src.mode == SRC_ENERGY || y.cin % v) return false;
     if (src.mode == SRC_UPCAT && (src.C0 % v || src.C1 % v)) return false;
+    // the tiled kernel takes each K chunk's channels from one source
+    const int kc = prec == NPG_FP32 ? KC32 : (y.cin % 32 == 0 ? 32 : 16);
+    if (src.mode == SRC_UPCAT && src.C0 % kc) return false;
     return tiling(y, H, W, t, mw_lim);
   }
 

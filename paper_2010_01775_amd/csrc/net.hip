@@ -722,12 +722,13 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
           for (int k = 0; k < 9; ++k) xv[k] = (A0)xp[(k / 3) * EW + k % 3];
 #pragma unroll
-          for (int c = 0; c < KC; ++c) {
+          for (int cc = 0; cc < KC; ++cc) {  // this chunk's channels c0 .. c0 + KC - 1
+            const int c = c0 + cc;
             A0 acc0 = (A0)a.b0[c];
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc0 = fma((A0)a.w0[c * 9 + k], xv[k], acc0);
             const A0 rl = acc0 > (A0)0 ? acc0 : (A0)0;
-            res[c] = from_d<T>(sizeof(T) == 1 ? (double)(rl * (A0)a.oinv0) : (double)rl);
+            res[cc] = from_d<T>(sizeof(T) == 1 ? (double)(rl * (A0)a.oinv0) : (double)rl);
           }
         } else {
 #pragma unroll
@@ -1214,7 +1215,7 @@ template <class P, int MW, int NW>
 hipError_t launch_mfma_t(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
   if (a.src.mode == SRC_POOL) return launch_mfma_k<P, MW, NW, 1>(a, lds, tiles, s);
   if (a.src.mode == SRC_ENERGY) {
-    if constexpr (NW == 1 && P::KC == 16) return launch_mfma_k<P, MW, NW, 2>(a, lds, tiles, s);
+    if constexpr (NW == 1 && P::KC <= 16 && 16 % P::KC == 0) return launch_mfma_k<P, MW, NW, 2>(a, lds, tiles, s);
     return hipErrorInvalidValue;
   }
   return launch_mfma_k<P, MW, NW, 0>(a, lds, tiles, s);
@@ -1329,7 +1330,7 @@ struct Runner {
     a.fPP = make_fastdiv((uint32_t)((t.TW + 2) * (t.TR + 2)));
     a.tiles_x = W / t.TW;
     a.tiles_per_leaf = (H / t.TR) * a.tiles_x;
-    a.nchunk = 1;
+    a.nchunk = prec == NPG_FP32 ? 16 / KC32 : 1;
     a.bias = l1.b;
     a.head_w = nullptr;
     a.wsc = l1.wsc8;

@@ -1,21 +1,51 @@
 // Guided direction sampling by table inversion, and pdf evaluation.
 //
-// One thread per query.  Row and column are found by a branch-free binary
-// search over the monotone float32 tables (exact comparisons), so a query
-// selects exactly the bin the definition names: the last entry <= u.
+// One thread per query.  Row and column are found by searches over the
+// monotone float32 tables with exact comparisons, so a query selects exactly
+// the bin the definition names: the last entry <= u.
 #include <math.h>
 
 #include "npg_internal.h"
 
 namespace {
 
-// largest i in [0, n-1] with t[i] <= u, for t[0] <= u, t non-decreasing,
-// n a power of two.
+// largest i in [0, n-1] with t[i] <= u, for t non-decreasing with
+// t[0] <= u < t[n].  The search starts at the entry a linear table would
+// hold u at, gallops outwards until u is bracketed and bisects the bracket:
+// for smooth tables the first probe and its neighbour share a cache line.
 __device__ __forceinline__ int last_le(const float *__restrict__ t, int n, float u) {
-  int i = 0;
-  for (int step = n >> 1; step > 0; step >>= 1)
-    if (t[i + step] <= u) i += step;
-  return i;
+  int g = (int)(u * (float)n);
+  g = g < n - 1 ? g : n - 1;
+  int lo, hi;  // t[lo] <= u < t[hi]
+  if (t[g] <= u) {
+    lo = g;
+    for (int step = 1;; step <<= 1) {
+      hi = lo + step;
+      if (hi >= n) {
+        hi = n;
+        break;
+      }
+      if (t[hi] > u) break;
+      lo = hi;
+    }
+  } else {
+    hi = g;
+    for (int step = 1;; step <<= 1) {
+      lo = hi - step;
+      if (lo <= 0) {
+        lo = 0;
+        break;
+      }
+      if (t[lo] <= u) break;
+      hi = lo;
+    }
+  }
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (t[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
 __global__ __launch_bounds__(256) void sample_kernel(

@@ -1182,8 +1182,18 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
     const int BM = 64 * MW;
     Tiling c{MW, NW, 0, 0, 1};
     if (BM <= HW) {
+      // the TR x TW shape (TW >= 8, a power of two like W and H) with the
+      // smallest halo patch (TR + 2) x (TW + 2): fewer bytes staged per pixel
       c.TW = std::min(W, BM);
       c.TR = BM / c.TW;
+      for (int tw = c.TW / 2; tw >= 8; tw /= 2) {
+        const int tr = BM / tw;
+        if (tr > H) break;
+        if ((tr + 2) * (tw + 2) < (c.TR + 2) * (c.TW + 2)) {
+          c.TW = tw;
+          c.TR = tr;
+        }
+      }
     } else if (BM % HW == 0 && BM / HW <= 8 && W >= 4) {
       c.TW = W;
       c.TR = H;

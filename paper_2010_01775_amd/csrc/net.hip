@@ -664,8 +664,149 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
     for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = AccV{0, 0, 0, 0};
 
+  // the nine taps of one K chunk on the staged patch (weights wg of the chunk)
+  auto taps = [&](const WT *wg) {
+    // WGLB: this lane's B values of a tap, [k step][n tile]
+    float wcur[WGLB ? KC / 4 : 1][WGLB ? NW : 1], wnxt[WGLB ? KC / 4 : 1][WGLB ? NW : 1];
+    if constexpr (WGLB) {
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+        for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wg[(ks * 4 + lg) * BN + ni * 16 + lr];
+    }
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int toff = (tap / 3) * PW + (tap % 3);
+      if constexpr (WGLB) {
+        if (tap < 8) {
+#pragma unroll
+          for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+            for (int ni = 0; ni < NW; ++ni)
+              wnxt[ks][ni] = wg[((tap + 1) * KC + ks * 4 + lg) * BN + ni * 16 + lr];
+        }
+      }
+      if constexpr (IS_F32) {
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+          double av[MW], bv[NW];
+#pragma unroll
+          for (int mi = 0; mi < MW; ++mi)
+            av[mi] = (double)patch[(bp[mi] + toff) * PSTR + ks * 4 + lg];
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni)
+            bv[ni] = WGLB ? (double)wcur[WGLB ? ks : 0][WGLB ? ni : 0]
+                          : (double)wl[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
+#pragma unroll
+          for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NW; ++ni)
+              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+        }
+      } else if constexpr (!TWO_TAP) {
+        using Frag = typename P::Frag;
+        Frag av[MW], bv[NW];
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + toff) * PSTR + lg * 8);
+#pragma unroll
+        for (int ni = 0; ni < NW; ++ni)
+          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tap * BN + ni * 16 + lr) * KCP + lg * 8);
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
+      } else {
+        if (tap & 1) continue;  // taps handled in pairs (tap, tap + 1)
+        // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
+        // tap has zero weights; its patch reads stay inside the patch)
+        const int tl = tap + (lg >> 1);
+        const int tofl = tl < 9 ? (tl / 3) * PW + (tl % 3) : 0;
+        const int cofs = (lg & 1) * 8;
+        using Frag = typename P::Frag;
+        Frag av[MW], bv[NW];
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + tofl) * PSTR + cofs);
+#pragma unroll
+        for (int ni = 0; ni < NW; ++ni)
+          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tl * BN + ni * 16 + lr) * KCP + cofs);
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
+      }
+      if constexpr (WGLB) {
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+          for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wnxt[ks][ni];
+      }
+    }
+  };
+
+  // FP64 tiles on plain or concatenated inputs whose patch has at most one
+  // pixel per thread: the next chunk's pixel is loaded into registers while
+  // the matrix cores work on the current chunk (their weights come straight
+  // from global memory, so the patch is all there is to stage)
+  bool piped = false;
+  if constexpr (WGLB && MODE == 0) {
+    const int npx = TL * PH * PW;
+    if (npx <= 256) {
+      piped = true;
+      auto load_px = [&](int ch, uint4 (&v)[G]) {
+        const int c0 = ch * KC, pp = tid;
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g] = make_uint4(0, 0, 0, 0);
+        if (pp >= npx) return;
+        const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+        const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+        const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
+        if (leaf >= a.Lc || y < 0 || y >= H || x < 0 || x >= W) return;
+        const T *q = nullptr;
+        int cleft = 0;
+        if (a.src.mode == SRC_UPCAT) {
+          if (c0 < a.src.C0) {
+            q = static_cast<const T *>(a.src.s0) + (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * a.src.C0 +
+                c0;
+            cleft = a.src.C0 - c0;
+          } else if (c0 - a.src.C0 < a.src.C1) {
+            q = static_cast<const T *>(a.src.s1) + (((size_t)leaf * H + y) * W + x) * a.src.C1 + (c0 - a.src.C0);
+            cleft = a.src.C1 - (c0 - a.src.C0);
+          }
+        } else if (c0 < a.src.C0) {
+          q = static_cast<const T *>(a.src.s0) + (((size_t)leaf * H + y) * W + x) * a.src.C0 + c0;
+          cleft = a.src.C0 - c0;
+        }
+        if (q) {
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            if (g * VEC < cleft) v[g] = reinterpret_cast<const uint4 *>(q)[g];
+        }
+      };
+      auto store_px = [&](const uint4 (&v)[G]) {
+        if (tid < npx) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) *reinterpret_cast<uint4 *>(patch + tid * PSTR + g * VEC) = v[g];
+        }
+      };
+      uint4 nv[G];
+      load_px(0, nv);
+      store_px(nv);
+      __syncthreads();
+      for (int ch = 0; ch < a.nchunk; ++ch) {
+        if (ch + 1 < a.nchunk) load_px(ch + 1, nv);
+        taps(static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN);
+        __syncthreads();
+        if (ch + 1 < a.nchunk) {
+          store_px(nv);
+          __syncthreads();
+        }
+      }
+    }
+  }
   const int items = TL * PH * PW * G;
-  for (int ch = 0; ch < a.nchunk; ++ch) {
+  for (int ch = 0; ch < (piped ? 0 : a.nchunk); ++ch) {
     const int c0 = ch * KC;
     // 8/16-bit weights: the first batch is loaded before the patch so that
     // both arrive in one global round trip
@@ -882,83 +1023,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     }
     __syncthreads();
-    // WGLB: this lane's B values of a tap, [k step][n tile]
-    float wcur[WGLB ? KC / 4 : 1][WGLB ? NW : 1], wnxt[WGLB ? KC / 4 : 1][WGLB ? NW : 1];
-    if constexpr (WGLB) {
-#pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-        for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wg[(ks * 4 + lg) * BN + ni * 16 + lr];
-    }
-#pragma unroll 1
-    for (int tap = 0; tap < 9; ++tap) {
-      const int toff = (tap / 3) * PW + (tap % 3);
-      if constexpr (WGLB) {
-        if (tap < 8) {
-#pragma unroll
-          for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-            for (int ni = 0; ni < NW; ++ni)
-              wnxt[ks][ni] = wg[((tap + 1) * KC + ks * 4 + lg) * BN + ni * 16 + lr];
-        }
-      }
-      if constexpr (IS_F32) {
-#pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks) {
-          double av[MW], bv[NW];
-#pragma unroll
-          for (int mi = 0; mi < MW; ++mi)
-            av[mi] = (double)patch[(bp[mi] + toff) * PSTR + ks * 4 + lg];
-#pragma unroll
-          for (int ni = 0; ni < NW; ++ni)
-            bv[ni] = WGLB ? (double)wcur[WGLB ? ks : 0][WGLB ? ni : 0]
-                          : (double)wl[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
-#pragma unroll
-          for (int mi = 0; mi < MW; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < NW; ++ni)
-              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
-        }
-      } else if constexpr (!TWO_TAP) {
-        using Frag = typename P::Frag;
-        Frag av[MW], bv[NW];
-#pragma unroll
-        for (int mi = 0; mi < MW; ++mi)
-          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + toff) * PSTR + lg * 8);
-#pragma unroll
-        for (int ni = 0; ni < NW; ++ni)
-          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tap * BN + ni * 16 + lr) * KCP + lg * 8);
-#pragma unroll
-        for (int mi = 0; mi < MW; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
-      } else {
-        if (tap & 1) continue;  // taps handled in pairs (tap, tap + 1)
-        // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
-        // tap has zero weights; its patch reads stay inside the patch)
-        const int tl = tap + (lg >> 1);
-        const int tofl = tl < 9 ? (tl / 3) * PW + (tl % 3) : 0;
-        const int cofs = (lg & 1) * 8;
-        using Frag = typename P::Frag;
-        Frag av[MW], bv[NW];
-#pragma unroll
-        for (int mi = 0; mi < MW; ++mi)
-          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + tofl) * PSTR + cofs);
-#pragma unroll
-        for (int ni = 0; ni < NW; ++ni)
-          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tl * BN + ni * 16 + lr) * KCP + cofs);
-#pragma unroll
-        for (int mi = 0; mi < MW; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
-      }
-      if constexpr (WGLB) {
-#pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-          for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wnxt[ks][ni];
-      }
-    }
+    taps(wg);
     __syncthreads();
   }
 

@@ -340,6 +340,52 @@ def test_sample_parity_same_tables(ctx, npg, orc, L, H, W, n):
     assert mism <= max(3, n // 20000), mism
 
 
+def test_sample_chi_square_across_leaves(ctx, npg):
+    """GPU samples of many leaves against their tabulated pdfs: the chi-square
+    p-value of each leaf's sampled bins (bins with expected count < 5
+    merged) must look uniform across leaves (KS test), and zero bins are
+    never drawn."""
+    from scipy import stats
+    rng = np.random.default_rng(31)
+    L, H, W, per = 160, 32, 32, 30000
+    dens = rng.lognormal(0.0, 1.5, (L, H, W))
+    dens[rng.random((L, H, W)) < 0.15] = 0.0
+    tabs = npg.build_cdf(ctx, torch.from_numpy(dens.astype(np.float32)).to(DEV))
+    leaf = np.repeat(np.arange(L, dtype=np.uint32), per)
+    g = synth.rng_for(32)
+    u = np.stack([synth.uniforms(g, L * per), synth.uniforms(g, L * per)], 1)   # exact float32 in [0, 1)
+    d, p, b = npg.sample_dirs(ctx, tabs, t32(leaf), tf(u))
+    assert npg.sync_status(ctx) == 0
+    b = u32(b).reshape(L, per).astype(np.int64)
+    pk_all = dens.astype(np.float32).astype(np.float64)
+    pvals = []
+    for l in range(L):
+        pk = (pk_all[l] / pk_all[l].sum()).ravel()
+        assert np.all(pk[b[l]] > 0), l
+        obs = np.bincount(b[l], minlength=H * W).astype(np.float64)
+        exp = pk * per
+        order = np.argsort(exp)
+        # merge the smallest expectations until each group expects >= 5
+        o_m, e_m, oc, ec = [], [], 0.0, 0.0
+        for k in order:
+            if exp[k] == 0:
+                continue
+            oc += obs[k]
+            ec += exp[k]
+            if ec >= 5:
+                o_m.append(oc)
+                e_m.append(ec)
+                oc = ec = 0.0
+        if ec > 0:
+            o_m[-1] += oc
+            e_m[-1] += ec
+        e_m = np.array(e_m)
+        pvals.append(stats.chisquare(o_m, e_m * per / e_m.sum()).pvalue)
+    ks = stats.kstest(pvals, "uniform").pvalue
+    print(f"chi-square p-values over {L} leaves: KS p = {ks:.3g}, min p = {min(pvals):.3g}")
+    assert ks > 1e-3
+
+
 def test_sample_errors(ctx, npg, orc):
     s, pdf, marg, cond = _oracle_tables(orc, 1, 2, 8, 8)
     tabs = npg.CdfTables(tf(pdf), tf(marg), tf(cond), None)

@@ -177,3 +177,26 @@ def test_sample_and_eval_errors(orc):
     rc, pe = orc.eval_pdf(pdf, np.array([1, 5, 0], np.uint32), dirs)
     assert rc == orc.E_RANGE
     assert pe[0] == pdf[1, 3, 0] and pe[1] == 0 and pe[2] == 0
+
+
+def test_fp32_tables_total_variation(orc):
+    """The float32 tables select bins with probabilities (M_{i+1} - M_i) *
+    (C_{i,j+1} - C_{i,j}); every stored prefix is within half an ulp (at most
+    2^-25) of the float64 prefix, so the total-variation distance to p is at
+    most (H + W) * 2^-24 / 2, even for spiky maps with zero rows."""
+    for seed, (H, W), spike in ((21, (32, 32), False), (22, (64, 64), True), (23, (128, 16), True)):
+        s = synth.random_density(seed, 6, H, W, zero_frac=0.3).astype(np.float64)
+        if spike:
+            s[1] *= 1e-12
+            s[1, 3, 5] = 1.0                           # one dominant bin
+            s[2, : H // 2] = 0.0                       # zero rows
+        rc, pdf, marg, cond, tot = orc.build_cdf(s)
+        assert rc == 0
+        for l in range(s.shape[0]):
+            p = s[l] / s[l].sum()
+            m = np.diff(marg[l].astype(np.float64))
+            c = np.diff(cond[l].astype(np.float64), axis=1)
+            q = m[:, None] * c
+            assert abs(q.sum() - 1.0) < 1e-12
+            tv = 0.5 * np.abs(q - p).sum()
+            assert tv <= (H + W) * 2.0 ** -25, (seed, l, tv)

@@ -128,6 +128,13 @@ __device__ __forceinline__ uint8_t e4m3_enc_d(float x) {
   return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(c, c, 0, false) & 0xff);
 }
 __device__ __forceinline__ float e4m3_dec_d(uint8_t v) { return __builtin_amdgcn_cvt_f32_fp8((int)v, 0); }
+// Four values as four e4m3 bytes (first value in the low byte), each clamped
+// and rounded as e4m3_enc_d does: two conversion instructions.
+__device__ __forceinline__ float e4m3_clamp_d(float x) { return x != x ? x : fminf(fmaxf(x, -E4M3_MAX), E4M3_MAX); }
+__device__ __forceinline__ uint32_t e4m3_pack4_d(float a, float b, float c, float d) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp_d(a), e4m3_clamp_d(b), 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp_d(c), e4m3_clamp_d(d), lo, true);
+}
 
 // Parses the NPGW v1 file and checks the declared topology.
 static int parse_model(npg_ctx *ctx, const unsigned char *buf, size_t len, npg_model *m) {
@@ -288,12 +295,8 @@ enum Act : int { ACT_RELU = 0, ACT_SOFTPLUS = 1 };
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bf16 bits, round to nearest even (one conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
 __device__ __forceinline__ double softplus_f(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
@@ -521,7 +524,7 @@ struct FP8S : FP8P {
   static constexpr int KC = KC8S, PSTR = KC + 32, KCP = KC + 32, SPX = 4;
 };
 
-// n / d for n, d < 2^16 as a multiply-high by m = ceil(2^32 / d).
+// n / d for 2 <= d and n * d < 2^32, as a multiply-high by m = ceil(2^32 / d).
 struct FastDiv {
   uint32_t d, m;
 };
@@ -532,6 +535,7 @@ struct ConvArgs {
   Src src;
   int Cin, Cout, H, W, TW, TR, TL, nchunk;
   FastDiv fPW, fPP;       // divisions by the patch row length and patch size
+  FastDiv fTW, fTPX;      // divisions by the tile row length and pixels per leaf
   int Lc;                 // leaves in this launch
   int tiles_x, tiles_per_leaf;
   const void *wpk;
@@ -655,8 +659,9 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
   for (int mi = 0; mi < MW; ++mi) {
     const int m = wave * 16 * MW + mi * 16 + lr;
-    const int ls = m / TPX, rem = m - ls * TPX;
-    bp[mi] = ls * PH * PW + (rem / TW) * PW + (rem % TW);
+    const int ls = (int)fdiv((uint32_t)m, a.fTPX), rem = m - ls * TPX;
+    const int ry = (int)fdiv((uint32_t)rem, a.fTW);
+    bp[mi] = ls * PH * PW + ry * PW + (rem - ry * TW);
   }
   AccV acc[MW][NW];
 #pragma unroll
@@ -1031,9 +1036,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // barrier) so that global stores are whole 16-byte pieces of output rows
   const int BM = 64 * MW;
   auto gpix = [&](int m) -> long {  // global pixel index of tile pixel m, -1 if past the last leaf
-    const int ls = m / TPX, rem = m - ls * TPX;
+    const int ls = (int)fdiv((uint32_t)m, a.fTPX), rem = m - ls * TPX;
     if (leaf0 + ls >= a.Lc) return -1;
-    return ((long)(leaf0 + ls) * H + ty0 + rem / TW) * W + tx0 + rem % TW;
+    const int ry = (int)fdiv((uint32_t)rem, a.fTW);
+    return ((long)(leaf0 + ls) * H + ty0 + ry) * W + tx0 + (rem - ry * TW);
   };
   if constexpr (!P::F64) {
     // 8/16-bit tiles hold the transposed product (weights as the A operand):
@@ -1053,18 +1059,25 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
       for (int mi = 0; mi < MW; ++mi) {
         AS v = 0;
+        // the values the unfused path would store (type T) feed the head
+        if constexpr (P::Q8) {
+          float q[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          // the value the unfused path would store (type T) feeds the head
-          AS act;
-          if constexpr (P::Q8) {
+          for (int r = 0; r < 4; ++r) {
             const AS v0 = acc[mi][0][r] * ws[r] + bn[r];
-            act = (AS)(e4m3_dec_d(e4m3_enc_d((v0 > (AS)0 ? v0 : (AS)0) * a.oinv)) * a.asc);
-          } else {
-            const AS v0 = acc[mi][0][r] + bn[r];
-            act = (AS)to_d<T>(from_d<T>((double)(v0 > (AS)0 ? v0 : (AS)0)));
+            q[r] = (v0 > (AS)0 ? v0 : (AS)0) * a.oinv;
           }
-          v += act * hw[r];
+          const int pk = (int)e4m3_pack4_d(q[0], q[1], q[2], q[3]);
+          const auto d01 = __builtin_amdgcn_cvt_pk_f32_fp8(pk, false), d23 = __builtin_amdgcn_cvt_pk_f32_fp8(pk, true);
+          const float dq[4] = {d01[0], d01[1], d23[0], d23[1]};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v += (AS)(dq[r] * a.asc) * hw[r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const AS v0 = acc[mi][0][r] + bn[r];
+            v += (AS)bf2f(f2bf(v0 > (AS)0 ? v0 : (AS)0)) * hw[r];
+          }
         }
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
@@ -1093,24 +1106,23 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
       for (int mi = 0; mi < MW; ++mi) {
         const int m = wave * 16 * MW + mi * 16 + lr;
-        T q[4];
+        float q[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           if constexpr (P::Q8) {
             const AS v = acc[mi][ni][r] * ws[r] + bn[r];
-            q[r] = e4m3_enc_d((v > (AS)0 ? v : (AS)0) * a.oinv);
+            q[r] = (v > (AS)0 ? v : (AS)0) * a.oinv;
           } else {
             const AS v = acc[mi][ni][r] + bn[r];
-            q[r] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));
+            q[r] = v > (AS)0 ? v : (AS)0;
           }
         }
         T *o = ol + m * BN + 16 * ni + 4 * lg;  // four consecutive channels: one store
         if constexpr (sizeof(T) == 2)
-          *reinterpret_cast<uint2 *>(o) = make_uint2((uint32_t)q[0] | ((uint32_t)q[1] << 16),
-                                                     (uint32_t)q[2] | ((uint32_t)q[3] << 16));
+          *reinterpret_cast<uint2 *>(o) = make_uint2((uint32_t)f2bf(q[0]) | ((uint32_t)f2bf(q[1]) << 16),
+                                                     (uint32_t)f2bf(q[2]) | ((uint32_t)f2bf(q[3]) << 16));
         else
-          *reinterpret_cast<uint32_t *>(o) = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) |
-                                             ((uint32_t)q[3] << 24);
+          *reinterpret_cast<uint32_t *>(o) = e4m3_pack4_d(q[0], q[1], q[2], q[3]);
       }
     }
     __syncthreads();
@@ -1403,6 +1415,8 @@ struct Runner {
     a.Lc = Lc;
     a.fPW = make_fastdiv((uint32_t)(t.TW + 2));
     a.fPP = make_fastdiv((uint32_t)((t.TW + 2) * (t.TR + 2)));
+    a.fTW = make_fastdiv((uint32_t)t.TW);
+    a.fTPX = make_fastdiv((uint32_t)(t.TW * t.TR));
     a.tiles_x = W / t.TW;
     a.tiles_per_leaf = (H / t.TR) * a.tiles_x;
     a.nchunk = prec == NPG_FP32 ? 16 / KC32 : 1;
@@ -1476,6 +1490,8 @@ struct Runner {
       a.Lc = Lc;
       a.fPW = make_fastdiv((uint32_t)(t.TW + 2));
       a.fPP = make_fastdiv((uint32_t)((t.TW + 2) * (t.TR + 2)));
+      a.fTW = make_fastdiv((uint32_t)t.TW);
+      a.fTPX = make_fastdiv((uint32_t)(t.TW * t.TR));
       a.tiles_x = W / t.TW;
       a.tiles_per_leaf = (H / t.TR) * a.tiles_x;
       a.bias = y.b;

@@ -552,32 +552,56 @@ struct ConvArgs {
   int wbytes;            // LDS bytes of the weight tile (the energy tile follows it)
 };
 
-// Address of the 16 bytes of VEC channels at c of a plain or concatenated
-// input, or nullptr where the channels are padding.
-template <class P>
-__device__ __forceinline__ const uint4 *vec_ptr(const Src &s, int leaf, int y, int x, int c, int H, int W) {
-  using T = typename P::T;
-  if (s.mode == SRC_UPCAT) {
-    if (c < s.C0)
-      return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) +
-                                             (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * s.C0 + c);
-    if (c - s.C0 < s.C1)
-      return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s1) +
-                                             (((size_t)leaf * H + y) * W + x) * s.C1 + (c - s.C0));
-    return nullptr;
+// The input channels of one K chunk (plain or upsampled + concatenated
+// input) as a buffer resource over the tile's leaves.  Loads at offsets past
+// its end return zeros, so the zero padding outside the map and past the last
+// leaf of the launch needs no branches.
+template <class T>
+struct ChunkSrc {
+  __amdgpu_buffer_rsrc_t rs;
+  int shift;       // 1: the half-resolution input read through nearest upsampling
+  int Ws, C;       // source row length and channels per pixel
+  int plane;       // source elements per leaf
+  uint32_t cbyte;  // byte offset of the chunk's first channel within a pixel
+  int cleft;       // source channels from the chunk's first on (<= 0: padding)
+  // byte offset of pixel (y, x) of tile leaf ls, out of range outside the map
+  __device__ __forceinline__ uint32_t off(int ls, int y, int x, int H, int W) const {
+    const bool in = (uint32_t)y < (uint32_t)H && (uint32_t)x < (uint32_t)W;
+    const uint32_t o = (uint32_t)(ls * plane + ((y >> shift) * Ws + (x >> shift)) * C) * (uint32_t)sizeof(T) + cbyte;
+    return in ? o : 0x80000000u;
   }
-  if (c >= s.C0) return nullptr;
-  return reinterpret_cast<const uint4 *>(static_cast<const T *>(s.s0) + (((size_t)leaf * H + y) * W + x) * s.C0 + c);
-}
+  __device__ __forceinline__ uint4 load(uint32_t o) const {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+  }
+};
+// Buffer-resource word 3 for raw (unswizzled, untyped) buffers on gfx9.
+constexpr int BUF_WORD3 = 0x00020000;
 
-// Address of the top-left input of the 2x2 pooling window of output pixel
-// (y, x), channels c..c+VEC-1, or nullptr where the channels are padding.
-template <class P>
-__device__ __forceinline__ const typename P::T *pool_ptr(const Src &s, int leaf, int y, int x, int c, int H,
-                                                         int W) {
-  using T = typename P::T;
-  if (c >= s.C0) return nullptr;
-  return static_cast<const T *>(s.s0) + (((size_t)leaf * 2 * H + 2 * y) * (2 * W) + 2 * x) * s.C0 + c;
+template <class T>
+__device__ __forceinline__ ChunkSrc<T> chunk_src(const ConvArgs &a, int leaf0, int c0) {
+  ChunkSrc<T> cs;
+  const void *base = nullptr;
+  int C = 0, shift = 0, cl = 0, coff = 0;
+  if (a.src.mode == SRC_UPCAT) {
+    if (c0 < a.src.C0) {
+      base = a.src.s0, C = a.src.C0, shift = 1, cl = a.src.C0 - c0, coff = c0;
+    } else if (c0 - a.src.C0 < a.src.C1) {
+      base = a.src.s1, C = a.src.C1, cl = a.src.C1 - (c0 - a.src.C0), coff = c0 - a.src.C0;
+    }
+  } else if (c0 < a.src.C0) {
+    base = a.src.s0, C = a.src.C0, cl = a.src.C0 - c0, coff = c0;
+  }
+  cs.shift = shift;
+  cs.Ws = a.W >> shift;
+  cs.C = C;
+  cs.plane = (a.H >> shift) * cs.Ws * C;
+  cs.cbyte = (uint32_t)coff * (uint32_t)sizeof(T);
+  cs.cleft = cl;
+  const int nl = min(a.TL, a.Lc - leaf0);
+  const T *b = base ? static_cast<const T *>(base) + (size_t)leaf0 * cs.plane : nullptr;
+  cs.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(b), (short)0, b ? nl * cs.plane * (int)sizeof(T) : 0,
+                                            BUF_WORD3);
+  return cs;
 }
 
 // Mean of four 16-byte pieces (the pooling window), rounded to storage.
@@ -759,35 +783,14 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     const int npx = TL * PH * PW;
     if (npx <= 256) {
       piped = true;
+      // this thread's patch pixel (the same in every chunk)
+      const int ls = (int)fdiv((uint32_t)tid, a.fPP), pr = tid - ls * PH * PW;
+      const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
       auto load_px = [&](int ch, uint4 (&v)[G]) {
-        const int c0 = ch * KC, pp = tid;
+        const ChunkSrc<T> cs = chunk_src<T>(a, leaf0, ch * KC);
+        const uint32_t o = tid < npx ? cs.off(ls, ty0 - 1 + py, tx0 - 1 + px, H, W) : 0x80000000u;
 #pragma unroll
-        for (int g = 0; g < G; ++g) v[g] = make_uint4(0, 0, 0, 0);
-        if (pp >= npx) return;
-        const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
-        const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-        const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
-        if (leaf >= a.Lc || y < 0 || y >= H || x < 0 || x >= W) return;
-        const T *q = nullptr;
-        int cleft = 0;
-        if (a.src.mode == SRC_UPCAT) {
-          if (c0 < a.src.C0) {
-            q = static_cast<const T *>(a.src.s0) + (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * a.src.C0 +
-                c0;
-            cleft = a.src.C0 - c0;
-          } else if (c0 - a.src.C0 < a.src.C1) {
-            q = static_cast<const T *>(a.src.s1) + (((size_t)leaf * H + y) * W + x) * a.src.C1 + (c0 - a.src.C0);
-            cleft = a.src.C1 - (c0 - a.src.C0);
-          }
-        } else if (c0 < a.src.C0) {
-          q = static_cast<const T *>(a.src.s0) + (((size_t)leaf * H + y) * W + x) * a.src.C0 + c0;
-          cleft = a.src.C0 - c0;
-        }
-        if (q) {
-#pragma unroll
-          for (int g = 0; g < G; ++g)
-            if (g * VEC < cleft) v[g] = reinterpret_cast<const uint4 *>(q)[g];
-        }
+        for (int g = 0; g < G; ++g) v[g] = g * VEC < cs.cleft ? cs.load(o + 16 * g) : make_uint4(0, 0, 0, 0);
       };
       auto store_px = [&](const uint4 (&v)[G]) {
         if (tid < npx) {
@@ -886,29 +889,33 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     } else if constexpr (MODE == 1) {
       constexpr int SBP = P::SBP;  // pooling windows (four loads each) in flight per thread
-      const size_t dr = (size_t)2 * W * a.src.C0;
+      // the full-resolution input of the tile's leaves as a buffer resource
+      // (out-of-range offsets read zeros: padding outside the map)
+      const int C0 = a.src.C0, W2 = 2 * W, plane = 4 * H * W * C0;
+      const int nl = min(TL, a.Lc - leaf0);
+      const T *pb = static_cast<const T *>(a.src.s0) + (size_t)leaf0 * plane;
+      const auto prs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pb), (short)0, nl * plane * (int)sizeof(T),
+                                                         BUF_WORD3);
+      const uint32_t dcb = (uint32_t)(C0 * sizeof(T)), drb = (uint32_t)W2 * dcb;
+      auto pld = [&](uint32_t o) {
+        return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(prs, o, 0, 0));
+      };
       for (int base = 0; base < items; base += 256 * SBP) {
         uint4 q[SBP][4];
 #pragma unroll
         for (int k = 0; k < SBP; ++k) {
           const int it = base + k * 256 + tid;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) q[k][j] = make_uint4(0, 0, 0, 0);
-          if (it < items) {
-            const int pp = it / G, g = it - pp * G;
-            const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
-            const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-            const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
-            if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
-              const T *p = pool_ptr<P>(a.src, leaf, y, x, c0 + g * VEC, H, W);
-              if (p) {
-                q[k][0] = *reinterpret_cast<const uint4 *>(p);
-                q[k][1] = *reinterpret_cast<const uint4 *>(p + a.src.C0);
-                q[k][2] = *reinterpret_cast<const uint4 *>(p + dr);
-                q[k][3] = *reinterpret_cast<const uint4 *>(p + dr + a.src.C0);
-              }
-            }
-          }
+          const int pp = it / G, g = it - pp * G;
+          const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+          const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+          const int y = ty0 - 1 + py, x = tx0 - 1 + px, c = c0 + g * VEC;
+          const bool in = it < items && (uint32_t)y < (uint32_t)H && (uint32_t)x < (uint32_t)W && c < C0;
+          const uint32_t o = in ? (uint32_t)(ls * plane + (2 * y * W2 + 2 * x) * C0 + c) * (uint32_t)sizeof(T)
+                                : 0x80000000u;
+          q[k][0] = pld(o);
+          q[k][1] = pld(o + dcb);
+          q[k][2] = pld(o + drb);
+          q[k][3] = pld(o + drb + dcb);
         }
 #pragma unroll
         for (int k = 0; k < SBP; ++k) {
@@ -920,46 +927,22 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
       }
     } else {
-      // one address per patch pixel, then its G 16-byte pieces back to back
+      // one offset per patch pixel, then its G 16-byte pieces back to back
       // (a chunk's channels come from one source: the concatenation boundary
       // is a multiple of KC)
       constexpr int SPX = P::SPX;  // pixels per thread per batch
       const int npx = TL * PH * PW;
+      const ChunkSrc<T> cs = chunk_src<T>(a, leaf0, c0);
       for (int base = 0; base < npx; base += 256 * SPX) {
         uint4 v[SPX][G];
 #pragma unroll
         for (int k = 0; k < SPX; ++k) {
           const int pp = base + k * 256 + tid;
+          const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+          const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+          const uint32_t o = pp < npx ? cs.off(ls, ty0 - 1 + py, tx0 - 1 + px, H, W) : 0x80000000u;
 #pragma unroll
-          for (int g = 0; g < G; ++g) v[k][g] = make_uint4(0, 0, 0, 0);
-          if (pp < npx) {
-            const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
-            const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-            const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
-            if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
-              const T *q = nullptr;
-              int cleft = 0;  // channels of the source from c on
-              if (a.src.mode == SRC_UPCAT) {
-                if (c0 < a.src.C0) {
-                  q = static_cast<const T *>(a.src.s0) +
-                      (((size_t)leaf * (H / 2) + y / 2) * (W / 2) + x / 2) * a.src.C0 + c0;
-                  cleft = a.src.C0 - c0;
-                } else if (c0 - a.src.C0 < a.src.C1) {
-                  q = static_cast<const T *>(a.src.s1) + (((size_t)leaf * H + y) * W + x) * a.src.C1 +
-                      (c0 - a.src.C0);
-                  cleft = a.src.C1 - (c0 - a.src.C0);
-                }
-              } else if (c0 < a.src.C0) {
-                q = static_cast<const T *>(a.src.s0) + (((size_t)leaf * H + y) * W + x) * a.src.C0 + c0;
-                cleft = a.src.C0 - c0;
-              }
-              if (q) {
-#pragma unroll
-                for (int g = 0; g < G; ++g)
-                  if (g * VEC < cleft) v[k][g] = reinterpret_cast<const uint4 *>(q)[g];
-              }
-            }
-          }
+          for (int g = 0; g < G; ++g) v[k][g] = g * VEC < cs.cleft ? cs.load(o + 16 * g) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int k = 0; k < SPX; ++k) {
@@ -1381,7 +1364,13 @@ struct Runner {
     // the tiled kernel takes each K chunk's channels from one source
     const int kc = prec == NPG_FP32 ? KC32 : (y.cin % 32 == 0 ? 32 : 16);
     if (src.mode == SRC_UPCAT && src.C0 % kc) return false;
-    return tiling(y, H, W, t, mw_lim);
+    if (!tiling(y, H, W, t, mw_lim)) return false;
+    // the tiles read their input through buffer resources: the bytes of one
+    // tile's leaves must stay below 2^31 (offsets at or past 2^31 mean padding)
+    const size_t esz = prec == NPG_FP32 ? sizeof(double) : prec == NPG_FP8 ? 1 : 2;
+    const size_t px = src.mode == SRC_POOL ? (size_t)4 * H * W : (size_t)H * W;
+    const size_t ch = (size_t)std::max(src.C0, src.C1);
+    return (size_t)t->TL * px * ch * esz < ((size_t)1 << 31);
   }
 
   // The first layer (energy -> 16 channels, 3x3, ReLU) can be computed inside

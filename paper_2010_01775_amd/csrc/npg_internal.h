@@ -89,16 +89,14 @@ __device__ __forceinline__ void load_quarter(const float2 *__restrict__ tab1024,
 }
 
 __device__ __forceinline__ float2 bnd_ray(const float2 *q4, int b, int W) {
-  const int Q = W >> 2;
-  const int q = b / Q;
-  const int r = b - q * Q;
-  const float2 e = q4[r];
-  switch (q) {
-    case 0: return make_float2(e.x, e.y);
-    case 1: return make_float2(-e.y, e.x);
-    case 2: return make_float2(-e.x, -e.y);
-    default: return make_float2(e.y, -e.x);
-  }
+  const int Q = W >> 2;                          // a power of two
+  const int q = b >> (__builtin_ctz((unsigned)W) - 2);
+  const float2 e = q4[b & (Q - 1)];
+  // rotation by q quarter turns (negations are exact): an odd q turns
+  // (x, y) into (-y, x), q >= 2 negates both
+  float cx = (q & 1) ? -e.y : e.x, cy = (q & 1) ? e.x : e.y;
+  if (q & 2) cx = -cx, cy = -cy;
+  return make_float2(cx, cy);
 }
 
 // Sign test of cross(e, v) = e.x*y - e.y*x.  Both products of float32
@@ -110,14 +108,30 @@ __device__ __forceinline__ bool left_of(float2 e, float x, float y) {
   return a - b >= 0.0;
 }
 
+// Estimate of atan2(y, x) in [-pi, pi] for (x, y) != 0: the odd polynomial of
+// Abramowitz & Stegun 4.4.47 for atan on [0, 1] (absolute error <= 1e-5),
+// applied to min/max of |x|, |y| and unfolded to the octant.  Callers settle
+// the exact answer with exact tests; the estimate only has to be close.
+__device__ __forceinline__ float atan2_est(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float t = fminf(mn * __builtin_amdgcn_rcpf(mx), 1.0f);  // in [0, 1] even for subnormal inputs
+  const float t2 = t * t;
+  float r = fmaf(fmaf(fmaf(fmaf(0.0208351f, t2, -0.0851330f), t2, 0.1801410f), t2, -0.3302995f), t2, 0.9998660f) * t;
+  if (ay > ax) r = 1.57079632679f - r;
+  if (x < 0.0f) r = 3.14159265359f - r;
+  return y < 0.0f ? -r : r;
+}
+
 // Azimuth sector of (x, y): the b with cross(e_b, v) >= 0 > cross(e_{b+1}, v).
-// A float32 atan2 estimate lands within one sector of the answer; the exact
-// tests then settle it.  A bisection over all sectors backs up the
-// (never observed) case of a farther estimate.
+// An atan2 estimate lands within one sector of the answer (its error is far
+// below the sector width 2 pi / W >= 6e-3 rad); the exact tests then settle
+// it.  A bisection over all sectors backs up the (never observed) case of a
+// farther estimate.
 __device__ __forceinline__ int phi_sector(const float2 *q4, float x, float y, int W) {
   if (x == 0.0f && y == 0.0f) return 0;
   const float k = (float)W * 0.15915494309189535f;  // W / (2 pi)
-  float f = atan2f(y, x) * k;
+  float f = atan2_est(y, x) * k;
   if (f < 0.0f) f += (float)W;
   int b = (int)f;
   b = b < 0 ? 0 : (b >= W ? W - 1 : b);
@@ -154,11 +168,13 @@ __device__ __forceinline__ int phi_sector(const float2 *q4, float x, float y, in
 __device__ __forceinline__ int z_row(float z, int H) {
   float t = (z + 1.0f) * (0.5f * (float)H);
   int iz = (int)floorf(fminf(fmaxf(t, 0.0f), (float)(H - 1)));
-  const float hh = 0.5f * (float)H;
-  if (iz > 0 && z < -1.0f + (float)iz / hh) --iz;
-  if (iz > 0 && z < -1.0f + (float)iz / hh) --iz;
-  if (iz < H - 1 && z >= -1.0f + (float)(iz + 1) / hh) ++iz;
-  if (iz < H - 1 && z >= -1.0f + (float)(iz + 1) / hh) ++iz;
+  // boundary b is -1 + b * (2 / H); 2 / H is a power of two, so the product
+  // is the exact quotient b / (H / 2)
+  const float ih = 2.0f / (float)H;
+  if (iz > 0 && z < -1.0f + (float)iz * ih) --iz;
+  if (iz > 0 && z < -1.0f + (float)iz * ih) --iz;
+  if (iz < H - 1 && z >= -1.0f + (float)(iz + 1) * ih) ++iz;
+  if (iz < H - 1 && z >= -1.0f + (float)(iz + 1) * ih) ++iz;
   return iz;
 }
 

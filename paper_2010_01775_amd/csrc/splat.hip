@@ -73,17 +73,33 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
   __syncthreads();
   for (uint64_t r0 = beg; r0 < end; r0 += SPLAT_ROUND) {
     const uint32_t r1 = (uint32_t)min((uint64_t)end, r0 + SPLAT_ROUND);
-    for (uint32_t i = (uint32_t)r0 + tid; i < r1; i += SPLAT_THREADS) {
-      const uint32_t p = src.idx(leaf, i);
-      const float x = dir[3 * (size_t)p], y = dir[3 * (size_t)p + 1], z = dir[3 * (size_t)p + 2];
-      if (!finite3(x, y, z)) {
-        bad = true;
-        continue;
+    // PB photons per thread and step: all their loads are issued before
+    // the first bin is computed
+    constexpr int PB = 2;
+    for (uint32_t i0 = (uint32_t)r0 + tid; i0 < r1; i0 += PB * SPLAT_THREADS) {
+      float x[PB], y[PB], z[PB];
+      uint32_t wp[PB];
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        const uint32_t i = i0 + j * SPLAT_THREADS;
+        const uint32_t p = src.idx(leaf, i < r1 ? i : i0);
+        x[j] = dir[3 * (size_t)p];
+        y[j] = dir[3 * (size_t)p + 1];
+        z[j] = dir[3 * (size_t)p + 2];
+        wp[j] = w[p];
       }
-      const int iz = z_row(z, H) - row0;
-      if (iz < 0 || iz >= band_rows) continue;
-      const int k = iz * W + phi_sector(q4, x, y, W);
-      atomicAdd(&acc[k], (1ull << PACK_SHIFT) + (unsigned long long)w[p]);
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        if (i0 + j * SPLAT_THREADS >= r1) continue;
+        if (!finite3(x[j], y[j], z[j])) {
+          bad = true;
+          continue;
+        }
+        const int iz = z_row(z[j], H) - row0;
+        if (iz < 0 || iz >= band_rows) continue;
+        const int k = iz * W + phi_sector(q4, x[j], y[j], W);
+        atomicAdd(&acc[k], (1ull << PACK_SHIFT) + (unsigned long long)wp[j]);
+      }
     }
     __syncthreads();
 #pragma unroll

@@ -34,6 +34,7 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 8 bits -> every th
   return r;
 }
 
+// cnt == nullptr: the histogram is left to cell_hist_kernel
 __global__ __launch_bounds__(256) void cells_kernel(const float *__restrict__ pos, uint64_t n, int dmax,
                                                     uint32_t *__restrict__ cell, uint32_t *__restrict__ cnt,
                                                     uint32_t *err) {
@@ -52,8 +53,46 @@ __global__ __launch_bounds__(256) void cells_kernel(const float *__restrict__ po
       raise_err(err, ERR_RANGE);
     }
     cell[i] = c;
-    atomicAdd(&cnt[c], 1u);
+    if (cnt) atomicAdd(&cnt[c], 1u);
   }
+}
+
+// Finest-cell histogram without hot-spot atomics.  Photons of a clustered
+// scene pile into few cells, and one global atomic per photon serialises on
+// those addresses.  Workgroup (r, p) instead counts, in LDS, the cells of
+// range r (HIST_RANGE consecutive cell ids) among the photons of slice p,
+// then adds its non-zero counts to the global histogram: one global atomic
+// per (workgroup, occupied cell).
+constexpr int HIST_RANGE = 32768;  // cells per workgroup (128 KiB of LDS counters)
+constexpr int HIST_THREADS = 1024;
+
+__global__ __launch_bounds__(HIST_THREADS) void cell_hist_kernel(const uint32_t *__restrict__ cell, uint64_t n,
+                                                                 uint32_t ncell, uint64_t per_slice,
+                                                                 uint32_t *__restrict__ cnt) {
+  extern __shared__ uint32_t h[];
+  const uint32_t r0 = blockIdx.x * (uint32_t)HIST_RANGE;
+  const uint32_t nr = min((uint32_t)HIST_RANGE, ncell - r0);
+  for (uint32_t k = threadIdx.x; k < nr; k += HIST_THREADS) h[k] = 0u;
+  __syncthreads();
+  // per_slice is a multiple of 4, so every slice starts 16-byte aligned
+  const uint64_t b = (uint64_t)blockIdx.y * per_slice;
+  const uint64_t e = min(n, b + per_slice);
+  const uint64_t e4 = b + ((e - b) & ~(uint64_t)3);
+  const uint4 *c4 = reinterpret_cast<const uint4 *>(cell + b);
+  for (uint64_t i = threadIdx.x; b + 4 * i < e4; i += HIST_THREADS) {
+    const uint4 v = c4[i];
+    const uint32_t c[4] = {v.x - r0, v.y - r0, v.z - r0, v.w - r0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (c[j] < nr) atomicAdd(&h[c[j]], 1u);
+  }
+  for (uint64_t i = e4 + threadIdx.x; i < e; i += HIST_THREADS) {
+    const uint32_t c = cell[i] - r0;
+    if (c < nr) atomicAdd(&h[c], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < nr; k += HIST_THREADS)
+    if (h[k]) atomicAdd(&cnt[r0 + k], h[k]);
 }
 
 // ---------------------------------------------------------------- scan
@@ -175,13 +214,34 @@ __global__ void emit_kernel(const uint32_t *__restrict__ cstart, const uint32_t 
   }
 }
 
-__global__ void leaf_of_kernel(const uint32_t *__restrict__ cell, uint64_t n, const uint32_t *__restrict__ lid,
-                               const uint32_t *__restrict__ flag, uint32_t *__restrict__ leaf_of) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+// leaf id of every finest cell: the number of leaf starts up to and
+// including it, minus one
+__global__ void cell_leaf_kernel(const uint32_t *__restrict__ lid, const uint32_t *__restrict__ flag,
+                                 uint32_t ncell, uint32_t *__restrict__ leafc) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < ncell; f += gridDim.x * blockDim.x)
+    leafc[f] = lid[f] + flag[f] - 1u;
+}
+
+// leaf_of[i] = leafc[cell[i]], four photons per thread and step (cell is
+// scratch, 256-byte aligned; leaf_of takes 16-byte stores when aligned)
+__global__ void leaf_of_kernel(const uint32_t *__restrict__ cell, uint64_t n, const uint32_t *__restrict__ leafc,
+                               uint32_t *__restrict__ leaf_of, int vec_store) {
+  const uint64_t n4 = n / 4;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n4;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t c = cell[i];
-    leaf_of[i] = lid[c] + flag[c] - 1u;
+    const uint4 c = reinterpret_cast<const uint4 *>(cell)[i];
+    const uint4 v = make_uint4(leafc[c.x], leafc[c.y], leafc[c.z], leafc[c.w]);
+    if (vec_store) {
+      reinterpret_cast<uint4 *>(leaf_of)[i] = v;
+    } else {
+      leaf_of[4 * i] = v.x;
+      leaf_of[4 * i + 1] = v.y;
+      leaf_of[4 * i + 2] = v.z;
+      leaf_of[4 * i + 3] = v.w;
+    }
   }
+  const uint64_t t = 4 * n4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (t < n) leaf_of[t] = leafc[cell[t]];
 }
 
 // ---------------------------------------------------------- radix sort
@@ -200,6 +260,10 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *__r
 }
 
 // Stable scatter of one tile.  vals == NULL: the value is the item index.
+// The tile is first ordered by digit in LDS (ranks from wavefront ballots,
+// waves and rounds in item order, so equal digits keep their input order),
+// then streamed out: consecutive LDS entries of one digit go to consecutive
+// global positions, so the writes form runs instead of single words.
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *__restrict__ key,
                                                                 const uint32_t *__restrict__ vals, uint64_t n,
                                                                 int shift, uint32_t nblocks,
@@ -207,22 +271,41 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
                                                                 uint32_t *__restrict__ key_out,
                                                                 uint32_t *__restrict__ val_out) {
   __shared__ uint32_t cnt[RS_THREADS / 64][256];
+  __shared__ uint32_t tile_off[256];  // first LDS slot of each digit
+  __shared__ uint32_t gdst[256];      // global position of that slot
+  __shared__ uint32_t lkey[RS_TILE], lval[RS_TILE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int w = 0; w < RS_THREADS / 64; ++w) cnt[w][threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t wbase = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)wave * RS_WAVE_ITEMS;
+  const uint64_t tbase = (uint64_t)blockIdx.x * RS_TILE;
+  const uint64_t wbase = tbase + (uint64_t)wave * RS_WAVE_ITEMS;
   for (int k = lane; k < RS_WAVE_ITEMS; k += 64) {
     const uint64_t i = wbase + k;
     if (i < n) atomicAdd(&cnt[wave][(key[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  {  // per-wave base offsets for digit d = threadIdx.x
+  {  // digit d = threadIdx.x: its tile count, then per-wave starts
     const int d = threadIdx.x;
-    uint32_t run = offs[(uint64_t)d * nblocks + blockIdx.x];
+    uint32_t c = 0;
+    for (int w = 0; w < RS_THREADS / 64; ++w) c += cnt[w][d];
+    // exclusive scan of the 256 digit counts
+    __shared__ uint32_t ws[RS_THREADS / 64];
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - c;
+    for (int w = 0; w < wave; ++w) run += ws[w];
+    tile_off[d] = run;
+    gdst[d] = offs[(uint64_t)d * nblocks + blockIdx.x];
     for (int w = 0; w < RS_THREADS / 64; ++w) {
-      const uint32_t c = cnt[w][d];
+      const uint32_t cw = cnt[w][d];
       cnt[w][d] = run;
-      run += c;
+      run += cw;
     }
   }
   __syncthreads();
@@ -245,11 +328,20 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
     __builtin_amdgcn_wave_barrier();
     if (act) {
       const uint32_t pos = basev + rank;
-      key_out[pos] = kk;
-      val_out[pos] = vals ? vals[i] : (uint32_t)i;
+      lkey[pos] = kk;
+      lval[pos] = vals ? vals[i] : (uint32_t)i;
       if (rank == 0) cnt[wave][dg] = basev + tot;
     }
     __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  const uint32_t nt = (uint32_t)min((uint64_t)RS_TILE, n - tbase);
+  for (uint32_t j = threadIdx.x; j < nt; j += RS_THREADS) {
+    const uint32_t kk = lkey[j];
+    const uint32_t dg = (kk >> shift) & 255u;
+    const uint32_t pos = gdst[dg] + (j - tile_off[dg]);
+    key_out[pos] = kk;
+    val_out[pos] = lval[j];
   }
 }
 
@@ -323,9 +415,30 @@ extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t 
   uint32_t *btmp = cv.take<uint32_t>((scan_max + SCAN_TILE - 1) / SCAN_TILE + 1);
 
   NPG_HIP_CHECK(ctx, hipMemsetAsync(cnt, 0, 4 * ((size_t)ncell + 1), s));
+  // up to 8 cell ranges (depth <= 6) the LDS histogram reads the cell ids
+  // once per range; deeper trees spread their photons over enough cells for
+  // direct atomics
+  const uint32_t nranges = (ncell + HIST_RANGE - 1) / HIST_RANGE;
+  const bool lds_hist = nranges <= 8;
   if (n)
-    hipLaunchKernelGGL(cells_kernel, dim3(grid_of(n)), dim3(256), 0, s, pos_dev, n, D, cell, cnt, ctx->err_dev);
+    hipLaunchKernelGGL(cells_kernel, dim3(grid_of(n)), dim3(256), 0, s, pos_dev, n, D, cell,
+                       lds_hist ? nullptr : cnt, ctx->err_dev);
   NPG_HIP_CHECK(ctx, hipGetLastError());
+  if (n && lds_hist) {
+    static bool attr = false;
+    if (!attr) {
+      NPG_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cell_hist_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, HIST_RANGE * 4));
+      attr = true;
+    }
+    // about 1024 workgroups; slices of at least 16k photons, multiples of 4
+    const uint64_t slices = std::max<uint64_t>(1, std::min<uint64_t>(1024 / nranges, (n + 16383) / 16384));
+    const uint64_t per_slice = ((n + slices - 1) / slices + 3) & ~(uint64_t)3;
+    const uint32_t ns = (uint32_t)((n + per_slice - 1) / per_slice);
+    hipLaunchKernelGGL(cell_hist_kernel, dim3(nranges, ns), dim3(HIST_THREADS), HIST_RANGE * 4, s, cell, n, ncell,
+                       per_slice, cnt);
+    NPG_HIP_CHECK(ctx, hipGetLastError());
+  }
   NPG_HIP_CHECK(ctx, scan_u32(cnt, ncell, cstart, btmp, s));
   hipLaunchKernelGGL(decide_kernel, dim3(grid_of(ncell)), dim3(256), 0, s, cstart, ncell, D, params->split_count,
                      flag, ldepth);
@@ -347,7 +460,11 @@ extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t 
     return npg_fail(ctx, NPG_E_CAPACITY, "build_hierarchy: %u leaves exceed max_leaves %u", L, max_leaves);
   if (n == 0) return NPG_OK;
   uint32_t *lof = leaf_of_dev ? leaf_of_dev : lof_own;
-  hipLaunchKernelGGL(leaf_of_kernel, dim3(grid_of(n)), dim3(256), 0, s, cell, n, lid, flag, lof);
+  uint32_t *leafc = cnt;  // the histogram is no longer needed
+  hipLaunchKernelGGL(cell_leaf_kernel, dim3(grid_of(ncell)), dim3(256), 0, s, lid, flag, ncell, leafc);
+  NPG_HIP_CHECK(ctx, hipGetLastError());
+  hipLaunchKernelGGL(leaf_of_kernel, dim3(grid_of((n + 3) / 4)), dim3(256), 0, s, cell, n, leafc, lof,
+                     ((uintptr_t)lof & 15) == 0 ? 1 : 0);
   NPG_HIP_CHECK(ctx, hipGetLastError());
   // stable radix sort of (leaf id, index) -> perm
   int bits = 1;

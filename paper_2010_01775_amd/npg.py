@@ -214,15 +214,23 @@ class CdfTables:
 
 
 def build_hierarchy(ctx: Context, pos, split_count: int = 8192, max_depth: int = 6,
-                    max_leaves: int | None = None, want_leaf_of: bool = True, stream=None):
-    """Octree leaves of the photon positions; returns a dict of device tensors."""
+                    max_leaves: int | None = None, want_leaf_of: bool = True, stream=None,
+                    leaf_of_out=None):
+    """Octree leaves of the photon positions; returns a dict of device tensors.
+    leaf_of_out: optional caller tensor (int32 [n]) for the per-photon leaf ids."""
     _dev(pos, torch.float32, "pos")
     n = pos.shape[0]
     dev = pos.device
     if max_leaves is None:
         max_leaves = max(1, min(n, 8 ** max_depth))
     perm = torch.empty(n, dtype=torch.int32, device=dev)
-    leaf_of = torch.empty(n, dtype=torch.int32, device=dev) if want_leaf_of else None
+    if leaf_of_out is not None:
+        _dev(leaf_of_out, torch.int32, "leaf_of_out")
+        if leaf_of_out.shape != (n,):
+            raise ValueError("leaf_of_out must have shape (n,)")
+        leaf_of = leaf_of_out
+    else:
+        leaf_of = torch.empty(n, dtype=torch.int32, device=dev) if want_leaf_of else None
     off = torch.empty(max_leaves + 1, dtype=torch.int32, device=dev)
     key = torch.empty(max_leaves, dtype=torch.int64, device=dev)
     depth = torch.empty(max_leaves, dtype=torch.uint8, device=dev)

@@ -48,6 +48,17 @@ def test_hierarchy_edges(ctx, npg, orc):
     assert out["n_leaves"] == 0 and out["leaf_off"].cpu().tolist() == [0]
 
 
+def test_hierarchy_leaf_of_unaligned_output(ctx, npg):
+    """leaf_of written into a caller buffer that is not 16-byte aligned."""
+    pts = _pts(7, 10003)
+    buf = torch.full((pts.shape[0] + 1,), -1, dtype=torch.int32, device=DEV)
+    out = npg.build_hierarchy(ctx, torch.from_numpy(pts).to(DEV), 64, 5, leaf_of_out=buf[1:])
+    ref = npg.build_hierarchy(ctx, torch.from_numpy(pts).to(DEV), 64, 5)
+    assert npg.sync_status(ctx) == 0
+    assert buf[0].item() == -1
+    assert torch.equal(buf[1:], ref["leaf_of"]) and torch.equal(out["perm"], ref["perm"])
+
+
 def test_hierarchy_errors(ctx, npg):
     pos = torch.from_numpy(_pts(0, 5000)).to(DEV)
     with pytest.raises(npg.NpgError) as e:

@@ -5,9 +5,11 @@
 //   S = sum s;  p = s / S;  pdf = p*H*W/(4 pi)
 //   row mass m_i = sum_j p_ij, marginal M_i = sum_{i'<i} m_i' (M_H = 1)
 //   conditional C_ij = sum_{j'<j} p_ij' / m_i (C_iW = 1; j/W if m_i = 0)
-// A row is scanned by one wavefront: each lane takes a contiguous segment,
-// scans it serially, and a wavefront-wide exclusive scan of the segment
-// totals gives each lane its offset.
+// The quotients are taken as products with binary64 reciprocals of S and
+// m_i (one more binary64 rounding, far below the float32 rounding of the
+// stored values).  A row is scanned by one wavefront in slices of 64
+// consecutive bins (coalesced loads and stores): a wavefront scan per slice
+// plus the running total of the slices before it.
 #include <math.h>
 
 #include "npg_internal.h"
@@ -55,7 +57,7 @@ struct DescOut {
   }
 };
 
-template <class OUT>
+template <class OUT, int SEG>
 __global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restrict__ dens, int H, int W, OUT out,
                                                           uint32_t *err) {
   extern __shared__ double rowmass[];  // [H]
@@ -94,36 +96,44 @@ __global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restric
     }
     return;
   }
-  const double pdf_scale = (double)HW;
-  // rows: one wavefront per row
-  const int seg = (W + 63) / 64;  // elements per lane
+  const double invS = 1.0 / S;
+  const double pdf_k = (double)HW / FOUR_PI;
+  // rows: one wavefront per row, bins j = 64 t + lane of slice t
   for (int i = wave; i < H; i += 4) {
     const float *srow = s + (size_t)i * W;
-    const int j0 = lane * seg;
-    double part = 0.0;
-    for (int t = 0; t < seg; ++t) {
-      const int j = j0 + t;
-      if (j < W) {
-        const double p = (double)srow[j] / S;
-        pl[(size_t)i * W + j] = (float)(p * pdf_scale / FOUR_PI);
-        part += p;
+    float *prow = pl + (size_t)i * W;
+    double c[SEG];  // exclusive prefix of p over the row at this lane's bins
+    double run = 0.0;
+#pragma unroll
+    for (int t = 0; t < SEG; ++t) {
+      const int j = 64 * t + lane;
+      const double p = j < W ? (double)srow[j] * invS : 0.0;
+      if (j < W) prow[j] = (float)(p * pdf_k);
+      double incl = p;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
       }
+      // the previous lane's inclusive sum: non-decreasing along the row
+      double ex = __shfl_up(incl, 1);
+      if (lane == 0) ex = 0.0;
+      c[t] = run + ex;
+      run += __shfl(incl, 63);
     }
-    const double m = wave_sum(part);
-    const double before = wave_excl_scan(part, lane);
+    const double m = run;
     float *crow = cl + (size_t)i * (W + 1);
     if (m > 0.0) {
-      double c = before;
-      for (int t = 0; t < seg; ++t) {
-        const int j = j0 + t;
-        if (j < W) {
-          crow[j] = (float)(c / m);
-          c += (double)srow[j] / S;
-        }
+      const double invm = 1.0 / m;
+#pragma unroll
+      for (int t = 0; t < SEG; ++t) {
+        const int j = 64 * t + lane;
+        if (j < W) crow[j] = (float)(c[t] * invm);
       }
     } else {
-      for (int t = 0; t < seg; ++t) {
-        const int j = j0 + t;
+#pragma unroll
+      for (int t = 0; t < SEG; ++t) {
+        const int j = 64 * t + lane;
         if (j < W) crow[j] = (float)((double)j / (double)W);
       }
     }
@@ -155,18 +165,29 @@ __global__ __launch_bounds__(CDF_THREADS) void cdf_kernel(const float *__restric
   }
 }
 
+template <class OUT>
+hipError_t launch_cdf_t(const float *density, uint32_t L, int H, int W, const OUT &o, uint32_t *err,
+                        hipStream_t s) {
+  const size_t lds = sizeof(double) * H;
+  const int seg = (W + 63) / 64;  // W is a power of two in [4, 1024]
+  switch (seg) {
+    case 1: hipLaunchKernelGGL((cdf_kernel<OUT, 1>), dim3(L), dim3(CDF_THREADS), lds, s, density, H, W, o, err); break;
+    case 2: hipLaunchKernelGGL((cdf_kernel<OUT, 2>), dim3(L), dim3(CDF_THREADS), lds, s, density, H, W, o, err); break;
+    case 4: hipLaunchKernelGGL((cdf_kernel<OUT, 4>), dim3(L), dim3(CDF_THREADS), lds, s, density, H, W, o, err); break;
+    case 8: hipLaunchKernelGGL((cdf_kernel<OUT, 8>), dim3(L), dim3(CDF_THREADS), lds, s, density, H, W, o, err); break;
+    default: hipLaunchKernelGGL((cdf_kernel<OUT, 16>), dim3(L), dim3(CDF_THREADS), lds, s, density, H, W, o, err);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_build_cdf(const float *density, uint32_t L, int H, int W, float *pdf, float *marg,
                             float *cond, double *total, uint32_t *err, hipStream_t s) {
-  hipLaunchKernelGGL(cdf_kernel<BatchOut>, dim3(L), dim3(CDF_THREADS), sizeof(double) * H, s, density, H, W,
-                     BatchOut{pdf, marg, cond, total}, err);
-  return hipGetLastError();
+  return launch_cdf_t(density, L, H, W, BatchOut{pdf, marg, cond, total}, err, s);
 }
 
 hipError_t launch_build_cdf_desc(const float *density, const npg_leaf_desc *d, uint32_t L, int H, int W,
                                  uint32_t *err, hipStream_t s) {
-  hipLaunchKernelGGL(cdf_kernel<DescOut>, dim3(L), dim3(CDF_THREADS), sizeof(double) * H, s, density, H, W,
-                     DescOut{d}, err);
-  return hipGetLastError();
+  return launch_cdf_t(density, L, H, W, DescOut{d}, err, s);
 }

@@ -293,6 +293,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--experts", action="store_true",
+                    help="five U-Nets chosen by leaf photon count ([0,100), [100,500), [500,1000), "
+                         "[1000,5000), [5000,inf)) instead of one")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -333,6 +336,7 @@ def main():
         desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, octree split > 8192 depth <= 6 "
                 f"({L} leaves), 128x128 maps, U-Net 16/32/64/128, 1e8 guided samples")
     model = npg.Model(ctx, model_bytes)
+    experts = [model] + [npg.Model(ctx, synth.unet_model(2000 + k)) for k in range(4)] if args.experts else None
     nq = q_leaf.shape[0]
     flops_leaf = model_flops_per_leaf(model_bytes, H, W)
 
@@ -359,6 +363,8 @@ def main():
     ev = {s: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for s in stages}
     stream = torch.cuda.current_stream()
 
+    expert_leaves = [0] * 5
+
     def step(record):
         def mark(s, i):
             if record:
@@ -381,7 +387,11 @@ def main():
             npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
         mark("splat", 1)
         mark("recon", 0)
-        npg.reconstruct_density(ctx, model, energy, args.precision, count=count, density=dens)
+        if experts:
+            lo = hier_out["off"][:L + 1] if pos is not None else off
+            _, expert_leaves[:] = npg.reconstruct_experts(ctx, experts, lo, energy, args.precision, density=dens)
+        else:
+            npg.reconstruct_density(ctx, model, energy, args.precision, count=count, density=dens)
         mark("recon", 1)
         mark("cdf", 0)
         npg.build_cdf(ctx, dens, out=tabs)
@@ -401,11 +411,13 @@ def main():
             npg.splat_histograms(ctx, dirs, w, lo_, H, W, perm=out["perm"], energy=energy, count=count)
         else:
             npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
-        model.calibrate_fp8(energy[::16][:256].contiguous())
+        for m in experts or [model]:
+            m.calibrate_fp8(energy[::16][:256].contiguous())
     tune = None
     if not args.no_autotune:
         # per-layer pixel tiles and leaf-chunk size, chosen once before timing
-        tune = npg.autotune(ctx, model, H, W, args.precision, probe_leaves=min(L, 1024))
+        for m in experts or [model]:
+            tune = npg.autotune(ctx, m, H, W, args.precision, probe_leaves=min(L, 1024))
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -449,7 +461,7 @@ def main():
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
     src_sha = sha_of(os.path.join(ROOT, "paper_2010_01775_amd", "csrc", "net.hip"))
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and not args.experts:
         t = json.load(open(tfile))
         if t.get("source_sha") == src_sha:
             traffic = t.get("bytes_per_launch")
@@ -471,7 +483,9 @@ def main():
                    "precision": {"fp32": "fp32 weights, f64 activations and conv accumulation",
                                  "bf16": "bf16 conv, f32 accumulation",
                                  "fp8": "fp8 e4m3 conv (static per-layer activation scales, "
-                                        "per-output-channel weight scales), f32 accumulation"}[args.precision]},
+                                        "per-output-channel weight scales), f32 accumulation"}[args.precision]}
+                  | ({"experts": "5 U-Nets by leaf photon count [0,100) [100,500) [500,1000) [1000,5000) "
+                                 "[5000,inf)", "expert_leaves": expert_leaves} if experts else {}),
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
         "p50_ms": float(np.percentile(per_step, 50)),

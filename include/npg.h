@@ -108,7 +108,8 @@ void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak);
  *   "graphs"       1: npg_reconstruct_fused captures its launches into a HIP
  *                  graph on the second call with the same arguments on a
  *                  non-default stream and replays it afterwards (default 0)
- *   "chunk_leaves" leaves per network chunk; 0 = autotuned or 1024
+ *   "chunk_leaves" leaves per network chunk (and at most per gather batch
+ *                  of npg_reconstruct_experts); 0 = autotuned or 1024
  *   "force_direct" 1: direct convolutions only (testing; default 0)
  *   "fuse_first"   0: store the first layer's activations instead of
  *                  computing them inside the second layer's input staging
@@ -218,6 +219,28 @@ int npg_normalize_input(npg_ctx *ctx, const uint64_t *energy_dev, uint32_t L, in
 int npg_reconstruct_density(npg_ctx *ctx, const npg_model *model, const uint64_t *energy_dev,
                             const uint32_t *count_dev, uint32_t L, int H, int W,
                             npg_precision precision, float *density_dev, void *stream);
+
+/* Mixture of experts by leaf photon count (Sec. 8, Implementation, training: five
+ * networks, each for one range of photons per voxel, [0,100), [100,500),
+ * [500,1000), [1000,5000) and [5000,inf)).  Leaf l holds
+ * n_l = leaf_off[l+1] - leaf_off[l] photons and goes to expert
+ * e = #{k : bounds[k] <= n_l}; its density is that of
+ * npg_reconstruct_density with models[e] (bit for bit: each expert's leaves
+ * are gathered, in leaf order, into one batch run by the same kernels, and
+ * the densities are scattered back).
+ *   models       host array of n_experts model handles, 1 <= n_experts <= 8
+ *                (the same precision must be usable with each: FP8 needs
+ *                every model calibrated)
+ *   bounds       host array of n_experts - 1 strictly increasing counts
+ *   leaf_off_dev [L+1] uint32 leaf CSR offsets (as in npg_splat_histograms)
+ *   energy_dev   [L][H][W] uint64;  density_dev [L][H][W] float32 out
+ *   counts_out   host array of n_experts (leaves per expert) or NULL
+ * Synchronises `stream` once (the leaves per expert size the launches) and
+ * holds gather buffers for the call's duration (within the budget). */
+int npg_reconstruct_experts(npg_ctx *ctx, const npg_model *const *models, int n_experts,
+                            const uint32_t *bounds, const uint32_t *leaf_off_dev, const uint64_t *energy_dev,
+                            uint32_t L, int H, int W, npg_precision precision, float *density_dev,
+                            uint32_t *counts_out, void *stream);
 
 /* The batched form of the path: splat -> normalise -> network -> CDF for a
  * batch of leaves of uneven photon counts, processed in chunks whose energy

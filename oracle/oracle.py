@@ -111,6 +111,35 @@ def net_forward(model: bytes, x):
     return rc, s
 
 
+def expert_of(photons, bounds):
+    """Mixture of experts by photon count (Sec. 8, Implementation, training):
+    expert e is responsible for the range [lo_e, hi_e) of photons per voxel,
+    lo_0 = 0, lo_e = bounds[e-1], hi_e = bounds[e], hi_last = infinity.
+    Returns, per count, the index of the range that holds it."""
+    los = [0] + [int(b) for b in bounds]
+    his = [int(b) for b in bounds] + [None]
+    out = []
+    for n in np.asarray(photons).ravel().tolist():
+        e = next(i for i, (lo, hi) in enumerate(zip(los, his)) if lo <= n and (hi is None or n < hi))
+        out.append(e)
+    return np.array(out, dtype=np.int64)
+
+
+def experts_forward(models, photons, bounds, x):
+    """Each leaf's map through the network of its expert (net_forward per
+    expert on that expert's leaves)."""
+    x = _c(x, np.float64)
+    e = expert_of(photons, bounds)
+    out = np.empty_like(x)
+    for k, model in enumerate(models):
+        sel = np.nonzero(e == k)[0]
+        if sel.size:
+            rc, out[sel] = net_forward(model, x[sel])
+            if rc:
+                return rc, out
+    return OK, out
+
+
 def conv2d(w, b, x):
     """One conv layer: w [co,ci,k,k] f32, b [co] f32 or None, x [ci,H,W] f64."""
     w = _c(w, np.float32)

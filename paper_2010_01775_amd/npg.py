@@ -24,7 +24,7 @@ SYMBOLS = [
     "npg_create", "npg_destroy", "npg_last_error", "npg_sync_status", "npg_memory_usage",
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
     "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
-    "npg_reconstruct_density", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
+    "npg_reconstruct_density", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
     "npg_serve_create", "npg_serve_destroy", "npg_serve_submit_recon", "npg_serve_submit_sample",
     "npg_serve_poll", "npg_serve_wait", "npg_serve_tables", "npg_serve_copy_tables", "npg_serve_release",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "npg_splat_histograms": (I, [P, P, P, P, P, U32, I, I, P, P, I, P]),
         "npg_normalize_input": (I, [P, P, U32, I, I, P, P]),
         "npg_reconstruct_density": (I, [P, P, P, P, U32, I, I, I, P, P]),
+        "npg_reconstruct_experts": (I, [P, P, I, P, P, P, U32, I, I, I, P, P, P]),
         "npg_build_cdf": (I, [P, P, U32, I, I, P, P, P, P, P]),
         "npg_sample_dirs": (I, [P, C.POINTER(Tables), P, P, U64, P, P, P, P]),
         "npg_eval_pdf": (I, [P, C.POINTER(Tables), P, P, U64, P, P]),
@@ -279,6 +280,31 @@ def reconstruct_density(ctx: Context, model: Model, energy, precision="fp32", co
     ctx.check(ctx.lib.npg_reconstruct_density(ctx.h, model.h, _ptr(energy), _ptr(count), L, H, W, p,
                                               _ptr(density), _stream(stream)))
     return density
+
+
+# photon-count ranges of the five experts: [0,100), [100,500), [500,1000),
+# [1000,5000), [5000,inf)
+PAPER_EXPERT_BOUNDS = (100, 500, 1000, 5000)
+
+
+def reconstruct_experts(ctx: Context, models, leaf_off, energy, precision="fp32",
+                        bounds=PAPER_EXPERT_BOUNDS, density=None, stream=None):
+    """Densities with one model per photon-count range; returns
+    (density, leaves per expert)."""
+    _dev(leaf_off, torch.int32, "leaf_off")
+    L, H, W = energy.shape
+    if leaf_off.shape != (L + 1,):
+        raise ValueError("leaf_off must have L + 1 entries")
+    if density is None:
+        density = torch.empty((L, H, W), dtype=torch.float32, device=energy.device)
+    n = len(models)
+    hs = (C.c_void_p * n)(*[m.h for m in models])
+    bd = (C.c_uint32 * max(1, len(bounds)))(*bounds)
+    counts = (C.c_uint32 * n)()
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.lib.npg_reconstruct_experts(ctx.h, hs, n, bd, _ptr(leaf_off), _ptr(energy), L, H, W, p,
+                                              _ptr(density), counts, _stream(stream)))
+    return density, list(counts)
 
 
 def _new_tables(L, H, W, dev):

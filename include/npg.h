@@ -309,6 +309,48 @@ int npg_sample_dirs(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf
 int npg_eval_pdf(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf_dev,
                  const float *dir_dev, uint64_t n, float *pdf_out_dev, void *stream);
 
+/* One-sample MIS of BSDF sampling and guiding (Sec. 7.3, Eq. "mis_alpha"
+ * and Eq. "mis_coef").  Per leaf j, from the path statistics of its bounces:
+ * nu_B, nu_G = summed contributions of bounces whose direction came from
+ * BSDF / guided sampling, Q_B, Q_G = their numbers:
+ *   alpha_j = (nu_B/Q_B) / (nu_B/Q_B + nu_G/Q_G) once Q_B >= 50 and
+ *   Q_G >= 50 (0.5 before, and 0.5 if both averages are 0), clamped to
+ *   [0.2, 0.8]; computed in FP64, stored as float32.
+ *   nu_b_dev, nu_g_dev [L] float32 (>= 0);  q_b_dev, q_g_dev [L] uint32
+ *   alpha_dev [L] float32 out
+ * A negative or non-finite contribution flags NPG_E_RANGE and gives 0.5. */
+int npg_mis_alpha(npg_ctx *ctx, const float *nu_b_dev, const float *nu_g_dev, const uint32_t *q_b_dev,
+                  const uint32_t *q_g_dev, uint32_t L, float *alpha_dev, void *stream);
+
+/* One-sample MIS sampling with a cosine-lobe BSDF about a per-query normal
+ * (the stand-in BSDF, p_BSDF(w) = max(0, n.w)/pi):
+ *   u = (u0, u1, u2) in [0,1)^3;  a = alpha[l]
+ *   u0 < a: BSDF sample, r = sqrt(u1), phi = 2 pi u2,
+ *           w = r cos(phi) t + r sin(phi) b + sqrt(1 - u1) n with the
+ *           orthonormal frame (t, b, n) of Duff et al. 2017 (JCGT 6(1));
+ *   else:   the guided sample of npg_sample_dirs from (u1, u2);
+ *   pdf = a p_BSDF(w) + (1 - a) p_guide(w), p_guide = pdf[l][bin] with the
+ *   sampled bin for guided samples and the bin rule of npg_splat_histograms
+ *   for BSDF samples.
+ *   alpha_dev [L];  leaf_dev [n];  normal_dev [n][3] (unit);  u_dev [n][3]
+ *   dir_out_dev [n][3] out;  pdf_out_dev [n] out;  strategy_out_dev [n]
+ *   uint8 out (1 = BSDF, 0 = guided) or NULL
+ * leaf >= L, a uniform outside [0,1) or a non-finite normal flags
+ * NPG_E_RANGE; that query's direction and pdf are NaN. */
+int npg_sample_mis(npg_ctx *ctx, const npg_tables *tables, const float *alpha_dev, const uint32_t *leaf_dev,
+                   const float *normal_dev, const float *u_dev, uint64_t n, float *dir_out_dev,
+                   float *pdf_out_dev, uint8_t *strategy_out_dev, void *stream);
+
+/* The one-sample MIS pdf of directions (Eq. "mis_coef" with the cosine-lobe
+ * BSDF): a p_BSDF(w) + (1 - a) pdf[l][bin(w)], a = alpha[l].
+ *   alpha_dev [L];  leaf_dev [n];  normal_dev [n][3];  dir_dev [n][3]
+ *   pdf_out_dev [n] out
+ * leaf >= L or a non-finite direction or normal flags NPG_E_RANGE; pdf 0
+ * there. */
+int npg_eval_pdf_mis(npg_ctx *ctx, const npg_tables *tables, const float *alpha_dev, const uint32_t *leaf_dev,
+                     const float *normal_dev, const float *dir_dev, uint64_t n, float *pdf_out_dev,
+                     void *stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A server takes reconstruction and sampling requests as a render loop emits

@@ -189,6 +189,103 @@ def eval_pdf(pdf, leaf, dirs):
     return rc, out
 
 
+# ------------------------------------------------------- one-sample MIS
+MIS_MIN_PATHS = 50          # both strategies need this many bounces (Sec. 7.3)
+MIS_CLAMP = (0.2, 0.8)      # alpha is clamped to this range (Sec. 7.3)
+
+
+def mis_alpha(nu_b, nu_g, q_b, q_g):
+    """Eq. mis_alpha: alpha_j = nu_bar_B / (nu_bar_B + nu_bar_G), nu_bar =
+    nu / Q, once Q_B and Q_G reach MIS_MIN_PATHS (0.5 before, and 0.5 when
+    both averages are zero), clamped to MIS_CLAMP; binary64, stored as
+    float32.  Returns (rc, alpha); a negative or non-finite contribution
+    gives E_RANGE and 0.5 for that leaf."""
+    out = []
+    rc = OK
+    for nb, ng, qb, qg in zip(np.asarray(nu_b, np.float64).tolist(), np.asarray(nu_g, np.float64).tolist(),
+                              np.asarray(q_b).tolist(), np.asarray(q_g).tolist()):
+        if not (np.isfinite(nb) and np.isfinite(ng) and nb >= 0.0 and ng >= 0.0):
+            rc = E_RANGE
+            out.append(0.5)
+            continue
+        a = 0.5
+        if qb >= MIS_MIN_PATHS and qg >= MIS_MIN_PATHS:
+            mb, mg = nb / qb, ng / qg
+            if mb + mg > 0.0:
+                a = mb / (mb + mg)
+        out.append(min(max(a, MIS_CLAMP[0]), MIS_CLAMP[1]))
+    return rc, np.array(out, dtype=np.float32)
+
+
+def onb(n):
+    """Orthonormal frame (t, b) completing the unit normal n (Duff et al.,
+    Building an Orthonormal Basis, Revisited, JCGT 6(1), 2017)."""
+    n = np.asarray(n, np.float64)
+    nx, ny, nz = n[:, 0], n[:, 1], n[:, 2]
+    sign = np.where(nz >= 0.0, 1.0, -1.0)
+    a = -1.0 / (sign + nz)
+    b = nx * ny * a
+    t = np.stack([1.0 + sign * nx * nx * a, sign * b, -sign * nx], axis=1)
+    bt = np.stack([b, sign + ny * ny * a, -ny], axis=1)
+    return t, bt
+
+
+def cosine_sample(n, u1, u2):
+    """Cosine-weighted direction about n: disk point (sqrt(u1), 2 pi u2)
+    lifted to the hemisphere (Malley's method)."""
+    n = np.asarray(n, np.float64)
+    u1 = np.asarray(u1, np.float64)
+    u2 = np.asarray(u2, np.float64)
+    t, bt = onb(n)
+    r = np.sqrt(u1)
+    phi = 2.0 * np.pi * u2
+    h = np.sqrt(np.maximum(0.0, 1.0 - u1))
+    return (r * np.cos(phi))[:, None] * t + (r * np.sin(phi))[:, None] * bt + h[:, None] * n
+
+
+def cosine_pdf(n, w):
+    """p_BSDF of the cosine lobe: max(0, n.w) / pi."""
+    c = np.sum(np.asarray(n, np.float64) * np.asarray(w, np.float64), axis=1)
+    return np.maximum(0.0, c) / np.pi
+
+
+def eval_pdf_mis(pdf, alpha, leaf, normal, dirs):
+    """Eq. mis_coef: a p_BSDF(w) + (1 - a) pdf[l][bin(w)], a = alpha[l]."""
+    a = np.asarray(alpha, np.float64)[np.asarray(leaf, np.int64)]
+    rc, g = eval_pdf(pdf, leaf, dirs)
+    return rc, a * cosine_pdf(normal, dirs) + (1.0 - a) * g.astype(np.float64)
+
+
+def sample_mis(pdf, marg, cond, alpha, leaf, normal, u):
+    """One-sample MIS: u0 < alpha[l] picks the BSDF (cosine lobe from
+    (u1, u2)), else the guided sample of `sample` from (u1, u2); the pdf is
+    the mixture, with the guide term of the sampled bin for guided samples
+    and of bin(w) (w rounded to float32) for BSDF samples.  Returns
+    (rc, dirs, pdf, strategy) with strategy 1 = BSDF."""
+    u = np.asarray(u, np.float32)
+    leaf = np.asarray(leaf, np.uint32)
+    alpha = np.asarray(alpha, np.float32)
+    n = u.shape[0]
+    L = pdf.shape[0]
+    ok = leaf < L
+    a32 = np.where(ok, alpha[np.minimum(leaf, L - 1)], np.float32(0))
+    strat = (u[:, 0] < a32).astype(np.uint8)
+    rc, dg, pg, bg = sample(pdf, marg, cond, leaf, u[:, 1:3])
+    db = cosine_sample(normal, u[:, 1], u[:, 2])
+    d = np.where(strat[:, None] == 1, db, dg)
+    a = a32.astype(np.float64)
+    pb = cosine_pdf(normal, d)
+    rc2, g_b = eval_pdf(pdf, np.minimum(leaf, L - 1), d.astype(np.float32))
+    g = np.where(strat == 1, g_b.astype(np.float64), pg.astype(np.float64))
+    p = a * pb + (1.0 - a) * g
+    bad = ~ok | ~np.all((u >= 0) & (u < 1), axis=1) | ~np.all(np.isfinite(normal), axis=1)
+    d[bad] = np.nan
+    p[bad] = np.nan
+    if np.any(bad):
+        rc = E_RANGE
+    return rc, d, p, strat
+
+
 def build_tree(pos, T: int = 8192, Dmax: int = 6, max_leaves: int | None = None):
     pos = _c(pos, np.float32)
     n = pos.shape[0]

@@ -424,6 +424,39 @@ def main():
     if npg.sync_status(ctx) != 0:
         raise RuntimeError("data-dependent error during warm-up")
 
+    def mis_rates(reps=3):
+        """One-sample MIS on the final tables (outside the timed steps): the
+        guided queries' uniforms plus a fresh selection uniform, random unit
+        normals for the cosine-lobe BSDF, per-leaf alpha from synthetic path
+        statistics; samples/s and evaluations/s."""
+        g = torch.Generator(device=dev).manual_seed(4242)
+        normal = torch.randn((nq, 3), generator=g, device=dev)
+        normal /= normal.norm(dim=1, keepdim=True)
+        u3 = torch.cat([torch.rand((nq, 1), generator=g, device=dev), q_u.view(nq, 2)], 1).contiguous()
+        nu_b = torch.rand(L, generator=g, device=dev) * 4
+        nu_g = torch.rand(L, generator=g, device=dev) * 4
+        qcount = (torch.rand((2, L), generator=g, device=dev) * 200).to(torch.int32)
+        alpha = npg.mis_alpha(ctx, nu_b, nu_g, qcount[0].contiguous(), qcount[1].contiguous())
+        outs = (torch.empty((nq, 3), dtype=torch.float32, device=dev), torch.empty(nq, dtype=torch.float32, device=dev),
+                torch.empty(nq, dtype=torch.uint8, device=dev))
+        pe_m = torch.empty(nq, dtype=torch.float32, device=dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        ts, te = [], []
+        for r in range(reps + 1):
+            e0.record(stream)
+            npg.sample_mis(ctx, tabs, alpha, q_leaf, normal, u3, out=outs)
+            e1.record(stream)
+            npg.eval_pdf_mis(ctx, tabs, alpha, q_leaf, normal, outs[0], out=pe_m)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            if r:  # the first pass warms up
+                ts.append(e0.elapsed_time(e1))
+                te.append(e1.elapsed_time(e2))
+        if npg.sync_status(ctx) != 0:
+            raise RuntimeError("data-dependent error in the MIS calls")
+        return {"mis_samples_per_s": nq / (np.mean(ts) / 1e3), "mis_eval_per_s": nq / (np.mean(te) / 1e3),
+                "bsdf_fraction": float(outs[2].float().mean()), "mean_alpha": float(alpha.mean())}
+
     per_step, stage_ms = [], {s: [] for s in stages}
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -445,6 +478,7 @@ def main():
         raise RuntimeError("data-dependent error during the timed steps")
 
     avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
+    mis = mis_rates()
     recon_s = avg["recon"] / 1e3
     flops = flops_leaf * L
     if args.precision == "fp32":
@@ -488,6 +522,7 @@ def main():
                                  "[5000,inf)", "expert_leaves": expert_leaves} if experts else {}),
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
+        "one_sample_mis": mis,
         "p50_ms": float(np.percentile(per_step, 50)),
         "p99_ms": float(np.percentile(per_step, 99)),
         "stage_ms": avg,

@@ -259,4 +259,50 @@ int npg_eval_pdf(npg_ctx *ctx, const npg_tables *tables, const uint32_t *leaf_de
   return NPG_OK;
 }
 
+int npg_mis_alpha(npg_ctx *ctx, const float *nu_b_dev, const float *nu_g_dev, const uint32_t *q_b_dev,
+                  const uint32_t *q_g_dev, uint32_t L, float *alpha_dev, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  if (L == 0) return NPG_OK;
+  if (!nu_b_dev || !nu_g_dev || !q_b_dev || !q_g_dev || !alpha_dev)
+    return npg_fail(ctx, NPG_E_ARG, "mis_alpha: null pointer");
+  int rc = npg_set_device(ctx);
+  if (rc) return rc;
+  NPG_HIP_CHECK(ctx, launch_mis_alpha(nu_b_dev, nu_g_dev, q_b_dev, q_g_dev, L, alpha_dev, ctx->err_dev,
+                                      static_cast<hipStream_t>(stream)));
+  return NPG_OK;
+}
+
+int npg_sample_mis(npg_ctx *ctx, const npg_tables *tables, const float *alpha_dev, const uint32_t *leaf_dev,
+                   const float *normal_dev, const float *u_dev, uint64_t n, float *dir_out_dev,
+                   float *pdf_out_dev, uint8_t *strategy_out_dev, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_tables(ctx, tables, true);
+  if (rc) return rc;
+  if (n == 0) return NPG_OK;
+  if (!alpha_dev || !leaf_dev || !normal_dev || !u_dev || !dir_out_dev || !pdf_out_dev)
+    return npg_fail(ctx, NPG_E_ARG, "sample_mis: null pointer");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  NPG_HIP_CHECK(ctx, launch_sample_mis(ctx->bnd_dev, *tables, alpha_dev, leaf_dev, normal_dev, u_dev, n,
+                                       dir_out_dev, pdf_out_dev, strategy_out_dev, ctx->err_dev,
+                                       static_cast<hipStream_t>(stream)));
+  return NPG_OK;
+}
+
+int npg_eval_pdf_mis(npg_ctx *ctx, const npg_tables *tables, const float *alpha_dev, const uint32_t *leaf_dev,
+                     const float *normal_dev, const float *dir_dev, uint64_t n, float *pdf_out_dev,
+                     void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_tables(ctx, tables, false);
+  if (rc) return rc;
+  if (n == 0) return NPG_OK;
+  if (!alpha_dev || !leaf_dev || !normal_dev || !dir_dev || !pdf_out_dev)
+    return npg_fail(ctx, NPG_E_ARG, "eval_mis: null pointer");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  NPG_HIP_CHECK(ctx, launch_eval_mis(ctx->bnd_dev, *tables, alpha_dev, leaf_dev, normal_dev, dir_dev, n,
+                                     pdf_out_dev, ctx->err_dev, static_cast<hipStream_t>(stream)));
+  return NPG_OK;
+}
+
 }  // extern "C"

@@ -219,3 +219,11 @@ hipError_t launch_sample(const npg_tables &t, const uint32_t *leaf, const float 
                          float *dir, float *pdf, uint32_t *bin, uint32_t *err, hipStream_t s);
 hipError_t launch_eval(const float2 *bnd, const npg_tables &t, const uint32_t *leaf, const float *dir, uint64_t n,
                        float *pdf, uint32_t *err, hipStream_t s);
+hipError_t launch_mis_alpha(const float *nu_b, const float *nu_g, const uint32_t *q_b, const uint32_t *q_g,
+                            uint32_t L, float *alpha, uint32_t *err, hipStream_t s);
+hipError_t launch_sample_mis(const float2 *bnd, const npg_tables &t, const float *alpha, const uint32_t *leaf,
+                             const float *normal, const float *u, uint64_t n, float *dir, float *pdf,
+                             uint8_t *strat, uint32_t *err, hipStream_t s);
+hipError_t launch_eval_mis(const float2 *bnd, const npg_tables &t, const float *alpha, const uint32_t *leaf,
+                           const float *normal, const float *dir, uint64_t n, float *pdf, uint32_t *err,
+                           hipStream_t s);

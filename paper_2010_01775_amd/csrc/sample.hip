@@ -48,13 +48,45 @@ __device__ __forceinline__ int last_le(const float *__restrict__ t, int n, float
   return lo;
 }
 
+// The guided sample of leaf l from (u1, u2): direction, the table pdf of the
+// sampled bin and the bin (the leaf and the uniforms are valid).
+__device__ __forceinline__ void guided_sample(const float *__restrict__ pdf, const float *__restrict__ marg,
+                                              const float *__restrict__ cond, uint32_t l, int H, int W,
+                                              float u1, float u2, float *d, float *p, uint32_t *bin) {
+  const float below1 = __int_as_float(0x3f7fffff);
+  const float two_over_h = 2.0f / (float)H;
+  const float dphi = 6.283185307179586f / (float)W;
+  const float *M = marg + (size_t)l * (H + 1);
+  const int i = last_le(M, H, u1);
+  const float *C = cond + ((size_t)l * H + i) * (W + 1);
+  const int j = last_le(C, W, u2);
+  const float m0 = M[i], m1 = M[i + 1];
+  const float c0 = C[j], c1 = C[j + 1];
+  float t1 = (u1 - m0) / (m1 - m0);
+  float t2 = (u2 - c0) / (c1 - c0);
+  t1 = fminf(fmaxf(t1, 0.0f), below1);
+  t2 = fminf(fmaxf(t2, 0.0f), below1);
+  // -1 + 2i/H, 2i/H and 2(H-i)/H are exact; each of z, 1+z, 1-z takes
+  // one rounding, so sin(theta) = sqrt((1-z)(1+z)) stays accurate at the
+  // poles where 1 - z*z would cancel.
+  const float z = fmaf(t1, two_over_h, fmaf((float)i, two_over_h, -1.0f));
+  const float opz = fmaf(t1, two_over_h, (float)i * two_over_h);
+  const float omz = fmaf(-t1, two_over_h, (float)(H - i) * two_over_h);
+  const float phi = fmaf(t2, dphi, (float)j * dphi);
+  float sp, cp;
+  sincosf(phi, &sp, &cp);
+  const float r = sqrtf(fmaxf(0.0f, omz * opz));
+  d[0] = r * cp;
+  d[1] = r * sp;
+  d[2] = z;
+  *p = pdf[(size_t)l * H * W + (size_t)i * W + j];
+  *bin = (uint32_t)(i * W + j);
+}
+
 __global__ __launch_bounds__(256) void sample_kernel(
     const float *__restrict__ pdf, const float *__restrict__ marg, const float *__restrict__ cond,
     uint32_t L, int H, int W, const uint32_t *__restrict__ leaf, const float2 *__restrict__ u, uint64_t n,
     float *__restrict__ dir, float *__restrict__ pdf_out, uint32_t *__restrict__ bin_out, uint32_t *err) {
-  const float below1 = __int_as_float(0x3f7fffff);
-  const float two_over_h = 2.0f / (float)H;
-  const float dphi = 6.283185307179586f / (float)W;
   for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n;
        q += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t l = leaf[q];
@@ -69,31 +101,136 @@ __global__ __launch_bounds__(256) void sample_kernel(
       raise_err(err, ERR_RANGE);
       continue;
     }
-    const float *M = marg + (size_t)l * (H + 1);
-    const int i = last_le(M, H, uu.x);
-    const float *C = cond + ((size_t)l * H + i) * (W + 1);
-    const int j = last_le(C, W, uu.y);
-    const float m0 = M[i], m1 = M[i + 1];
-    const float c0 = C[j], c1 = C[j + 1];
-    float t1 = (uu.x - m0) / (m1 - m0);
-    float t2 = (uu.y - c0) / (c1 - c0);
-    t1 = fminf(fmaxf(t1, 0.0f), below1);
-    t2 = fminf(fmaxf(t2, 0.0f), below1);
-    // -1 + 2i/H, 2i/H and 2(H-i)/H are exact; each of z, 1+z, 1-z takes
-    // one rounding, so sin(theta) = sqrt((1-z)(1+z)) stays accurate at the
-    // poles where 1 - z*z would cancel.
-    const float z = fmaf(t1, two_over_h, fmaf((float)i, two_over_h, -1.0f));
-    const float opz = fmaf(t1, two_over_h, (float)i * two_over_h);
-    const float omz = fmaf(-t1, two_over_h, (float)(H - i) * two_over_h);
-    const float phi = fmaf(t2, dphi, (float)j * dphi);
-    float sp, cp;
-    sincosf(phi, &sp, &cp);
-    const float r = sqrtf(fmaxf(0.0f, omz * opz));
-    dir[3 * q] = r * cp;
-    dir[3 * q + 1] = r * sp;
-    dir[3 * q + 2] = z;
-    pdf_out[q] = pdf[(size_t)l * H * W + (size_t)i * W + j];
-    if (bin_out) bin_out[q] = (uint32_t)(i * W + j);
+    float d[3], p;
+    uint32_t b;
+    guided_sample(pdf, marg, cond, l, H, W, uu.x, uu.y, d, &p, &b);
+    dir[3 * q] = d[0];
+    dir[3 * q + 1] = d[1];
+    dir[3 * q + 2] = d[2];
+    pdf_out[q] = p;
+    if (bin_out) bin_out[q] = b;
+  }
+}
+
+// ------------------------------------------------------- one-sample MIS
+constexpr float INV_PI = 0.3183098861837907f;
+
+// alpha_j from the path statistics: FP64 quotient of the two averages once
+// both strategies have MIS_MIN bounces, clamped to [0.2, 0.8]
+constexpr uint32_t MIS_MIN = 50;
+__global__ void mis_alpha_kernel(const float *__restrict__ nu_b, const float *__restrict__ nu_g,
+                                 const uint32_t *__restrict__ q_b, const uint32_t *__restrict__ q_g, uint32_t L,
+                                 float *__restrict__ alpha, uint32_t *err) {
+  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x) {
+    const double nb = nu_b[l], ng = nu_g[l];
+    const uint32_t qb = q_b[l], qg = q_g[l];
+    if (!(nb >= 0.0 && ng >= 0.0 && isfinite(nb) && isfinite(ng))) {
+      alpha[l] = 0.5f;
+      raise_err(err, ERR_RANGE);
+      continue;
+    }
+    double a = 0.5;
+    if (qb >= MIS_MIN && qg >= MIS_MIN) {
+      const double mb = nb / (double)qb, mg = ng / (double)qg;
+      if (mb + mg > 0.0) a = mb / (mb + mg);
+    }
+    alpha[l] = (float)fmin(fmax(a, 0.2), 0.8);
+  }
+}
+
+// Cosine-lobe direction about the unit normal (nx, ny, nz) from (u1, u2):
+// disk point (sqrt(u1), 2 pi u2) lifted to the hemisphere, in the frame of
+// Duff et al. 2017 (sign of nz with +0 counted as positive)
+__device__ __forceinline__ void cosine_sample(float nx, float ny, float nz, float u1, float u2, float *w) {
+  const float sg = nz >= 0.0f ? 1.0f : -1.0f;
+  const float a = -1.0f / (sg + nz);
+  const float b = nx * ny * a;
+  const float tx = 1.0f + sg * nx * nx * a, ty = sg * b, tz = -sg * nx;
+  const float bx = b, by = sg + ny * ny * a, bz = -ny;
+  const float r = sqrtf(u1);
+  float sp, cp;
+  sincosf(6.283185307179586f * u2, &sp, &cp);
+  const float h = sqrtf(fmaxf(0.0f, 1.0f - u1));
+  const float x = r * cp, y = r * sp;
+  w[0] = x * tx + y * bx + h * nx;
+  w[1] = x * ty + y * by + h * ny;
+  w[2] = x * tz + y * bz + h * nz;
+}
+
+// The mixture a p_BSDF(w) + (1 - a) g, spelled out with explicit fused
+// multiply-adds so that sampling and evaluation round it identically
+// (contraction left to the compiler could differ between the two kernels).
+__device__ __forceinline__ float mis_mixture(float a, float nx, float ny, float nz, const float *w, float g) {
+  const float c = fmaf(nz, w[2], fmaf(ny, w[1], nx * w[0]));
+  const float pb = fmaxf(0.0f, c) * INV_PI;
+  return fmaf(a, pb, (1.0f - a) * g);
+}
+
+__global__ __launch_bounds__(256) void sample_mis_kernel(
+    const float2 *__restrict__ bnd, const float *__restrict__ pdf, const float *__restrict__ marg,
+    const float *__restrict__ cond, uint32_t L, int H, int W, const float *__restrict__ alpha,
+    const uint32_t *__restrict__ leaf, const float *__restrict__ normal, const float *__restrict__ u, uint64_t n,
+    float *__restrict__ dir, float *__restrict__ pdf_out, uint8_t *__restrict__ strat, uint32_t *err) {
+  __shared__ float2 q4[256];
+  load_quarter(bnd, W, q4);
+  __syncthreads();
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t l = leaf[q];
+    const float u0 = u[3 * q], u1 = u[3 * q + 1], u2 = u[3 * q + 2];
+    const float nx = normal[3 * q], ny = normal[3 * q + 1], nz = normal[3 * q + 2];
+    if (l >= L || !(u0 >= 0.0f && u0 < 1.0f) || !(u1 >= 0.0f && u1 < 1.0f) || !(u2 >= 0.0f && u2 < 1.0f) ||
+        !finite3(nx, ny, nz)) {
+      const float qnan = __int_as_float(0x7fc00000);
+      dir[3 * q] = qnan;
+      dir[3 * q + 1] = qnan;
+      dir[3 * q + 2] = qnan;
+      pdf_out[q] = qnan;
+      if (strat) strat[q] = 0;
+      raise_err(err, ERR_RANGE);
+      continue;
+    }
+    const float a = alpha[l];
+    float w[3], g;
+    const bool bsdf = u0 < a;
+    if (bsdf) {
+      cosine_sample(nx, ny, nz, u1, u2, w);
+      const int k = z_row(w[2], H) * W + phi_sector(q4, w[0], w[1], W);
+      g = pdf[(size_t)l * H * W + k];
+    } else {
+      uint32_t b;
+      guided_sample(pdf, marg, cond, l, H, W, u1, u2, w, &g, &b);
+    }
+    dir[3 * q] = w[0];
+    dir[3 * q + 1] = w[1];
+    dir[3 * q + 2] = w[2];
+    pdf_out[q] = mis_mixture(a, nx, ny, nz, w, g);
+    if (strat) strat[q] = bsdf ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void eval_mis_kernel(const float2 *__restrict__ bnd, const float *__restrict__ pdf,
+                                                       uint32_t L, int H, int W, const float *__restrict__ alpha,
+                                                       const uint32_t *__restrict__ leaf,
+                                                       const float *__restrict__ normal,
+                                                       const float *__restrict__ dir, uint64_t n,
+                                                       float *__restrict__ out, uint32_t *err) {
+  __shared__ float2 q4[256];
+  load_quarter(bnd, W, q4);
+  __syncthreads();
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t l = leaf[q];
+    const float w[3] = {dir[3 * q], dir[3 * q + 1], dir[3 * q + 2]};
+    const float nx = normal[3 * q], ny = normal[3 * q + 1], nz = normal[3 * q + 2];
+    if (l >= L || !finite3(w[0], w[1], w[2]) || !finite3(nx, ny, nz)) {
+      out[q] = 0.0f;
+      raise_err(err, ERR_RANGE);
+      continue;
+    }
+    const float a = alpha[l];
+    const int k = z_row(w[2], H) * W + phi_sector(q4, w[0], w[1], W);
+    out[q] = mis_mixture(a, nx, ny, nz, w, pdf[(size_t)l * H * W + k]);
   }
 }
 
@@ -129,6 +266,28 @@ hipError_t launch_sample(const npg_tables &t, const uint32_t *leaf, const float 
                          float *dir, float *pdf, uint32_t *bin, uint32_t *err, hipStream_t s) {
   hipLaunchKernelGGL(sample_kernel, dim3(grid_for(n)), dim3(256), 0, s, t.pdf_dev, t.marg_dev, t.cond_dev,
                      t.L, t.H, t.W, leaf, reinterpret_cast<const float2 *>(u), n, dir, pdf, bin, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_mis_alpha(const float *nu_b, const float *nu_g, const uint32_t *q_b, const uint32_t *q_g,
+                            uint32_t L, float *alpha, uint32_t *err, hipStream_t s) {
+  hipLaunchKernelGGL(mis_alpha_kernel, dim3(grid_for(L)), dim3(256), 0, s, nu_b, nu_g, q_b, q_g, L, alpha, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_mis(const float2 *bnd, const npg_tables &t, const float *alpha, const uint32_t *leaf,
+                             const float *normal, const float *u, uint64_t n, float *dir, float *pdf,
+                             uint8_t *strat, uint32_t *err, hipStream_t s) {
+  hipLaunchKernelGGL(sample_mis_kernel, dim3(grid_for(n)), dim3(256), 0, s, bnd, t.pdf_dev, t.marg_dev, t.cond_dev,
+                     t.L, t.H, t.W, alpha, leaf, normal, u, n, dir, pdf, strat, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_mis(const float2 *bnd, const npg_tables &t, const float *alpha, const uint32_t *leaf,
+                           const float *normal, const float *dir, uint64_t n, float *pdf, uint32_t *err,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(eval_mis_kernel, dim3(grid_for(n)), dim3(256), 0, s, bnd, t.pdf_dev, t.L, t.H, t.W, alpha, leaf,
+                     normal, dir, n, pdf, err);
   return hipGetLastError();
 }
 

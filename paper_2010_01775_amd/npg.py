@@ -25,6 +25,7 @@ SYMBOLS = [
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
     "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
     "npg_reconstruct_density", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
+    "npg_mis_alpha", "npg_sample_mis", "npg_eval_pdf_mis",
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
     "npg_serve_create", "npg_serve_destroy", "npg_serve_submit_recon", "npg_serve_submit_sample",
     "npg_serve_poll", "npg_serve_wait", "npg_serve_tables", "npg_serve_copy_tables", "npg_serve_release",
@@ -87,6 +88,9 @@ def load_library(path: str = LIB_PATH):
         "npg_build_cdf": (I, [P, P, U32, I, I, P, P, P, P, P]),
         "npg_sample_dirs": (I, [P, C.POINTER(Tables), P, P, U64, P, P, P, P]),
         "npg_eval_pdf": (I, [P, C.POINTER(Tables), P, P, U64, P, P]),
+        "npg_mis_alpha": (I, [P, P, P, P, P, U32, P, P]),
+        "npg_sample_mis": (I, [P, C.POINTER(Tables), P, P, P, P, U64, P, P, P, P]),
+        "npg_eval_pdf_mis": (I, [P, C.POINTER(Tables), P, P, P, P, U64, P, P]),
         "npg_bin_boundaries": (I, [I, P]),
         "npg_set_option": (I, [P, C.c_char_p, C.c_int64]),
         "npg_reconstruct_fused": (I, [P, P, P, P, P, P, U32, I, I, I, P, P, P, P, P]),
@@ -374,6 +378,45 @@ def eval_pdf(ctx: Context, tables: CdfTables, leaf, dirs, out=None, stream=None)
     t = tables.c()
     ctx.check(ctx.lib.npg_eval_pdf(ctx.h, C.byref(t), _ptr(leaf), _ptr(dirs), n, _ptr(out),
                                    _stream(stream)))
+    return out
+
+
+def mis_alpha(ctx: Context, nu_b, nu_g, q_b, q_g, out=None, stream=None):
+    """Per-leaf one-sample MIS weight from the path statistics."""
+    _dev(nu_b, torch.float32, "nu_b")
+    _dev(nu_g, torch.float32, "nu_g")
+    _dev(q_b, torch.int32, "q_b (uint32 bits in int32)")
+    _dev(q_g, torch.int32, "q_g (uint32 bits in int32)")
+    L = nu_b.shape[0]
+    if out is None:
+        out = torch.empty(L, dtype=torch.float32, device=nu_b.device)
+    ctx.check(ctx.lib.npg_mis_alpha(ctx.h, _ptr(nu_b), _ptr(nu_g), _ptr(q_b), _ptr(q_g), L, _ptr(out),
+                                    _stream(stream)))
+    return out
+
+
+def sample_mis(ctx: Context, tables: CdfTables, alpha, leaf, normal, u, out=None, stream=None):
+    """One-sample MIS directions; returns (dirs, pdf, strategy: 1 = BSDF)."""
+    n = leaf.shape[0]
+    dev = leaf.device
+    if out is None:
+        out = (torch.empty((n, 3), dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.uint8, device=dev))
+    d, p, st = out
+    t = tables.c()
+    ctx.check(ctx.lib.npg_sample_mis(ctx.h, C.byref(t), _ptr(alpha), _ptr(leaf), _ptr(normal), _ptr(u), n,
+                                     _ptr(d), _ptr(p), _ptr(st), _stream(stream)))
+    return d, p, st
+
+
+def eval_pdf_mis(ctx: Context, tables: CdfTables, alpha, leaf, normal, dirs, out=None, stream=None):
+    n = leaf.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=leaf.device)
+    t = tables.c()
+    ctx.check(ctx.lib.npg_eval_pdf_mis(ctx.h, C.byref(t), _ptr(alpha), _ptr(leaf), _ptr(normal), _ptr(dirs), n,
+                                       _ptr(out), _stream(stream)))
     return out
 
 

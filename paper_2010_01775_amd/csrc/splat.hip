@@ -46,8 +46,8 @@ struct DescLeaves {
   __device__ const uint32_t *ws(int leaf) const { return d[leaf].w; }
 };
 
-template <int BPT, class LS>
-__global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
+template <int BPT, int NT, class LS>
+__global__ __launch_bounds__(NT) void splat_kernel(
     const float2 *__restrict__ bnd, LS src, int H, int W, int band_rows, uint64_t *__restrict__ energy,
     uint32_t *__restrict__ count, int accumulate, uint32_t *err) {
   extern __shared__ unsigned long long acc[];
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
   const int row0 = blockIdx.y * band_rows;
   const int nb = band_rows * W;
   const int tid = threadIdx.x;
-  for (int k = tid; k < nb; k += SPLAT_THREADS) acc[k] = 0ull;
+  for (int k = tid; k < nb; k += NT) acc[k] = 0ull;
   load_quarter(bnd, W, q4);
   unsigned long long e[BPT];
   uint32_t c[BPT];
@@ -76,12 +76,12 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
     // PB photons per thread and step: all their loads are issued before
     // the first bin is computed
     constexpr int PB = 2;
-    for (uint32_t i0 = (uint32_t)r0 + tid; i0 < r1; i0 += PB * SPLAT_THREADS) {
+    for (uint32_t i0 = (uint32_t)r0 + tid; i0 < r1; i0 += PB * NT) {
       float x[PB], y[PB], z[PB];
       uint32_t wp[PB];
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
-        const uint32_t i = i0 + j * SPLAT_THREADS;
+        const uint32_t i = i0 + j * NT;
         const uint32_t p = src.idx(leaf, i < r1 ? i : i0);
         x[j] = dir[3 * (size_t)p];
         y[j] = dir[3 * (size_t)p + 1];
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
       }
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
-        if (i0 + j * SPLAT_THREADS >= r1) continue;
+        if (i0 + j * NT >= r1) continue;
         if (!finite3(x[j], y[j], z[j])) {
           bad = true;
           continue;
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
-      const int k = tid + j * SPLAT_THREADS;
+      const int k = tid + j * NT;
       if (k < nb) {
         const unsigned long long v = acc[k];
         acc[k] = 0ull;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
   const size_t base = ((size_t)leaf * H + row0) * W;
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
-    const int k = tid + j * SPLAT_THREADS;
+    const int k = tid + j * NT;
     if (k < nb) {
       if (accumulate) {
         energy[base + k] += e[j];
@@ -131,37 +131,43 @@ __global__ __launch_bounds__(SPLAT_THREADS) void splat_kernel(
   }
 }
 
-template <int BPT, class LS>
+template <int BPT, int NT, class LS>
 hipError_t launch_splat_t(const float2 *bnd, const LS &src, uint32_t L, int H, int W, int band_rows,
                           uint64_t *energy, uint32_t *count, int accumulate, uint32_t *err, hipStream_t s) {
   const size_t lds = sizeof(unsigned long long) * (size_t)band_rows * W;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)splat_kernel<BPT, LS>,
+    hipError_t e = hipFuncSetAttribute((const void *)splat_kernel<BPT, NT, LS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        SPLAT_MAX_BINS * sizeof(unsigned long long));
     if (e != hipSuccess) return e;
     attr = true;
   }
   dim3 grid(L, H / band_rows);
-  hipLaunchKernelGGL((splat_kernel<BPT, LS>), grid, dim3(SPLAT_THREADS), lds, s, bnd, src, H, W, band_rows,
+  hipLaunchKernelGGL((splat_kernel<BPT, NT, LS>), grid, dim3(NT), lds, s, bnd, src, H, W, band_rows,
                      energy, count, accumulate, err);
   return hipGetLastError();
 }
 
+// Maps of up to 4096 bins take 512-thread workgroups (four fit a CU, so a
+// 1024-leaf batch is resident at once); larger bands 1024 threads.
 template <class LS>
 hipError_t launch_splat_any(const float2 *bnd, const LS &src, uint32_t L, int H, int W, uint64_t *energy,
                             uint32_t *count, int accumulate, uint32_t *err, hipStream_t s) {
   int band_rows = H;
   while (band_rows * W > SPLAT_MAX_BINS) band_rows >>= 1;
   const int nb = band_rows * W;
-  const int bpt = (nb + SPLAT_THREADS - 1) / SPLAT_THREADS;
-  switch (bpt) {
-    case 1: return launch_splat_t<1>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
-    case 2: return launch_splat_t<2>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
-    case 4: return launch_splat_t<4>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
-    case 8: return launch_splat_t<8>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
-    default: return launch_splat_t<16>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+  if (nb <= 4096) {
+    switch ((nb + 511) / 512) {
+      case 1: return launch_splat_t<1, 512>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+      case 2: return launch_splat_t<2, 512>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+      case 4: return launch_splat_t<4, 512>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+      default: return launch_splat_t<8, 512>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+    }
+  }
+  switch ((nb + SPLAT_THREADS - 1) / SPLAT_THREADS) {
+    case 8: return launch_splat_t<8, SPLAT_THREADS>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
+    default: return launch_splat_t<16, SPLAT_THREADS>(bnd, src, L, H, W, band_rows, energy, count, accumulate, err, s);
   }
 }
 

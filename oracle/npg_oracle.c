@@ -182,6 +182,7 @@ typedef struct {
 
 typedef struct {
   int arch, levels, n;
+  int in_ch; /* input channels: 1, or 5 for the five-channel U-Net */
   or_layer *layer;
 } or_net;
 
@@ -232,6 +233,7 @@ static int net_parse(const unsigned char *buf, size_t len, or_net *net) {
   }
   if (o != len) { net_free(net); return OR_E_ARG; }
   /* topology checks */
+  net->in_ch = 1;
   if (net->arch == 1) {
     int c = 1;
     for (int i = 0; i < net->n; i++) {
@@ -242,7 +244,10 @@ static int net_parse(const unsigned char *buf, size_t len, or_net *net) {
   } else if (net->arch == 2) {
     int D = net->levels;
     if (D < 1 || net->n != 4 * D - 1) { net_free(net); return OR_E_ARG; }
-    int prev = 1;
+    /* the first layer takes the one-channel raw map, or the five channels of
+     * Sec. 6 (then as a masked convolution) */
+    net->in_ch = net->layer[0].cin == 5 ? 5 : 1;
+    int prev = net->in_ch;
     for (int d = 0; d < D; d++) {
       or_layer *a = &net->layer[2 * d], *b = &net->layer[2 * d + 1];
       if (a->cin != prev || a->k != 3 || b->cin != a->cout || b->cout != a->cout || b->k != 3) {
@@ -284,6 +289,32 @@ static void conv2d(const or_layer *y, const double *in, int H, int W, double *ou
               acc += y->w[((co * y->cin + ci) * k + ky) * k + kx] * in[((size_t)ci * H + sy) * W + sx];
             }
         out[((size_t)co * H + yy) * W + xx] = acc;
+      }
+}
+
+/* Masked (partial) convolution, Liu et al. 2018, as the paper's first layer
+ * (Sec. 6.1: only valid bins contribute): with the mask M = in[mask_ch]
+ * (1 where the bin holds photons) and S = number of in-map taps of the
+ * k x k window with M = 1 (outside the map M = 0),
+ *   out = b + (k*k / S) * sum_{ci, taps} w * in * M   if S > 0, else 0. */
+static void pconv2d(const or_layer *y, const double *in, int mask_ch, int H, int W, double *out) {
+  int k = y->k, r = k / 2;
+  const double *M = in + (size_t)mask_ch * H * W;
+  for (int co = 0; co < y->cout; co++)
+    for (int yy = 0; yy < H; yy++)
+      for (int xx = 0; xx < W; xx++) {
+        double acc = 0.0;
+        int S = 0;
+        for (int ky = 0; ky < k; ky++)
+          for (int kx = 0; kx < k; kx++) {
+            int sy = yy + ky - r, sx = xx + kx - r;
+            if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+            double m = M[(size_t)sy * W + sx];
+            if (m != 0.0) S++;
+            for (int ci = 0; ci < y->cin; ci++)
+              acc += y->w[((co * y->cin + ci) * k + ky) * k + kx] * in[((size_t)ci * H + sy) * W + sx] * m;
+          }
+        out[((size_t)co * H + yy) * W + xx] = S > 0 ? y->b[co] + (double)(k * k) / (double)S * acc : 0.0;
       }
 }
 
@@ -347,7 +378,10 @@ static void net_forward_leaf(const or_net *net, const double *x, int H, int W, d
       cur = pooled;
     }
     double *t = malloc(sizeof(double) * (size_t)la->cout * h * w);
-    conv2d(la, cur, h, w, t);
+    if (d == 0 && net->in_ch == 5)
+      pconv2d(la, cur, 4, h, w, t); /* channel 4 is the valid-bin mask */
+    else
+      conv2d(la, cur, h, w, t);
     relu(t, (size_t)la->cout * h * w);
     double *o = malloc(sizeof(double) * (size_t)lb->cout * h * w);
     conv2d(lb, t, h, w, o);
@@ -399,10 +433,75 @@ int or_net_forward(const unsigned char *model, size_t model_len, const double *x
     }
   }
   size_t HW = (size_t)H * W;
+  if (net.in_ch != 1) {
+    net_free(&net);
+    return OR_E_ARG;
+  }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t l = 0; l < L; l++) net_forward_leaf(&net, x + (size_t)l * HW, H, W, s + (size_t)l * HW);
   net_free(&net);
   return OR_OK;
+}
+
+/* s[L][H][W] = five-channel network(x[L][5][H][W]). */
+int or_net_forward5(const unsigned char *model, size_t model_len, const double *x,
+                    int64_t L, int H, int W, double *s) {
+  or_net net;
+  int rc = net_parse(model, model_len, &net);
+  if (rc) return rc;
+  int D = net.levels;
+  if (net.arch != 2 || net.in_ch != 5 || (H % (1 << (D - 1))) || (W % (1 << (D - 1)))) {
+    net_free(&net);
+    return OR_E_ARG;
+  }
+  size_t HW = (size_t)H * W;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t l = 0; l < L; l++) net_forward_leaf(&net, x + (size_t)l * 5 * HW, H, W, s + (size_t)l * HW);
+  net_free(&net);
+  return OR_OK;
+}
+
+/* The five input channels of Sec. 6 for each leaf: the raw sampling maps of
+ * iterations t and t-1 (energies E, mean 1: H*W*E/sum(E), 0 for an empty
+ * map), their photon-count maps normalised the same way, and the mask of
+ * bins holding photons at iteration t; each map value rounded to float32
+ * (as the one-channel raw map).  x[L][5][H][W]. */
+void or_input5(const uint64_t *e_t, const uint64_t *e_p, const uint32_t *p_t, const uint32_t *p_p,
+               int64_t L, int H, int W, double *x) {
+  size_t HW = (size_t)H * W;
+#pragma omp parallel for schedule(static)
+  for (int64_t l = 0; l < L; l++) {
+    const uint64_t *E[2] = {e_t + l * HW, e_p + l * HW};
+    const uint32_t *P[2] = {p_t + l * HW, p_p + l * HW};
+    double *xl = x + (size_t)l * 5 * HW;
+    for (int c = 0; c < 2; c++) {
+      double S = 0.0, T = 0.0;
+      for (size_t k = 0; k < HW; k++) {
+        S += (double)E[c][k];
+        T += (double)P[c][k];
+      }
+      for (size_t k = 0; k < HW; k++) {
+        xl[(size_t)c * HW + k] = S > 0.0 ? (double)(float)((double)HW * (double)E[c][k] / S) : 0.0;
+        xl[(size_t)(2 + c) * HW + k] = T > 0.0 ? (double)(float)((double)HW * (double)P[c][k] / T) : 0.0;
+      }
+    }
+    for (size_t k = 0; k < HW; k++) xl[4 * HW + k] = P[0][k] > 0 ? 1.0 : 0.0;
+  }
+}
+
+/* One masked convolution layer (weights OIHW f32, bias f32) on in[C][H][W]
+ * with the mask in channel mask_ch, for pins. */
+void or_pconv2d(const float *w, const float *b, int cout, int cin, int k, const double *in, int mask_ch,
+                int H, int W, double *out) {
+  or_layer y;
+  size_t nw = (size_t)cout * cin * k * k;
+  y.cout = cout; y.cin = cin; y.k = k;
+  y.w = malloc(sizeof(double) * nw);
+  y.b = malloc(sizeof(double) * (size_t)cout);
+  for (size_t i = 0; i < nw; i++) y.w[i] = (double)w[i];
+  for (int i = 0; i < cout; i++) y.b[i] = b ? (double)b[i] : 0.0;
+  pconv2d(&y, in, mask_ch, H, W, out);
+  free(y.w); free(y.b);
 }
 
 /* Raw layer access for brute-force conv checks: one conv of a single

@@ -44,6 +44,9 @@ def lib():
             "or_normalize_input": (None, [P, I64, I, I, P]),
             "or_net_forward": (I, [P, C.c_size_t, P, I64, I, I, P]),
             "or_conv2d": (None, [P, P, I, I, I, P, I, I, P]),
+            "or_net_forward5": (I, [P, C.c_size_t, P, I64, I, I, P]),
+            "or_input5": (None, [P, P, P, P, I64, I, I, P]),
+            "or_pconv2d": (None, [P, P, I, I, I, P, I, I, I, P]),
             "or_build_cdf": (I, [P, I64, I, I, P, P, P, P]),
             "or_sample": (I, [P, P, P, I64, I, I, P, P, I64, P, P, P]),
             "or_eval_pdf": (I, [P, I64, I, I, P, P, I64, P]),
@@ -150,6 +153,41 @@ def conv2d(w, b, x):
     bb = None if b is None else _c(b, np.float32)
     lib().or_conv2d(_p(w), _p(bb), co, ci, k, _p(x), H, W, _p(out))
     return out
+
+
+def pconv2d(w, b, x, mask_ch):
+    """One masked (partial) conv layer with the mask in channel mask_ch of
+    x [ci,H,W] (the paper's first layer, Sec. 6.1)."""
+    w = _c(w, np.float32)
+    co, ci, k, _ = w.shape
+    x = _c(x, np.float64)
+    _, H, W = x.shape
+    out = np.empty((co, H, W), np.float64)
+    bb = None if b is None else _c(b, np.float32)
+    lib().or_pconv2d(_p(w), _p(bb), co, ci, k, _p(x), int(mask_ch), H, W, _p(out))
+    return out
+
+
+def input5(e_t, e_p, p_t, p_p):
+    """The five input channels (Sec. 6): raw maps of iterations t and t-1,
+    their photon counts (each mean-1 normalised, float32-rounded) and the
+    mask of bins with photons at t.  Returns x [L][5][H][W] (float64)."""
+    e_t, e_p = _c(e_t, np.uint64), _c(e_p, np.uint64)
+    p_t, p_p = _c(p_t, np.uint32), _c(p_p, np.uint32)
+    L, H, W = e_t.shape
+    x = np.empty((L, 5, H, W), np.float64)
+    lib().or_input5(_p(e_t), _p(e_p), _p(p_t), _p(p_p), L, H, W, _p(x))
+    return x
+
+
+def net_forward5(model: bytes, x):
+    """Five-channel U-Net (masked first layer) on x [L][5][H][W]."""
+    x = _c(x, np.float64)
+    L, _, H, W = x.shape
+    s = np.empty((L, H, W), np.float64)
+    buf = np.frombuffer(model, dtype=np.uint8)
+    rc = lib().or_net_forward5(_p(buf), len(model), _p(x), L, H, W, _p(s))
+    return rc, s
 
 
 def build_cdf(s):

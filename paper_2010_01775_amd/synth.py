@@ -182,6 +182,12 @@ def unet_model(seed: int, levels=(16, 32, 64, 128), random_bias=False) -> bytes:
     return pack_model(ARCH_UNET, len(levels), ws, bs)
 
 
+def unet5_model(seed: int, levels=(16, 32, 64, 128), random_bias=False) -> bytes:
+    """The U-Net with the five input channels of the paper (masked first layer)."""
+    ws, bs = he_weights(seed, unet_layers(levels, cin=5), random_bias)
+    return pack_model(ARCH_UNET, len(levels), ws, bs)
+
+
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------

@@ -220,6 +220,24 @@ int npg_reconstruct_density(npg_ctx *ctx, const npg_model *model, const uint64_t
                             const uint32_t *count_dev, uint32_t L, int H, int W,
                             npg_precision precision, float *density_dev, void *stream);
 
+/* The network on the paper's five input channels (Sec. 6): the raw maps
+ * of iterations t and t-1 (x = H*W*E/sum(E), 0 for an empty map), their
+ * photon-count maps normalised the same way (each value rounded to
+ * float32), and the mask B of bins holding photons at t; the first layer is
+ * a masked (partial) convolution: only taps with B = 1 contribute, the sum
+ * is rescaled by 9/S for the S valid in-map taps (0 where S = 0), then bias
+ * and ReLU; the rest is the U-Net of npg_reconstruct_density.  The model is
+ * a U-Net whose first layer has 5 input channels (other entry points reject
+ * such models and this one rejects the others).
+ *   energy_dev, energy_prev_dev [L][H][W] uint64;  count_dev, count_prev_dev
+ *   [L][H][W] uint32 (as written by npg_splat_histograms for iterations t
+ *   and t-1);  density_dev [L][H][W] float32 out
+ * NPG_FP32 or NPG_BF16 (NPG_E_ARG for NPG_FP8). */
+int npg_reconstruct_density5(npg_ctx *ctx, const npg_model *model, const uint64_t *energy_dev,
+                             const uint32_t *count_dev, const uint64_t *energy_prev_dev,
+                             const uint32_t *count_prev_dev, uint32_t L, int H, int W, npg_precision precision,
+                             float *density_dev, void *stream);
+
 /* Mixture of experts by leaf photon count (Sec. 8, Implementation, training: five
  * networks, each for one range of photons per voxel, [0,100), [100,500),
  * [500,1000), [1000,5000) and [5000,inf)).  Leaf l holds

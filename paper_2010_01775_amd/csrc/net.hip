@@ -58,6 +58,7 @@ struct LayerDev {
 struct npg_model {
   npg_ctx *ctx = nullptr;
   int arch = 0, levels = 0;
+  int in_ch = 1;  // 1, or 5: the five-channel U-Net (masked first layer)
   std::vector<LayerDev> layer;
   std::vector<std::vector<float>> host_w, host_b;
   void *blob = nullptr;  // one device allocation holding every array
@@ -177,7 +178,9 @@ static int parse_model(npg_ctx *ctx, const unsigned char *buf, size_t len, npg_m
   } else if (m->arch == 2) {
     const int D = m->levels;
     if (D < 1 || D > 10 || n != 4 * D - 1) return npg_fail(ctx, NPG_E_ARG, "model: U-Net layer count");
-    int prev = 1;
+    // one input channel (the raw map), or the five of the paper's input
+    m->in_ch = m->layer[0].cin == 5 ? 5 : 1;
+    int prev = m->in_ch;
     for (int d = 0; d < D; ++d) {
       const LayerDev &a = m->layer[2 * d], &b = m->layer[2 * d + 1];
       if (a.cin != prev || a.k != 3 || b.cin != a.cout || b.cout != a.cout || b.k != 3)
@@ -290,7 +293,7 @@ extern "C" void npg_model_free(npg_model *m) {
 // ------------------------------------------------------------- kernels
 namespace {
 
-enum SrcMode : int { SRC_PLAIN = 0, SRC_POOL = 1, SRC_UPCAT = 2, SRC_ENERGY = 3 };
+enum SrcMode : int { SRC_PLAIN = 0, SRC_POOL = 1, SRC_UPCAT = 2, SRC_ENERGY = 3, SRC_FIVE = 4 };
 enum Act : int { ACT_RELU = 0, ACT_SOFTPLUS = 1 };
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -322,6 +325,9 @@ struct Src {
   const double *tot;   // ENERGY: per-leaf energy totals
   int C0, C1;
   float dq0 = 1.0f, dq1 = 1.0f;  // FP8: value of one e4m3 unit of s0 / s1
+  // FIVE: s0, s1 = energies of iterations t and t-1 (uint64), s2, s3 = their
+  // photon counts (uint32), tot = [L][4] sums of the four maps
+  const void *s2 = nullptr, *s3 = nullptr;
 };
 
 // One input element (leaf, y, x, c) in storage units; (y, x) inside the map.
@@ -359,6 +365,88 @@ __device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, i
     return v * (double)((s.mode == SRC_UPCAT && c >= s.C0) ? s.dq1 : s.dq0);
   }
   return v;
+}
+
+// The paper's first layer on its five input channels (Sec. 6): raw maps of
+// iterations t and t-1 (mean-1 energies), their photon counts normalised the
+// same way (each value rounded to float32, as the one-channel raw map), and
+// the mask B of bins with photons at t, as a masked (partial) convolution:
+// only taps with B = 1 contribute, and the sum is rescaled by 9/S for the
+// S valid in-map taps (zero output where S = 0), then bias and ReLU.  One
+// thread per output pixel, all output channels; out T [L][H][W][cout].
+template <class T, class Acc, int COUT>
+__global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__restrict__ w,
+                                                          const float *__restrict__ b, int H, int W,
+                                                          size_t npix, void *out) {
+  constexpr int cout = COUT;
+  const size_t HW = (size_t)H * W;
+  for (size_t pix = blockIdx.x * (size_t)blockDim.x + threadIdx.x; pix < npix;
+       pix += (size_t)gridDim.x * blockDim.x) {
+    const size_t leaf = pix / HW;
+    const int r = (int)(pix - leaf * HW), y = r / W, x = r - y * W;
+    const double *tl = s.tot + 4 * leaf;
+    double inv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) inv[k] = tl[k] > 0.0 ? (double)HW / tl[k] : 0.0;
+    Acc acc[COUT];
+#pragma unroll
+    for (int c = 0; c < cout; ++c) acc[c] = (Acc)0;
+    int S = 0;
+    for (int t = 0; t < 9; ++t) {
+      const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
+      if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+      const size_t i = leaf * HW + (size_t)sy * W + sx;
+      const uint32_t pt = static_cast<const uint32_t *>(s.s2)[i];
+      if (pt == 0) continue;  // mask 0: the tap contributes nothing
+      ++S;
+      const Acc xv[5] = {
+          (Acc)(float)((double)static_cast<const uint64_t *>(s.s0)[i] * inv[0]),
+          (Acc)(float)((double)static_cast<const uint64_t *>(s.s1)[i] * inv[1]),
+          (Acc)(float)((double)pt * inv[2]),
+          (Acc)(float)((double)static_cast<const uint32_t *>(s.s3)[i] * inv[3]), (Acc)1};
+#pragma unroll
+      for (int c = 0; c < cout; ++c)
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch) acc[c] = fma((Acc)w[(c * 5 + ch) * 9 + t], xv[ch], acc[c]);
+    }
+    T *o = static_cast<T *>(out) + pix * cout;
+#pragma unroll
+    for (int c = 0; c < cout; ++c) {
+      Acc v = S > 0 ? (Acc)b[c] + (Acc)(9.0 / (double)S) * acc[c] : (Acc)0;
+      v = v > (Acc)0 ? v : (Acc)0;
+      o[c] = from_d<T>((double)v);
+    }
+  }
+}
+
+// Sums of the four maps of the five-channel input per leaf (exact integer
+// sums, stored as binary64): tot[L][4] = (E_t, E_t-1, P_t, P_t-1).
+__global__ __launch_bounds__(256) void leaf_totals5_kernel(const uint64_t *__restrict__ e_t,
+                                                           const uint64_t *__restrict__ e_p,
+                                                           const uint32_t *__restrict__ p_t,
+                                                           const uint32_t *__restrict__ p_p, int HW,
+                                                           double *__restrict__ tot) {
+  __shared__ unsigned long long part[4][4];
+  const int leaf = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t o = (size_t)leaf * HW;
+  unsigned long long v[4] = {0, 0, 0, 0};
+  for (int k = threadIdx.x; k < HW; k += 256) {
+    v[0] += e_t[o + k];
+    v[1] += e_p[o + k];
+    v[2] += p_t[o + k];
+    v[3] += p_p[o + k];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
+    if (lane == 0) part[j][wave] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int j = threadIdx.x;
+    tot[4 * (size_t)leaf + j] = (double)(part[j][0] + part[j][1] + part[j][2] + part[j][3]);
+  }
 }
 
 // Direct convolution, one thread per output pixel, binary64 sums.
@@ -1359,7 +1447,7 @@ struct Runner {
   int vec() const { return prec == NPG_FP32 ? 2 : prec == NPG_FP8 ? 16 : 8; }
   bool mfma_fits(const LayerDev &y, const Src &src, int H, int W, Tiling *t, int mw_lim = 8) const {
     const int v = vec();
-    if (force_direct || y.k != 3 || src.mode == SRC_ENERGY || y.cin % v) return false;
+    if (force_direct || y.k != 3 || src.mode == SRC_ENERGY || src.mode == SRC_FIVE || y.cin % v) return false;
     if (src.mode == SRC_UPCAT && (src.C0 % v || src.C1 % v)) return false;
     // the tiled kernel takes each K chunk's channels from one source
     const int kc = prec == NPG_FP32 ? KC32 : (y.cin % 32 == 0 ? 32 : 16);
@@ -1514,6 +1602,33 @@ struct Runner {
         e = launch_mfma<BF16S>(a, t, tiles, s);
       }
       if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "conv launch: %s", hipGetErrorString(e));
+      return NPG_OK;
+    }
+    if (src.mode == SRC_FIVE) {
+      if (y.k != 3 || y.cin != 5 || act != ACT_RELU || head || prec == NPG_FP8)
+        return npg_fail(ctx, NPG_E_ARG, "internal: five-channel first layer");
+      const size_t npix = (size_t)Lc * H * W;
+      const unsigned blocks = (unsigned)std::min<size_t>((npix + 255) / 256, 1u << 20);
+      auto go = [&](auto tag_t, auto tag_acc, auto tag_c) {
+        using TT = decltype(tag_t);
+        using AA = decltype(tag_acc);
+        constexpr int C = decltype(tag_c)::value;
+        hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C>), dim3(blocks), dim3(256), 0, s, src, y.w, y.b, H, W,
+                           npix, out);
+      };
+      auto by_c = [&](auto tag_t, auto tag_acc) {
+        switch (y.cout) {
+          case 4: go(tag_t, tag_acc, std::integral_constant<int, 4>{}); return true;
+          case 8: go(tag_t, tag_acc, std::integral_constant<int, 8>{}); return true;
+          case 16: go(tag_t, tag_acc, std::integral_constant<int, 16>{}); return true;
+          case 32: go(tag_t, tag_acc, std::integral_constant<int, 32>{}); return true;
+          default: return false;
+        }
+      };
+      const bool ok = prec == NPG_FP32 ? by_c(double{}, double{}) : by_c(uint16_t{}, float{});
+      if (!ok) return npg_fail(ctx, NPG_E_ARG, "five-channel first layer: %d outputs (4, 8, 16 or 32)", y.cout);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "five-channel conv launch: %s", hipGetErrorString(e));
       return NPG_OK;
     }
     if (!force_direct && src.mode == SRC_ENERGY && y.k == 3 && y.cin == 1 && y.cout <= 16 && act == ACT_RELU &&
@@ -1715,8 +1830,11 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
   return NPG_OK;
 }
 
-int check_net_args(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision precision) {
+int check_net_args(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision precision, int in_ch = 1) {
   if (!m) return npg_fail(ctx, NPG_E_ARG, "reconstruct: null model");
+  if (m->in_ch != in_ch)
+    return npg_fail(ctx, NPG_E_ARG, in_ch == 1 ? "reconstruct: a five-channel model needs npg_reconstruct_density5"
+                                               : "reconstruct: npg_reconstruct_density5 needs a five-channel U-Net");
   if (!pow2_in(H, 4, 1024) || !pow2_in(W, 4, 1024))
     return npg_fail(ctx, NPG_E_ARG, "reconstruct: bad H=%d W=%d", H, W);
   if (precision != NPG_FP32 && precision != NPG_BF16 && precision != NPG_FP8)
@@ -1818,6 +1936,49 @@ extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const u
                      nullptr);
 }
 
+extern "C" int npg_reconstruct_density5(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
+                                        const uint32_t *count_dev, const uint64_t *energy_prev_dev,
+                                        const uint32_t *count_prev_dev, uint32_t L, int H, int W,
+                                        npg_precision precision, float *density_dev, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_net_args(ctx, m, H, W, precision, 5);
+  if (rc) return rc;
+  if (precision == NPG_FP8) return npg_fail(ctx, NPG_E_ARG, "reconstruct5: FP32 or BF16 only");
+  if (L == 0) return NPG_OK;
+  if (!energy_dev || !count_dev || !energy_prev_dev || !count_prev_dev || !density_dev)
+    return npg_fail(ctx, NPG_E_ARG, "reconstruct5: null pointer");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Runner R = make_runner(ctx, m, precision, s);
+  std::vector<int> caps;
+  apply_tune(ctx, R, H, W, &caps);
+  const size_t HW = (size_t)H * W;
+  const NetPlan plan = plan_net(m, H, W, R.esz);
+  const size_t fixed = npg_align(4 * sizeof(double) * L) + (16u << 20);
+  size_t chunk = 0;
+  rc = chunk_for(ctx, m, precision, H, W, L, plan.per_leaf, fixed, &chunk);
+  if (rc) return rc;
+  void *scr = nullptr;
+  rc = npg_scratch(ctx, fixed + net_bufs_bytes(plan, chunk, R.esz), s, &scr);
+  if (rc) return rc;
+  Carver cv(scr);
+  double *tot = cv.take<double>(4 * (size_t)L);
+  const NetBufs B = carve_net(cv, plan, chunk, R.esz);
+  hipLaunchKernelGGL(leaf_totals5_kernel, dim3(L), dim3(256), 0, s, energy_dev, energy_prev_dev, count_dev,
+                     count_prev_dev, (int)HW, tot);
+  NPG_HIP_CHECK(ctx, hipGetLastError());
+  for (size_t l0 = 0; l0 < L; l0 += chunk) {
+    const int Lc = (int)std::min<size_t>(chunk, L - l0);
+    Src in{SRC_FIVE, energy_dev + l0 * HW, energy_prev_dev + l0 * HW, tot + 4 * l0, 5, 0};
+    in.s2 = count_dev + l0 * HW;
+    in.s3 = count_prev_dev + l0 * HW;
+    rc = net_chunk(R, in, Lc, H, W, density_dev + l0 * HW, B);
+    if (rc) return rc;
+  }
+  return NPG_OK;
+}
+
 // ----------------------------------------------------------- fused path
 // splat -> normalise -> network -> CDF, chunk by chunk: the energy maps and
 // densities of a chunk live in scratch only, never at full batch size.
@@ -1915,6 +2076,7 @@ extern "C" int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *m, const flo
 }
 
 bool npg_model_fp8_ready(const npg_model *m) { return m && m->fp8_ready; }
+int npg_model_in_channels(const npg_model *m) { return m ? m->in_ch : 0; }
 
 bool npg_model_fits(const npg_model *m, int H, int W) {
   if (m->arch != 2) return true;

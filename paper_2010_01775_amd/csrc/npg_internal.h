@@ -204,6 +204,7 @@ hipError_t launch_splat(const float2 *bnd, const float *dir, const uint32_t *w, 
 // true if the network's pooling levels divide an H x W map
 bool npg_model_fits(const npg_model *m, int H, int W);
 bool npg_model_fp8_ready(const npg_model *m);
+int npg_model_in_channels(const npg_model *m);
 hipError_t launch_splat_desc(const float2 *bnd, const npg_leaf_desc *d, uint32_t L, int H, int W,
                              uint64_t *energy, uint32_t *err, hipStream_t s);
 hipError_t launch_build_cdf_desc(const float *density, const npg_leaf_desc *d, uint32_t L, int H, int W,

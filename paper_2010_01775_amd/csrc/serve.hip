@@ -399,6 +399,8 @@ int npg_serve_create(npg_ctx *ctx, const npg_model *model, const npg_serve_param
     return npg_fail(ctx, NPG_E_ARG, "serve: bad precision %d", (int)prm->precision);
   if (prm->precision == NPG_FP8 && !npg_model_fp8_ready(model))
     return npg_fail(ctx, NPG_E_ARG, "serve: FP8 needs npg_model_calibrate_fp8 first");
+  if (npg_model_in_channels(model) != 1)
+    return npg_fail(ctx, NPG_E_ARG, "serve: one-channel models only");
   int rc = npg_set_device(ctx);
   if (rc) return rc;
   npg_server *sv = new npg_server();

@@ -25,7 +25,7 @@ SYMBOLS = [
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
     "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
     "npg_reconstruct_density", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
-    "npg_mis_alpha", "npg_sample_mis", "npg_eval_pdf_mis",
+    "npg_mis_alpha", "npg_sample_mis", "npg_eval_pdf_mis", "npg_reconstruct_density5",
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
     "npg_serve_create", "npg_serve_destroy", "npg_serve_submit_recon", "npg_serve_submit_sample",
     "npg_serve_poll", "npg_serve_wait", "npg_serve_tables", "npg_serve_copy_tables", "npg_serve_release",
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "npg_normalize_input": (I, [P, P, U32, I, I, P, P]),
         "npg_reconstruct_density": (I, [P, P, P, P, U32, I, I, I, P, P]),
         "npg_reconstruct_experts": (I, [P, P, I, P, P, P, U32, I, I, I, P, P, P]),
+        "npg_reconstruct_density5": (I, [P, P, P, P, P, P, U32, I, I, I, P, P]),
         "npg_build_cdf": (I, [P, P, U32, I, I, P, P, P, P, P]),
         "npg_sample_dirs": (I, [P, C.POINTER(Tables), P, P, U64, P, P, P, P]),
         "npg_eval_pdf": (I, [P, C.POINTER(Tables), P, P, U64, P, P]),
@@ -283,6 +284,27 @@ def reconstruct_density(ctx: Context, model: Model, energy, precision="fp32", co
     p = PRECISION[precision] if isinstance(precision, str) else int(precision)
     ctx.check(ctx.lib.npg_reconstruct_density(ctx.h, model.h, _ptr(energy), _ptr(count), L, H, W, p,
                                               _ptr(density), _stream(stream)))
+    return density
+
+
+def reconstruct_density5(ctx: Context, model: Model, energy, count, energy_prev, count_prev, precision="fp32",
+                         density=None, stream=None):
+    """Densities from the paper's five input channels (maps and photon counts
+    of iterations t and t-1, valid-bin mask)."""
+    L, H, W = energy.shape
+    for t, name in ((energy, "energy"), (energy_prev, "energy_prev")):
+        _dev(t, torch.int64, f"{name} (uint64 bits in int64)")
+        if t.shape != (L, H, W):
+            raise ValueError(f"{name} must be [L][H][W]")
+    for t, name in ((count, "count"), (count_prev, "count_prev")):
+        _dev(t, torch.int32, f"{name} (uint32 bits in int32)")
+        if t.shape != (L, H, W):
+            raise ValueError(f"{name} must be [L][H][W]")
+    if density is None:
+        density = torch.empty((L, H, W), dtype=torch.float32, device=energy.device)
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.lib.npg_reconstruct_density5(ctx.h, model.h, _ptr(energy), _ptr(count), _ptr(energy_prev),
+                                               _ptr(count_prev), L, H, W, p, _ptr(density), _stream(stream)))
     return density
 
 

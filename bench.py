@@ -69,10 +69,11 @@ def model_flops_per_leaf(model: bytes, H: int, W: int) -> float:
     return tot
 
 
-def model_bytes_per_leaf(model: bytes, H: int, W: int, esz: int) -> float:
+def model_bytes_per_leaf(model: bytes, H: int, W: int, esz: int, in_bytes: float = 8.0) -> float:
     """Algorithmic HBM bytes of one leaf's network pass: every layer reads its
-    input once (the u64 energy map for the first layer; pooled and
-    concatenated inputs at their stored resolution) and writes its output
+    input once (in_bytes per pixel for the first layer: the u64 energy map,
+    or u64 + u32 maps of two iterations for the five-channel input; pooled
+    and concatenated inputs at their stored resolution) and writes its output
     once (esz bytes per activation, float32 densities for the last layer)."""
     arch, levels, n = struct.unpack_from("<III", model, 8)
     off = 20
@@ -83,14 +84,14 @@ def model_bytes_per_leaf(model: bytes, H: int, W: int, esz: int) -> float:
         off += 12 + 4 * (co * ci * k * k + co)
     px = H * W
     if arch == 1:
-        b = 8.0 * px
+        b = in_bytes * px
         for i, (co, ci, k) in enumerate(shapes):
             if i:
                 b += ci * px * esz
             b += (4 if i == n - 1 else co * esz) * px
         return b
     D = levels
-    b = 8.0 * px                                   # energy map
+    b = in_bytes * px                              # input maps
     out = []                                       # (channels, pixels) of each layer's output
     for d in range(D):
         p = px >> (2 * d)
@@ -127,12 +128,17 @@ def sha_of(*paths):
     return h.hexdigest()[:16]
 
 
-def pdf_errors_vs_fp32(npg, ctx, model, energy, precision):
+def pdf_errors_vs_fp32(npg, ctx, model, energy, precision, maps5=None):
     """Per-leaf L1 and KL of the low-precision pdf against the FP32 path's
-    (which matches the FP64 oracle within 1e-5 relative), over every leaf."""
+    (which matches the FP64 oracle within 1e-5 relative), over every leaf.
+    maps5: (count, energy_prev, count_prev) of a five-channel model."""
     import torch
-    lo = npg.reconstruct_density(ctx, model, energy, precision).double()
-    hi = npg.reconstruct_density(ctx, model, energy, "fp32").double()
+    if maps5 is None:
+        run = lambda p: npg.reconstruct_density(ctx, model, energy, p).double()
+    else:
+        run = lambda p: npg.reconstruct_density5(ctx, model, energy, *maps5, p).double()
+    lo = run(precision)
+    hi = run("fp32")
     L = lo.shape[0]
     p = lo.reshape(L, -1)
     q = hi.reshape(L, -1)
@@ -145,7 +151,7 @@ def pdf_errors_vs_fp32(npg, ctx, model, energy, precision):
             "kl_median": qs(kl, 0.5), "kl_p99": qs(kl, 0.99), "kl_max": float(kl.max())}
 
 
-def cpu_baseline(workload: str, seconds_hint: float = 20.0):
+def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False):
     """The FP64 oracle, as it stands, on a bounded sample of the workload."""
     from oracle import oracle as orc
     from paper_2010_01775_amd import synth
@@ -156,13 +162,27 @@ def cpu_baseline(workload: str, seconds_hint: float = 20.0):
         b = synth.uniform_batch(L=L, n_queries=L * 1024)
     else:
         raise ValueError(workload)
+    if input5:
+        # iteration t-1 = first half of each leaf's photons, as in the GPU run
+        off = b.leaf_off.astype(np.int64)
+        half = (off[1:] - off[:-1]) // 2
+        perm_p = np.concatenate([np.arange(off[l], off[l] + half[l]) for l in range(L)]).astype(np.uint32)
+        off_p = np.concatenate([[0], np.cumsum(half)]).astype(np.uint32)
+        model5 = synth.unet5_model(1003)
+        rc, Ep, Pp = orc.splat(b.dirs, b.w, off_p, b.H, b.W, perm=perm_p)   # resident, not timed
     t0 = time.perf_counter()
-    ref = orc.pipeline(b)
+    if input5:
+        rc, E, P = orc.splat(b.dirs, b.w, b.leaf_off, b.H, b.W)
+        rc, dens = orc.net_forward5(model5, orc.input5(E, Ep, P, Pp))
+        rc, pdf, marg, cond, total = orc.build_cdf(dens)
+        ref = dict(pdf=pdf, marg=marg, cond=cond)
+    else:
+        ref = orc.pipeline(b)
     rc, d, p, bins = orc.sample(ref["pdf"], ref["marg"], ref["cond"], b.q_leaf, b.q_u)
     dt = time.perf_counter() - t0
     return {"value": L / dt, "unit": "leaves/s", "cores": min(threads, L), "kind": "oracle",
-            "sample": f"{L} leaves x 4096 photons (64x64, U-Net, FP64) end to end plus "
-                      f"{L * 1024} samples; {dt:.1f} s"}
+            "sample": f"{L} leaves x 4096 photons (64x64, {'five-channel ' if input5 else ''}U-Net, FP64) "
+                      f"end to end plus {L * 1024} samples; {dt:.1f} s"}
 
 
 def run_serving(args):
@@ -296,6 +316,9 @@ def main():
     ap.add_argument("--experts", action="store_true",
                     help="five U-Nets chosen by leaf photon count ([0,100), [100,500), [500,1000), "
                          "[1000,5000), [5000,inf)) instead of one")
+    ap.add_argument("--input5", action="store_true",
+                    help="the five-channel network input (maps and photon counts of iterations t and t-1, "
+                         "valid-bin mask) with a masked first layer; FP32 or BF16")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -304,6 +327,9 @@ def main():
 
     if args.workload == "serving":
         return run_serving(args)
+    if args.input5 and (args.experts or args.precision == "fp8"):
+        print("--input5 runs one five-channel U-Net in FP32 or BF16", file=sys.stderr)
+        sys.exit(2)
 
     import torch
 
@@ -335,6 +361,8 @@ def main():
         q_leaf, q_u = i32(ql), f32(qu)
         desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, octree split > 8192 depth <= 6 "
                 f"({L} leaves), 128x128 maps, U-Net 16/32/64/128, 1e8 guided samples")
+    if args.input5:
+        model_bytes = synth.unet5_model(1003)
     model = npg.Model(ctx, model_bytes)
     experts = [model] + [npg.Model(ctx, synth.unet_model(2000 + k)) for k in range(4)] if args.experts else None
     nq = q_leaf.shape[0]
@@ -352,6 +380,21 @@ def main():
           torch.empty(nq, dtype=torch.float32, device=dev),
           torch.empty(nq, dtype=torch.int32, device=dev))
     pe = torch.empty(nq, dtype=torch.float32, device=dev)
+    prev = None
+    if args.input5:
+        # maps of iteration t-1, resident before timing: the first half of each
+        # leaf's photons (photon maps accumulate over iterations)
+        lo_ = out["leaf_off"][:L + 1].long() if pos is not None else off[:L + 1].long()
+        half = (lo_[1:] - lo_[:-1]) // 2
+        off_p = torch.zeros(L + 1, dtype=torch.int64, device=dev)
+        off_p[1:] = torch.cumsum(half, 0)
+        leaf_id = torch.repeat_interleave(torch.arange(L, device=dev), half)
+        idx = lo_[leaf_id] + torch.arange(leaf_id.shape[0], device=dev) - off_p[leaf_id]
+        perm_p = (out["perm"].long()[idx] if pos is not None else idx).to(torch.int32)
+        prev = (torch.empty((L, H, W), dtype=torch.int64, device=dev),
+                torch.empty((L, H, W), dtype=torch.int32, device=dev))
+        npg.splat_histograms(ctx, dirs, w, off_p.to(torch.int32), H, W, perm=perm_p, energy=prev[0], count=prev[1])
+        del leaf_id, idx, perm_p
     hier_out = None
     if pos is not None:
         n = pos.shape[0]
@@ -390,6 +433,8 @@ def main():
         if experts:
             lo = hier_out["off"][:L + 1] if pos is not None else off
             _, expert_leaves[:] = npg.reconstruct_experts(ctx, experts, lo, energy, args.precision, density=dens)
+        elif prev is not None:
+            npg.reconstruct_density5(ctx, model, energy, count, prev[0], prev[1], args.precision, density=dens)
         else:
             npg.reconstruct_density(ctx, model, energy, args.precision, count=count, density=dens)
         mark("recon", 1)
@@ -489,13 +534,13 @@ def main():
         peak, peak_name = PEAK["bf16_mfma_TFLOPs"], "BF16 MFMA"
     achieved = flops / recon_s / 1e12
     esz = {"fp32": 8, "bf16": 2, "fp8": 1}[args.precision]
-    bytes_alg = model_bytes_per_leaf(model_bytes, H, W, esz) * L
+    bytes_alg = model_bytes_per_leaf(model_bytes, H, W, esz, 24.0 if args.input5 else 8.0) * L
     ridge = peak * 1e12 / (PEAK["hbm_GBps"] * 1e9)
     hbm_bound = flops / bytes_alg < ridge        # arithmetic intensity below the ridge point
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
     src_sha = sha_of(os.path.join(ROOT, "paper_2010_01775_amd", "csrc", "net.hip"))
-    if os.path.exists(tfile) and not args.experts:
+    if os.path.exists(tfile) and not args.experts and not args.input5:
         t = json.load(open(tfile))
         if t.get("source_sha") == src_sha:
             traffic = t.get("bytes_per_launch")
@@ -519,7 +564,9 @@ def main():
                                  "fp8": "fp8 e4m3 conv (static per-layer activation scales, "
                                         "per-output-channel weight scales), f32 accumulation"}[args.precision]}
                   | ({"experts": "5 U-Nets by leaf photon count [0,100) [100,500) [500,1000) [1000,5000) "
-                                 "[5000,inf)", "expert_leaves": expert_leaves} if experts else {}),
+                                 "[5000,inf)", "expert_leaves": expert_leaves} if experts else {})
+                  | ({"input": "5 channels: maps and photon counts of iterations t and t-1 (t-1: first half of "
+                               "each leaf's photons), valid-bin mask; masked first layer"} if args.input5 else {}),
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
         "one_sample_mis": mis,
@@ -538,9 +585,10 @@ def main():
                      "avg_launch_ms": avg["recon"], "source_sha": src_sha},
     }
     if args.precision != "fp32":
-        res["precision_vs_fp32"] = pdf_errors_vs_fp32(npg, ctx, model, energy, args.precision)
+        res["precision_vs_fp32"] = pdf_errors_vs_fp32(npg, ctx, model, energy, args.precision,
+                                                      (count, *prev) if prev is not None else None)
     if not args.no_cpu_baseline and args.workload == "uniform":
-        res["cpu_baseline"] = cpu_baseline(args.workload)
+        res["cpu_baseline"] = cpu_baseline(args.workload, input5=args.input5)
     print(json.dumps(res))
     model.free()
     ctx.close()

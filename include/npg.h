@@ -277,8 +277,9 @@ int npg_reconstruct_fused(npg_ctx *ctx, const npg_model *model, const float *dir
  * synthetic leaves of H x W under each pixel-tile size (64, 128, 256, 512 pixels
  * per workgroup) and then the leaf-chunk size, and keeps the fastest choices
  * in ctx for (model, precision, H, W); later reconstruct calls of that shape
- * use them.  The choice never changes a result (every output sums its terms
- * in the same order).  Synchronises `stream`. */
+ * use them (npg_reconstruct_density5 for a five-channel model, which tunes
+ * in FP32 or BF16 only).  The choice never changes a result (every output
+ * sums its terms in the same order).  Synchronises `stream`. */
 int npg_autotune(npg_ctx *ctx, const npg_model *model, int H, int W, npg_precision precision,
                  uint32_t probe_leaves, void *stream);
 

@@ -2133,8 +2133,10 @@ int npg_run_desc_batch(npg_ctx *ctx, const npg_model *m, npg_precision prec, con
 extern "C" int npg_autotune(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision precision,
                             uint32_t probe, void *stream) {
   if (!ctx) return NPG_E_ARG;
-  int rc = check_net_args(ctx, m, H, W, precision);
+  const int in_ch = m ? m->in_ch : 1;
+  int rc = check_net_args(ctx, m, H, W, precision, in_ch);
   if (rc) return rc;
+  if (in_ch == 5 && precision == NPG_FP8) return npg_fail(ctx, NPG_E_ARG, "autotune: five-channel models run FP32 or BF16");
   if (probe == 0) return npg_fail(ctx, NPG_E_ARG, "autotune: probe_leaves = 0");
   rc = npg_set_device(ctx);
   if (rc) return rc;
@@ -2143,18 +2145,33 @@ extern "C" int npg_autotune(npg_ctx *ctx, const npg_model *m, int H, int W, npg_
   const size_t HW = (size_t)H * W;
   const NetPlan plan = plan_net(m, H, W, R.esz);
   const size_t bytes = npg_align(probe * HW * sizeof(uint64_t)) + npg_align(probe * HW * sizeof(float)) +
-                       npg_align(probe * sizeof(double)) + net_bufs_bytes(plan, probe, R.esz);
+                       npg_align(4 * probe * sizeof(double)) + net_bufs_bytes(plan, probe, R.esz);
   void *scr = nullptr;
   rc = npg_scratch(ctx, bytes, s, &scr);
   if (rc) return rc;
   Carver cv(scr);
   uint64_t *energy = cv.take<uint64_t>(probe * HW);
   float *dens = cv.take<float>(probe * HW);
-  double *tot = cv.take<double>(probe);
+  double *tot = cv.take<double>(4 * (size_t)probe);
   const NetBufs B = carve_net(cv, plan, probe, R.esz);
   NPG_HIP_CHECK(ctx, hipMemsetAsync(energy, 0, probe * HW * sizeof(uint64_t), s));
-  NPG_HIP_CHECK(ctx, launch_leaf_scale(energy, probe, (int)HW, tot, s));
-  const Src in{SRC_ENERGY, energy, nullptr, tot, 0, 0};
+  // zero maps; a five-channel model reads them as all four of its maps (the
+  // zero words serve as uint32 counts too)
+  const uint32_t *zc = reinterpret_cast<const uint32_t *>(energy);
+  if (in_ch == 5) {
+    hipLaunchKernelGGL(leaf_totals5_kernel, dim3(probe), dim3(256), 0, s, energy, energy, zc, zc, (int)HW, tot);
+    NPG_HIP_CHECK(ctx, hipGetLastError());
+  } else {
+    NPG_HIP_CHECK(ctx, launch_leaf_scale(energy, probe, (int)HW, tot, s));
+  }
+  auto src_at = [&](uint32_t l0) {
+    if (in_ch == 1) return Src{SRC_ENERGY, energy + l0 * HW, nullptr, tot + l0, 0, 0};
+    Src f{SRC_FIVE, energy + l0 * HW, energy + l0 * HW, tot + 4 * (size_t)l0, 5, 0};
+    f.s2 = zc + l0 * HW;
+    f.s3 = zc + l0 * HW;
+    return f;
+  };
+  const Src in = src_at(0);
   // count the calls of one chunk
   rc = net_chunk(R, in, 1, H, W, dens, B);
   if (rc) return rc;
@@ -2198,8 +2215,7 @@ extern "C" int npg_autotune(npg_ctx *ctx, const npg_model *m, int H, int W, npg_
       (void)hipEventRecord(e0, s);
       for (uint32_t l0 = 0; l0 < probe && !err; l0 += c) {
         const uint32_t Lc = std::min(c, probe - l0);
-        const Src inc{SRC_ENERGY, energy + l0 * HW, nullptr, tot + l0, 0, 0};
-        err = net_chunk(R, inc, (int)Lc, H, W, dens + l0 * HW, B);
+        err = net_chunk(R, src_at(l0), (int)Lc, H, W, dens + l0 * HW, B);
       }
       (void)hipEventRecord(e1, s);
       if (hipStreamSynchronize(s) != hipSuccess) { err = npg_fail(ctx, NPG_E_HIP, "autotune sync"); break; }

@@ -90,6 +90,9 @@ def test_density5_bf16_error_and_chunking(ctx, npg, orc):
         finally:
             ctx.set_option("chunk_leaves", 0)
         assert torch.equal(full, part), prec
+        # autotuned tiles and chunk size change no result
+        npg.autotune(ctx, m, H, H, prec, probe_leaves=4)
+        assert torch.equal(full, npg.reconstruct_density5(ctx, m, *args, prec)), prec
     assert npg.sync_status(ctx) == 0
     m.free()
 
@@ -103,6 +106,7 @@ def test_density5_rejections(ctx, npg):
     for call in (lambda: npg.reconstruct_density5(ctx, m1, e, c, e, c, "fp32"),
                  lambda: npg.reconstruct_density(ctx, m5, e, "fp32"),
                  lambda: npg.reconstruct_density5(ctx, m5, e, c, e, c, "fp8"),
+                 lambda: npg.autotune(ctx, m5, H, H, "fp8", probe_leaves=2),
                  lambda: m5.calibrate_fp8(e)):
         with pytest.raises(npg.NpgError) as ex:
             call()

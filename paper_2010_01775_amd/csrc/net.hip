@@ -372,50 +372,102 @@ __device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, i
 // same way (each value rounded to float32, as the one-channel raw map), and
 // the mask B of bins with photons at t, as a masked (partial) convolution:
 // only taps with B = 1 contribute, and the sum is rescaled by 9/S for the
-// S valid in-map taps (zero output where S = 0), then bias and ReLU.  One
-// thread per output pixel, all output channels; out T [L][H][W][cout].
+// S valid in-map taps (zero output where S = 0), then bias and ReLU.
+//
+// One workgroup per tile of TR x TW output pixels of one leaf (TW = min(W,
+// 256), TR = min(H, 256 / TW); grid = (tiles per leaf, leaves)).  The tile
+// and its one-pixel halo are normalised once into LDS as float4 (x0..x3);
+// bins without photons at t and bins outside the map hold zeros, so their
+// taps add exact zeros, and B = [x2 > 0] (a bin with P > 0 has x2 >= 2^-32 *
+// H*W / H*W > 0).  Each thread then sums its nine taps from LDS in tap-major,
+// channel-minor order and writes its COUT outputs as 16-byte stores;
+// out T [L][H][W][COUT].
+constexpr int F5_LDS = 774;  // (TR + 2) * (TW + 2) for TR * TW = 256, at most 3 * 258
+
 template <class T, class Acc, int COUT>
 __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__restrict__ w,
-                                                          const float *__restrict__ b, int H, int W,
-                                                          size_t npix, void *out) {
-  constexpr int cout = COUT;
-  const size_t HW = (size_t)H * W;
-  for (size_t pix = blockIdx.x * (size_t)blockDim.x + threadIdx.x; pix < npix;
-       pix += (size_t)gridDim.x * blockDim.x) {
-    const size_t leaf = pix / HW;
-    const int r = (int)(pix - leaf * HW), y = r / W, x = r - y * W;
-    const double *tl = s.tot + 4 * leaf;
-    double inv[4];
+                                                          const float *__restrict__ b, int H, int W, int TW,
+                                                          int TR, void *out) {
+  __shared__ float4 tile[F5_LDS];
+  const int tiles_x = W / TW;
+  const int tx0 = (int)(blockIdx.x % (unsigned)tiles_x) * TW, ty0 = (int)(blockIdx.x / (unsigned)tiles_x) * TR;
+  const size_t leaf = blockIdx.y, HW = (size_t)H * W, base = leaf * HW;
+  const double *tl = s.tot + 4 * leaf;
+  double inv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) inv[k] = tl[k] > 0.0 ? (double)HW / tl[k] : 0.0;
-    Acc acc[COUT];
+  for (int k = 0; k < 4; ++k) inv[k] = tl[k] > 0.0 ? (double)HW / tl[k] : 0.0;
+  const uint64_t *e_t = static_cast<const uint64_t *>(s.s0) + base;
+  const uint64_t *e_p = static_cast<const uint64_t *>(s.s1) + base;
+  const uint32_t *p_t = static_cast<const uint32_t *>(s.s2) + base;
+  const uint32_t *p_p = static_cast<const uint32_t *>(s.s3) + base;
+  const int LW = TW + 2, n_in = (TR + 2) * LW, nj = (n_in + 255) / 256;
+  // all loads of the staging first (coordinates clamped into the map, so
+  // every load is in bounds and none waits on another), then the selects
+  uint64_t ve[4][2];
+  uint32_t vp[4][2];
+  bool ok[4];
 #pragma unroll
-    for (int c = 0; c < cout; ++c) acc[c] = (Acc)0;
-    int S = 0;
-    for (int t = 0; t < 9; ++t) {
-      const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
-      if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
-      const size_t i = leaf * HW + (size_t)sy * W + sx;
-      const uint32_t pt = static_cast<const uint32_t *>(s.s2)[i];
-      if (pt == 0) continue;  // mask 0: the tap contributes nothing
-      ++S;
-      const Acc xv[5] = {
-          (Acc)(float)((double)static_cast<const uint64_t *>(s.s0)[i] * inv[0]),
-          (Acc)(float)((double)static_cast<const uint64_t *>(s.s1)[i] * inv[1]),
-          (Acc)(float)((double)pt * inv[2]),
-          (Acc)(float)((double)static_cast<const uint32_t *>(s.s3)[i] * inv[3]), (Acc)1};
-#pragma unroll
-      for (int c = 0; c < cout; ++c)
-#pragma unroll
-        for (int ch = 0; ch < 5; ++ch) acc[c] = fma((Acc)w[(c * 5 + ch) * 9 + t], xv[ch], acc[c]);
+  for (int j = 0; j < 4; ++j) {
+    if (j < nj) {
+      const int i = min((int)threadIdx.x + 256 * j, n_in - 1);
+      const int ly = i / LW, lx = i - ly * LW, sy = ty0 + ly - 1, sx = tx0 + lx - 1;
+      ok[j] = sy >= 0 && sy < H && sx >= 0 && sx < W;
+      const size_t k = (size_t)min(max(sy, 0), H - 1) * W + min(max(sx, 0), W - 1);
+      ve[j][0] = e_t[k];
+      ve[j][1] = e_p[k];
+      vp[j][0] = p_t[k];
+      vp[j][1] = p_p[k];
     }
-    T *o = static_cast<T *>(out) + pix * cout;
+  }
 #pragma unroll
-    for (int c = 0; c < cout; ++c) {
-      Acc v = S > 0 ? (Acc)b[c] + (Acc)(9.0 / (double)S) * acc[c] : (Acc)0;
-      v = v > (Acc)0 ? v : (Acc)0;
-      o[c] = from_d<T>((double)v);
+  for (int j = 0; j < 4; ++j) {
+    const int i = (int)threadIdx.x + 256 * j;
+    if (j < nj && i < n_in) {
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (ok[j] && vp[j][0] != 0)
+        v = make_float4((float)((double)ve[j][0] * inv[0]), (float)((double)ve[j][1] * inv[1]),
+                        (float)((double)vp[j][0] * inv[2]), (float)((double)vp[j][1] * inv[3]));
+      tile[i] = v;
     }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x >= TR * TW) return;
+  const int ly = (int)threadIdx.x / TW, lx = (int)threadIdx.x - ly * TW;
+  Acc acc[COUT];
+#pragma unroll
+  for (int c = 0; c < COUT; ++c) acc[c] = (Acc)0;
+  int S = 0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const float4 v = tile[(ly + t / 3) * LW + lx + t % 3];
+    const int m = v.z > 0.0f;
+    S += m;
+    const Acc xv[5] = {(Acc)v.x, (Acc)v.y, (Acc)v.z, (Acc)v.w, (Acc)m};
+#pragma unroll
+    for (int c = 0; c < COUT; ++c)
+#pragma unroll
+      for (int ch = 0; ch < 5; ++ch) acc[c] = fma((Acc)w[(c * 5 + ch) * 9 + t], xv[ch], acc[c]);
+  }
+  const Acc sc = S > 0 ? (Acc)(9.0 / (double)S) : (Acc)0;
+  T o[COUT];
+#pragma unroll
+  for (int c = 0; c < COUT; ++c) {
+    Acc v = S > 0 ? (Acc)b[c] + sc * acc[c] : (Acc)0;
+    v = v > (Acc)0 ? v : (Acc)0;
+    o[c] = from_d<T>((double)v);
+  }
+  const size_t pix = base + (size_t)(ty0 + ly) * W + tx0 + lx;
+  T *dst = static_cast<T *>(out) + pix * COUT;
+  if constexpr (sizeof(o) % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(o) / 16); ++k) {
+      uint4 q;
+      __builtin_memcpy(&q, reinterpret_cast<const char *>(o) + 16 * k, 16);
+      reinterpret_cast<uint4 *>(dst)[k] = q;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < COUT; ++c) dst[c] = o[c];
   }
 }
 
@@ -1607,14 +1659,17 @@ struct Runner {
     if (src.mode == SRC_FIVE) {
       if (y.k != 3 || y.cin != 5 || act != ACT_RELU || head || prec == NPG_FP8)
         return npg_fail(ctx, NPG_E_ARG, "internal: five-channel first layer");
-      const size_t npix = (size_t)Lc * H * W;
-      const unsigned blocks = (unsigned)std::min<size_t>((npix + 255) / 256, 1u << 20);
+      // tile of TR x TW pixels per workgroup (H, W powers of two, 4..1024)
+      const int TW = std::min(W, 256), TR = std::min(H, 256 / TW);
+      if ((TR + 2) * (TW + 2) > F5_LDS || H % TR || W % TW)
+        return npg_fail(ctx, NPG_E_ARG, "internal: five-channel tile %dx%d", TR, TW);
+      const dim3 grid((unsigned)((H / TR) * (W / TW)), (unsigned)Lc);
       auto go = [&](auto tag_t, auto tag_acc, auto tag_c) {
         using TT = decltype(tag_t);
         using AA = decltype(tag_acc);
         constexpr int C = decltype(tag_c)::value;
-        hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C>), dim3(blocks), dim3(256), 0, s, src, y.w, y.b, H, W,
-                           npix, out);
+        hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C>), grid, dim3(256), 0, s, src, y.w, y.b, H, W, TW, TR,
+                           out);
       };
       auto by_c = [&](auto tag_t, auto tag_acc) {
         switch (y.cout) {

@@ -150,6 +150,26 @@ void npg_model_free(npg_model *model);
 int npg_model_calibrate_fp8(npg_ctx *ctx, npg_model *model, const uint64_t *energy_dev,
                             uint32_t L, int H, int W, void *stream);
 
+/* The paper's hierarchical grid (Sec. 7.1; Sec. 8, path-guiding details): a
+ * regular grid of res^3 voxels over the box [lo, hi], each valid voxel split
+ * into a local binary KD tree. */
+typedef struct {
+  int32_t res;         /* voxels per axis (the paper: 100), 1..1024            */
+  float lo[3], hi[3];  /* scene box, hi > lo per axis                          */
+  double split_count;  /* a node splits if its photon count > split_count ...  */
+  double split_var;    /* ... or its normal variance > split_var (the paper:
+                          500 * sqrt(2^t) at iteration t, and 0.5) ...         */
+  int32_t max_depth;   /* ... while its depth < max_depth (the paper: 8), 0..16 */
+} npg_kdgrid_params;
+
+/* One node of the local KD trees.  info & 3 = split axis (0, 1, 2) with the
+ * children at nodes (info >> 2) and (info >> 2) + 1, points with coordinate
+ * < split going to the first; info & 3 == 3: a leaf, leaf id = info >> 2. */
+typedef struct {
+  float split;
+  uint32_t info;
+} npg_kd_node;
+
 /* ------------------------------------------------------------- hot path */
 
 /* Assigns photons to the leaves of an adaptive octree over the unit box
@@ -175,6 +195,67 @@ int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n, const np
                         uint32_t *perm_dev, uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,
                         uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev, uint32_t max_leaves,
                         uint32_t *n_leaves_out, void *stream);
+
+/* Valid voxels (Sec. 7.1, detecting valid voxels; Algorithm 1, path step):
+ * a voxel is valid iff at least one bounce point of the camera paths lies in
+ * it.  The voxel of a point p is floor((p - lo) * (res / (hi - lo))) per axis,
+ * in FP64 and clamped to [0, res-1]; voxel id = ix + res * (iy + res * iz).
+ *   pts_dev    [n][3] float32 bounce points
+ *   valid_dev  [res^3] out: 1 for valid voxels, 0 otherwise (overwritten)
+ * A non-finite point returns NPG_E_RANGE (it marks nothing). */
+int npg_mark_valid(npg_ctx *ctx, const npg_kdgrid_params *params, const float *pts_dev, uint64_t n,
+                   uint8_t *valid_dev, void *stream);
+
+/* Builds the paper's hierarchical grid over one iteration's photons
+ * (Sec. 7.1 "Voxel subdivision"; Algorithm 1, subdivision step; Sec. 8
+ * parameters).  Photons in invalid voxels are dropped.  A node (a valid
+ * voxel holding photons, depth 0, or a sub-voxel) with M photons splits iff
+ * depth < max_depth, M >= 2 and (M > split_count or V > split_var), where V
+ * = 1 - |mean normal|^2 over its photons, from integer sums of the normals
+ * quantised as rint(clamp(n, -1, 1) * 2^20) and evaluated in FP64 as
+ * 1 - ((Sx*Sx + Sy*Sy) + Sz*Sz) / ((M*M) * 2^40) (no normals: V = 0).  The
+ * split axis is the longest of the node's box (ties: lower axis; a voxel's
+ * box is [lo + i*step, lo + (i+1)*step], step = (hi - lo) / res in FP64, cut
+ * at each split); the split coordinate s is the (M/2)-th smallest (0-based)
+ * photon coordinate on that axis (-0 read as +0); photons with coordinate
+ * < s go to the first child.  A node with no photon below s stays a leaf.
+ * Leaves are numbered voxel by voxel in ascending voxel id, depth first
+ * with the first child first.
+ *   pos_dev       [n][3] float32 photon positions
+ *   normal_dev    [n][3] float32 unit surface normals at the hit points, or
+ *                 NULL (the variance criterion is then off)
+ *   valid_dev     [res^3] voxel validity (npg_mark_valid), or NULL (all valid)
+ *   perm_dev      [n] out: photon indices grouped by leaf, ascending within a
+ *                 leaf; leaf l owns perm[off[l]..off[l+1]), off[L] = number of
+ *                 photons in valid voxels (the rest of perm is unspecified)
+ *   leaf_off_dev  [max_leaves+1] out: CSR offsets into perm
+ *   cell_root_dev [res^3] out: root node of each voxel, -1 for voxels that
+ *                 are invalid or hold no photon
+ *   nodes_dev     [2*max_leaves] out: the trees (npg_kd_node), the voxels'
+ *                 roots first in ascending voxel id, then level by level
+ *   n_leaves_out, n_nodes_out  host out: L and the number of nodes
+ * Synchronises `stream`.  A non-finite position, or a non-finite normal of a
+ * photon in a valid voxel, returns NPG_E_RANGE; more than max_leaves leaves
+ * NPG_E_CAPACITY (outputs
+ * unspecified, *n_leaves_out = 0).  n <= 2^32 - 1, max_leaves < 2^29. */
+int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, const float *pos_dev,
+                     const float *normal_dev, uint64_t n, const uint8_t *valid_dev, uint32_t *perm_dev,
+                     uint32_t *leaf_off_dev, int32_t *cell_root_dev, npg_kd_node *nodes_dev, uint32_t max_leaves,
+                     uint32_t *n_leaves_out, uint32_t *n_nodes_out, void *stream);
+
+/* Point location in the hierarchical grid (Sec. 8: the voxel in O(1), then
+ * O(depth) down its local tree): the leaf containing each query point, or
+ * 0xFFFFFFFF in voxels without a tree.  The voxel rule is that of
+ * npg_mark_valid; a point with coordinate < split descends to the first
+ * child (-0 read as +0).
+ *   q_dev         [n][3] float32 query points
+ *   cell_root_dev, nodes_dev, n_nodes: as written by npg_build_kdgrid
+ *   leaf_dev      [n] out: leaf ids
+ * A non-finite point, or a node index >= n_nodes met in the walk, gives
+ * 0xFFFFFFFF and NPG_E_RANGE at the next npg_sync_status. */
+int npg_locate(npg_ctx *ctx, const npg_kdgrid_params *params, const int32_t *cell_root_dev,
+               const npg_kd_node *nodes_dev, uint32_t n_nodes, const float *q_dev, uint64_t n, uint32_t *leaf_dev,
+               void *stream);
 
 /* Bins photons into per-leaf energy and count maps (Eq. "photon": the
  * energy of bin k of voxel j is the sum of the energies of the voxel's

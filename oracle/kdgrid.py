@@ -117,11 +117,11 @@ def build(pos, normal, valid, res, lo, hi, split_count, split_var, max_depth):
     pos = np.asarray(pos, np.float32)
     if not np.all(np.isfinite(pos)):
         raise ValueError("non-finite position")
-    if normal is not None and not np.all(np.isfinite(normal)):
-        raise ValueError("non-finite normal")
     g = KDGrid(res, lo, hi)
     cid = cell_ids(pos, res, lo, hi) if len(pos) else np.zeros(0, np.int64)
     keep = np.ones(len(pos), bool) if valid is None else np.asarray(valid)[cid] != 0
+    if normal is not None and not np.all(np.isfinite(np.asarray(normal)[keep])):
+        raise ValueError("non-finite normal of a photon in a valid voxel")
     step = (hi64 - lo64) / float(res)
     idx_all = np.nonzero(keep)[0]
     order = np.argsort(cid[idx_all], kind="stable")

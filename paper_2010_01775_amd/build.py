@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnpg.so")
-SOURCES = ["api.hip", "splat.hip", "net.hip", "cdf.hip", "sample.hip", "hier.hip", "serve.hip", "experts.hip"]
+SOURCES = ["api.hip", "splat.hip", "net.hip", "cdf.hip", "sample.hip", "hier.hip", "serve.hip", "experts.hip", "kdgrid.hip"]
 ARCH = os.environ.get("NPG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -363,6 +363,48 @@ static hipError_t scan_u32(const uint32_t *in, uint64_t n, uint32_t *out, uint32
   return hipGetLastError();
 }
 
+size_t npg_scan_tmp_words(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t npg_scan_u32(const uint32_t *in, uint64_t n, uint32_t *out, uint32_t *tmp, hipStream_t s) {
+  return scan_u32(in, n, out, tmp, s);
+}
+
+size_t npg_radix_work_bytes(uint64_t n) {
+  const uint64_t nb = (n + RS_TILE - 1) / RS_TILE, nhist = 256 * (nb ? nb : 1);
+  const uint64_t m = n ? n : 1;
+  return 4 * npg_align(4 * m) + 2 * npg_align(4 * (nhist + 1)) + npg_align(4 * npg_scan_tmp_words(nhist));
+}
+
+hipError_t npg_radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint64_t n, int bits,
+                          uint32_t *keys_out, uint32_t *vals_out, void *work, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (bits < 1 || bits > 32) return hipErrorInvalidValue;
+  const uint32_t nb = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+  const uint64_t nhist = 256ull * nb;
+  Carver cv(work);
+  uint32_t *ka = cv.take<uint32_t>(n), *kb = cv.take<uint32_t>(n);
+  uint32_t *va = cv.take<uint32_t>(n), *vb = cv.take<uint32_t>(n);
+  uint32_t *hist = cv.take<uint32_t>(nhist + 1), *offs = cv.take<uint32_t>(nhist + 1);
+  uint32_t *btmp = cv.take<uint32_t>(npg_scan_tmp_words(nhist));
+  const int passes = (bits + 7) / 8;
+  const uint32_t *kin = keys_in, *vin = vals_in;
+  for (int p = 0; p < passes; ++p) {
+    const bool last = p == passes - 1;
+    uint32_t *kout = last ? keys_out : ((p & 1) ? kb : ka);
+    uint32_t *vout = last ? vals_out : ((p & 1) ? vb : va);
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, s, kin, n, 8 * p, nb, hist);
+    hipError_t e = scan_u32(hist, nhist, offs, btmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(RS_THREADS), 0, s, kin, vin, n, 8 * p, nb, offs, kout,
+                       vout);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    kin = kout;
+    vin = vout;
+  }
+  return hipSuccess;
+}
+
 extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n,
                                    const npg_hier_params *params, uint32_t *perm_dev,
                                    uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,

@@ -228,3 +228,15 @@ hipError_t launch_sample_mis(const float2 *bnd, const npg_tables &t, const float
 hipError_t launch_eval_mis(const float2 *bnd, const npg_tables &t, const float *alpha, const uint32_t *leaf,
                            const float *normal, const float *dir, uint64_t n, float *pdf, uint32_t *err,
                            hipStream_t s);
+
+// Exclusive scan of n u32 into out[0..n] (out[n] = total); tmp holds
+// npg_scan_tmp_words(n) words.
+size_t npg_scan_tmp_words(uint64_t n);
+hipError_t npg_scan_u32(const uint32_t *in, uint64_t n, uint32_t *out, uint32_t *tmp, hipStream_t s);
+// Stable LSD radix sort (8-bit digits) of n (key, value) pairs on the low
+// `bits` (1..32) bits of the keys; vals_in == nullptr: the values are the
+// item indices.  The sorted pairs go to keys_out / vals_out (distinct from
+// the inputs); work holds npg_radix_work_bytes(n) bytes.
+size_t npg_radix_work_bytes(uint64_t n);
+hipError_t npg_radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint64_t n, int bits,
+                          uint32_t *keys_out, uint32_t *vals_out, void *work, hipStream_t s);

@@ -8,6 +8,7 @@ library has not been built (``python -m paper_2010_01775_amd.build``).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -23,7 +24,8 @@ PRECISION = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
 SYMBOLS = [
     "npg_create", "npg_destroy", "npg_last_error", "npg_sync_status", "npg_memory_usage",
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
-    "npg_build_hierarchy", "npg_splat_histograms", "npg_normalize_input",
+    "npg_build_hierarchy", "npg_mark_valid", "npg_build_kdgrid", "npg_locate",
+    "npg_splat_histograms", "npg_normalize_input",
     "npg_reconstruct_density", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
     "npg_mis_alpha", "npg_sample_mis", "npg_eval_pdf_mis", "npg_reconstruct_density5",
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
@@ -46,6 +48,11 @@ class Tables(C.Structure):
 
 class HierParams(C.Structure):
     _fields_ = [("split_count", C.c_uint32), ("max_depth", C.c_int32)]
+
+
+class KDGridParams(C.Structure):
+    _fields_ = [("res", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("split_count", C.c_double),
+                ("split_var", C.c_double), ("max_depth", C.c_int32)]
 
 
 class ServeParams(C.Structure):
@@ -81,6 +88,10 @@ def load_library(path: str = LIB_PATH):
         "npg_model_calibrate_fp8": (I, [P, P, P, U32, I, I, P]),
         "npg_build_hierarchy": (I, [P, P, U64, C.POINTER(HierParams), P, P, P, P, P, U32,
                                     C.POINTER(U32), P]),
+        "npg_mark_valid": (I, [P, C.POINTER(KDGridParams), P, U64, P, P]),
+        "npg_build_kdgrid": (I, [P, C.POINTER(KDGridParams), P, P, U64, P, P, P, P, P, U32, C.POINTER(U32),
+                                 C.POINTER(U32), P]),
+        "npg_locate": (I, [P, C.POINTER(KDGridParams), P, P, U32, P, U64, P, P]),
         "npg_splat_histograms": (I, [P, P, P, P, P, U32, I, I, P, P, I, P]),
         "npg_normalize_input": (I, [P, P, U32, I, I, P, P]),
         "npg_reconstruct_density": (I, [P, P, P, P, U32, I, I, I, P, P]),
@@ -249,6 +260,73 @@ def build_hierarchy(ctx: Context, pos, split_count: int = 8192, max_depth: int =
     L = nl.value
     return dict(perm=perm, leaf_of=leaf_of, leaf_off=off[:L + 1], key=key[:L], depth=depth[:L],
                 n_leaves=L)
+
+
+# the paper's grid: 100^3 voxels, split while the count exceeds 500 * sqrt(2^t)
+# at iteration t or the normal variance exceeds 0.5, local trees of depth <= 8
+PAPER_GRID_RES = 100
+PAPER_SPLIT_VAR = 0.5
+PAPER_MAX_DEPTH = 8
+
+
+def paper_split_count(t: int, c: float = 500.0) -> float:
+    return c * math.sqrt(2.0 ** t)
+
+
+def kdgrid_params(res=PAPER_GRID_RES, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), split_count=None,
+                  split_var=PAPER_SPLIT_VAR, max_depth=PAPER_MAX_DEPTH) -> KDGridParams:
+    sc = paper_split_count(1) if split_count is None else float(split_count)
+    return KDGridParams(int(res), (C.c_float * 3)(*lo), (C.c_float * 3)(*hi), sc, float(split_var), int(max_depth))
+
+
+def mark_valid(ctx: Context, params: KDGridParams, pts, valid=None, stream=None):
+    """uint8 [res^3] mask of the voxels holding at least one point."""
+    _dev(pts, torch.float32, "pts")
+    if valid is None:
+        valid = torch.empty(params.res ** 3, dtype=torch.uint8, device=pts.device)
+    ctx.check(ctx.lib.npg_mark_valid(ctx.h, C.byref(params), _ptr(pts), pts.shape[0], _ptr(valid), _stream(stream)))
+    return valid
+
+
+def build_kdgrid(ctx: Context, params: KDGridParams, pos, normal=None, valid=None, max_leaves: int | None = None,
+                 stream=None, out=None):
+    """The hierarchical grid over the photons; returns a dict of device
+    tensors (perm, leaf_off, cell_root, nodes as int32 pairs) and counts.
+    out: optional dict of preallocated perm / leaf_off / cell_root / nodes."""
+    _dev(pos, torch.float32, "pos")
+    n = pos.shape[0]
+    dev = pos.device
+    if normal is not None:
+        _dev(normal, torch.float32, "normal")
+    if valid is not None:
+        _dev(valid, torch.uint8, "valid")
+    if max_leaves is None:
+        max_leaves = max(1, min(n, (1 << 29) - 1))
+    nv = params.res ** 3
+    o = out or {}
+    perm = o.get("perm") if o.get("perm") is not None else torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    off = o.get("leaf_off") if o.get("leaf_off") is not None else torch.empty(max_leaves + 1, dtype=torch.int32,
+                                                                             device=dev)
+    root = o.get("cell_root") if o.get("cell_root") is not None else torch.empty(nv, dtype=torch.int32, device=dev)
+    nodes = o.get("nodes") if o.get("nodes") is not None else torch.empty((2 * max_leaves, 2), dtype=torch.int32,
+                                                                           device=dev)
+    nl, nn = C.c_uint32(0), C.c_uint32(0)
+    ctx.check(ctx.lib.npg_build_kdgrid(ctx.h, C.byref(params), _ptr(pos), _ptr(normal), n, _ptr(valid), _ptr(perm),
+                                       _ptr(off), _ptr(root), _ptr(nodes), max_leaves, C.byref(nl), C.byref(nn),
+                                       _stream(stream)))
+    L = nl.value
+    return dict(perm=perm, leaf_off=off[:L + 1], cell_root=root, nodes=nodes[:nn.value], n_leaves=L,
+                n_nodes=nn.value)
+
+
+def locate(ctx: Context, params: KDGridParams, grid: dict, q, out=None, stream=None):
+    """Leaf id (uint32 bits in int32; -1 = none) of each query point."""
+    _dev(q, torch.float32, "q")
+    if out is None:
+        out = torch.empty(q.shape[0], dtype=torch.int32, device=q.device)
+    ctx.check(ctx.lib.npg_locate(ctx.h, C.byref(params), _ptr(grid["cell_root"]), _ptr(grid["nodes"]),
+                                 grid["n_nodes"], _ptr(q), q.shape[0], _ptr(out), _stream(stream)))
+    return out
 
 
 def splat_histograms(ctx: Context, dirs, w, leaf_off, H: int, W: int, perm=None, energy=None,

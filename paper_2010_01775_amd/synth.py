@@ -188,6 +188,44 @@ def unet5_model(seed: int, levels=(16, 32, 64, 128), random_bias=False) -> bytes
     return pack_model(ARCH_UNET, len(levels), ws, bs)
 
 
+def surface_normals(seed: int, pos: np.ndarray, field_res: int = 32, crease_frac: float = 0.25,
+                    jitter: float = 0.15, chunk: int = 5_000_000) -> np.ndarray:
+    """Unit surface normals at photon hit points, float32 [n,3].
+
+    A fixed field_res^3 lattice of patches over the unit box: each patch has
+    a random normal; a crease_frac share of them is a crease, the half on
+    the far side of a random plane through the patch centre taking a second
+    random normal.  Each photon takes its patch's normal plus Gaussian jitter
+    (std `jitter` per component), renormalised.
+    """
+    rng = rng_for(seed)
+    nf = field_res ** 3
+    n1 = unit_vectors(rng, nf)
+    n2 = unit_vectors(rng, nf)
+    crease = rng.random(nf) < crease_frac
+    plane = unit_vectors(rng, nf)
+    out = np.empty((pos.shape[0], 3), np.float32)
+    for s0 in range(0, pos.shape[0], chunk):
+        p = pos[s0:s0 + chunk].astype(np.float64)
+        ijk = np.clip((p * field_res).astype(np.int64), 0, field_res - 1)
+        f = ijk[:, 0] + field_res * (ijk[:, 1] + field_res * ijk[:, 2])
+        centre = (ijk + 0.5) / field_res
+        far = crease[f] & (np.sum((p - centre) * plane[f], axis=1) > 0)
+        v = np.where(far[:, None], n2[f], n1[f]) + jitter * rng.standard_normal((p.shape[0], 3))
+        out[s0:s0 + chunk] = (v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    return out
+
+
+def bounce_points(seed: int, pos: np.ndarray, n: int, spread: float = 0.01) -> np.ndarray:
+    """Stand-ins for the bounce points of camera paths, float32 [n,3]: random
+    photon positions moved by Gaussian noise of std `spread`, clipped to the
+    unit box (camera paths reach roughly where photons land)."""
+    rng = rng_for(seed)
+    i = rng.integers(0, pos.shape[0], n)
+    p = pos[i].astype(np.float64) + spread * rng.standard_normal((n, 3))
+    return np.clip(p, 0.0, np.nextafter(1.0, 0.0)).astype(np.float32)
+
+
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------

@@ -316,6 +316,10 @@ def main():
     ap.add_argument("--experts", action="store_true",
                     help="five U-Nets chosen by leaf photon count ([0,100), [100,500), [500,1000), "
                          "[1000,5000), [5000,inf)) instead of one")
+    ap.add_argument("--hierarchy", default="octree", choices=["octree", "kdgrid"],
+                    help="clustered workload: the count-threshold octree, or the paper's hierarchical grid "
+                         "(100^3 voxels, valid voxels from bounce points, local KD trees split by photon count "
+                         "> 500 sqrt(2) or normal variance > 0.5, depth <= 8)")
     ap.add_argument("--input5", action="store_true",
                     help="the five-channel network input (maps and photon counts of iterations t and t-1, "
                          "valid-bin mask) with a masked first layer; FP32 or BF16")
@@ -352,15 +356,26 @@ def main():
                 "U-Net 16/32/64/128, 1048576 guided samples")
     else:
         cp = synth.clustered_photons()
-        H = W = 128
+        # the paper's grid yields ~20x more (and smaller) leaves than the
+        # octree: 64x64 maps keep their tables within HBM
+        H = W = 64 if args.hierarchy == "kdgrid" else 128
         pos, dirs, w = f32(cp.pos), f32(cp.dirs), i32(cp.w)
         model_bytes = synth.unet_model(1002)
-        out = npg.build_hierarchy(ctx, pos, 8192, 6, max_leaves=65536)
+        if args.hierarchy == "kdgrid":
+            kprm = npg.kdgrid_params()
+            knrm = f32(synth.surface_normals(1003, cp.pos))
+            kvalid = npg.mark_valid(ctx, kprm, f32(synth.bounce_points(1004, cp.pos, 2_000_000)))
+            out = npg.build_kdgrid(ctx, kprm, pos, knrm, kvalid, max_leaves=1 << 20)
+            hier_desc = (f"paper hierarchy: 100^3 grid, valid voxels from 2e6 bounce points, local KD split "
+                         f"count > {kprm.split_count:.1f} or normal variance > 0.5, depth <= 8")
+        else:
+            out = npg.build_hierarchy(ctx, pos, 8192, 6, max_leaves=65536)
+            hier_desc = "octree split > 8192 depth <= 6"
         L = out["n_leaves"]
         ql, qu = synth.queries(1102, L, 100_000_000)
         q_leaf, q_u = i32(ql), f32(qu)
-        desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, octree split > 8192 depth <= 6 "
-                f"({L} leaves), 128x128 maps, U-Net 16/32/64/128, 1e8 guided samples")
+        desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, {hier_desc} "
+                f"({L} leaves), {H}x{W} maps, U-Net 16/32/64/128, 1e8 guided samples")
     if args.input5:
         model_bytes = synth.unet5_model(1003)
     model = npg.Model(ctx, model_bytes)
@@ -398,8 +413,12 @@ def main():
     hier_out = None
     if pos is not None:
         n = pos.shape[0]
+        cap = (1 << 20) if args.hierarchy == "kdgrid" else 65536
         hier_out = dict(perm=torch.empty(n, dtype=torch.int32, device=dev),
-                        off=torch.empty(65537, dtype=torch.int32, device=dev))
+                        off=torch.empty(cap + 1, dtype=torch.int32, device=dev))
+        if args.hierarchy == "kdgrid":
+            hier_out["root"] = torch.empty(100 ** 3, dtype=torch.int32, device=dev)
+            hier_out["nodes"] = torch.empty((2 * cap, 2), dtype=torch.int32, device=dev)
 
     stages = ["hier", "splat", "recon", "cdf", "sample", "eval"] if pos is not None else \
              ["splat", "recon", "cdf", "sample", "eval"]
@@ -416,11 +435,20 @@ def main():
             import ctypes as C
             mark("hier", 0)
             nl = C.c_uint32(0)
-            prm = npg.HierParams(8192, 6)
-            ctx.check(ctx.lib.npg_build_hierarchy(ctx.h, pos.data_ptr(), pos.shape[0], C.byref(prm),
-                                                  hier_out["perm"].data_ptr(), None,
-                                                  hier_out["off"].data_ptr(), None, None, 65536,
-                                                  C.byref(nl), stream.cuda_stream))
+            if args.hierarchy == "kdgrid":
+                nn = C.c_uint32(0)
+                ctx.check(ctx.lib.npg_build_kdgrid(ctx.h, C.byref(kprm), pos.data_ptr(), knrm.data_ptr(),
+                                                   pos.shape[0], kvalid.data_ptr(), hier_out["perm"].data_ptr(),
+                                                   hier_out["off"].data_ptr(), hier_out["root"].data_ptr(),
+                                                   hier_out["nodes"].data_ptr(), 1 << 20, C.byref(nl),
+                                                   C.byref(nn), stream.cuda_stream))
+            else:
+                prm = npg.HierParams(8192, 6)
+                ctx.check(ctx.lib.npg_build_hierarchy(ctx.h, pos.data_ptr(), pos.shape[0], C.byref(prm),
+                                                      hier_out["perm"].data_ptr(), None,
+                                                      hier_out["off"].data_ptr(), None, None, 65536,
+                                                      C.byref(nl), stream.cuda_stream))
+            assert nl.value == L
             mark("hier", 1)
             lo = hier_out["off"][:L + 1]
             mark("splat", 0)
@@ -524,6 +552,27 @@ def main():
 
     avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
     mis = mis_rates()
+    locate = None
+    if pos is not None and args.hierarchy == "kdgrid":
+        # point location at render time (outside the timed steps): 2e7 points
+        # near where photons land, with the grid of the last timed build
+        kq = f32(synth.bounce_points(1005, cp.pos, 20_000_000))
+        grid = dict(cell_root=hier_out["root"], nodes=hier_out["nodes"], n_nodes=int(out["n_nodes"]))
+        kl = torch.empty(kq.shape[0], dtype=torch.int32, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tl = []
+        for r in range(4):
+            e0.record(stream)
+            npg.locate(ctx, kprm, grid, kq, out=kl)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r:
+                tl.append(e0.elapsed_time(e1))
+        if npg.sync_status(ctx) != 0:
+            raise RuntimeError("data-dependent error in point location")
+        locate = {"queries": kq.shape[0], "per_s": kq.shape[0] / (np.mean(tl) / 1e3),
+                  "located_fraction": float((kl != -1).float().mean()),
+                  "build_photons_per_s": pos.shape[0] / (avg["hier"] / 1e3), "nodes": int(out["n_nodes"])}
     recon_s = avg["recon"] / 1e3
     flops = flops_leaf * L
     if args.precision == "fp32":
@@ -570,6 +619,7 @@ def main():
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
         "one_sample_mis": mis,
+        **({"kdgrid_locate": locate} if locate else {}),
         "p50_ms": float(np.percentile(per_step, 50)),
         "p99_ms": float(np.percentile(per_step, 99)),
         "stage_ms": avg,

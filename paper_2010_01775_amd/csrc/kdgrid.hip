@@ -144,18 +144,23 @@ __global__ __launch_bounds__(256) void kd_root_counts_kernel(Level lv, uint32_t 
   if (j < n0) lv.count[j] = (j + 1 < n0 ? lv.start[j + 1] : *nvalid) - lv.start[j];
 }
 
-// Workgroup-wide sums and scans over KD_THREADS threads.
-__device__ __forceinline__ long long wg_sum_i64(long long v, long long *red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Workgroup-wide sums of three int64 values (exact, so the order is free).
+__device__ __forceinline__ void wg_sum3_i64(long long v[3], long long (*red)[KD_THREADS / 64]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  long long t = 0;
 #pragma unroll
-  for (int w = 0; w < KD_THREADS / 64; ++w) t += red[w];
-  return t;
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[a] += __shfl_xor(v[a], o);
+    if (lane == 0) red[a][wave] = v[a];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    long long t = 0;
+#pragma unroll
+    for (int w = 0; w < KD_THREADS / 64; ++w) t += red[a][w];
+    v[a] = t;
+  }
 }
 
 // Split test and median selection, one workgroup per node of the level.
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
                                                                double split_var, uint32_t *__restrict__ tkey,
                                                                uint32_t *__restrict__ sflag,
                                                                uint32_t *__restrict__ sel, uint32_t *err) {
-  __shared__ long long red[KD_THREADS / 64];
+  __shared__ long long red[3][KD_THREADS / 64];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[KD_THREADS / 64];
   __shared__ uint32_t pick[2];
@@ -192,9 +197,8 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
         }
       }
       if (bad) raise_err(err, ERR_RANGE);
-      const double sx = (double)wg_sum_i64(s[0], red);
-      const double sy = (double)wg_sum_i64(s[1], red);
-      const double sz = (double)wg_sum_i64(s[2], red);
+      wg_sum3_i64(s, red);
+      const double sx = (double)s[0], sy = (double)s[1], sz = (double)s[2];
       const double num = __dadd_rn(__dadd_rn(__dmul_rn(sx, sx), __dmul_rn(sy, sy)), __dmul_rn(sz, sz));
       const double den = __dmul_rn(__dmul_rn((double)M, (double)M), KD_QSCALE * KD_QSCALE);
       const double V = __dsub_rn(1.0, __ddiv_rn(num, den));
@@ -262,24 +266,23 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
   }
 }
 
-// Partition / leaf emission, one workgroup per node of the level.
+// Partition / leaf emission, one workgroup per node of the level.  A node
+// that does not split keeps its segment where it is and takes leaf slot
+// leaf_base + (number of non-splitting nodes before it); a splitting node
+// partitions its segment into tmp and copies it back in place.
 __global__ __launch_bounds__(KD_THREADS) void kd_partition_kernel(
-    const uint32_t *__restrict__ perm_in, uint32_t *__restrict__ perm_next, uint32_t *__restrict__ perm_out,
-    const uint32_t *__restrict__ tkey, Level lv, Level nx, const uint32_t *__restrict__ sflag,
-    const uint32_t *__restrict__ srank, const uint32_t *__restrict__ sel, uint32_t node_base_next,
-    npg_kd_node *__restrict__ nodes, uint32_t *__restrict__ leaf_start, uint32_t *__restrict__ leaf_node,
-    uint32_t *leaf_count, uint32_t max_leaves) {
+    uint32_t *__restrict__ perm, uint32_t *__restrict__ tmp, const uint32_t *__restrict__ tkey, Level lv, Level nx,
+    const uint32_t *__restrict__ sflag, const uint32_t *__restrict__ srank, const uint32_t *__restrict__ sel,
+    uint32_t node_base_next, npg_kd_node *__restrict__ nodes, uint32_t *__restrict__ leaf_start,
+    uint32_t *__restrict__ leaf_node, uint32_t leaf_base) {
   __shared__ uint32_t wl[KD_THREADS / 64], wr[KD_THREADS / 64];
   const uint32_t j = blockIdx.x;
   const uint32_t start = lv.start[j], M = lv.count[j], id = lv.id[j];
   if (!sflag[j]) {
-    for (uint32_t i = threadIdx.x; i < M; i += KD_THREADS) perm_out[start + i] = perm_in[start + i];
     if (threadIdx.x == 0) {
-      const uint32_t slot = atomicAdd(leaf_count, 1u);
-      if (slot < max_leaves) {
-        leaf_start[slot] = start;
-        leaf_node[slot] = id;
-      }
+      const uint32_t slot = leaf_base + (j - srank[j]);
+      leaf_start[slot] = start;
+      leaf_node[slot] = id;
     }
     return;
   }
@@ -311,12 +314,14 @@ __global__ __launch_bounds__(KD_THREADS) void kd_partition_kernel(
     if (act) {
       const uint32_t dst = left ? start + ol + (uint32_t)__popcll(bl & below)
                                 : start + less + orr + (uint32_t)__popcll(br & below);
-      perm_next[dst] = perm_in[start + i];
+      tmp[dst] = perm[start + i];
     }
     lbase += tl;
     rbase += tr;
     __syncthreads();
   }
+  // every read of the segment is done (barrier above): copy back in place
+  for (uint32_t i = threadIdx.x; i < M; i += KD_THREADS) perm[start + i] = tmp[start + i];
   if (threadIdx.x == 0) {
     const float s = okey_inv(key);
     nodes[id].split = s;
@@ -458,7 +463,7 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   const uint64_t cap = max_leaves;
   // scratch
   const size_t sort_work = npg_radix_work_bytes(std::max<uint64_t>(m, cap));
-  size_t bytes = 7 * npg_align(4 * m) + npg_align(4 * (m + 1)) + sort_work;
+  size_t bytes = 5 * npg_align(4 * m) + npg_align(4 * (m + 1)) + sort_work;
   bytes += npg_align(4 * npg_scan_tmp_words(std::max<uint64_t>(m, cap)));
   bytes += 2 * (3 * npg_align(4 * cap) + npg_align(48 * cap));   // two levels
   bytes += 2 * npg_align(4 * (cap + 1)) + npg_align(12 * cap);   // sflag, srank, sel
@@ -468,9 +473,8 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   if (rc) return rc;
   Carver cv(scr);
   uint32_t *key = cv.take<uint32_t>(m), *ks = cv.take<uint32_t>(m);
-  uint32_t *pa = cv.take<uint32_t>(m), *pb = cv.take<uint32_t>(m);
+  uint32_t *pa = cv.take<uint32_t>(m);  // partition staging
   uint32_t *tkey = cv.take<uint32_t>(m), *flag = cv.take<uint32_t>(m);
-  uint32_t *spare = cv.take<uint32_t>(m);
   uint32_t *seg = cv.take<uint32_t>(m + 1);
   void *work = cv.take<char>(sort_work);
   uint32_t *stmp = cv.take<uint32_t>(npg_scan_tmp_words(std::max<uint64_t>(m, cap)));
@@ -485,8 +489,7 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   uint32_t *sel = cv.take<uint32_t>(3 * cap);
   uint32_t *lstart = cv.take<uint32_t>(cap), *lnode = cv.take<uint32_t>(cap);
   uint32_t *lstart_s = cv.take<uint32_t>(cap), *lnode_s = cv.take<uint32_t>(cap);
-  uint32_t *ctr = cv.take<uint32_t>(4);  // [0] photons in valid voxels, [1] leaves
-  (void)spare;
+  uint32_t *ctr = cv.take<uint32_t>(4);  // [0] photons in valid voxels
 
   NPG_HIP_CHECK(ctx, hipMemsetAsync(ctr, 0, 16, s));
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, cell_root_dev, nvox, -1);
@@ -498,7 +501,7 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
     NPG_HIP_CHECK(ctx, hipGetLastError());
     int bits = 1;
     while (bits < 32 && (1ull << bits) <= (uint64_t)sent) ++bits;
-    NPG_HIP_CHECK(ctx, npg_radix_sort(key, nullptr, n, bits, ks, pa, work, s));
+    NPG_HIP_CHECK(ctx, npg_radix_sort(key, nullptr, n, bits, ks, perm_dev, work, s));
     hipLaunchKernelGGL(kd_seg_kernel, dim3(grid_for(n)), dim3(256), 0, s, ks, n, sent, flag, ctr);
     NPG_HIP_CHECK(ctx, hipGetLastError());
     NPG_HIP_CHECK(ctx, npg_scan_u32(flag, n, seg, stmp, s));
@@ -519,10 +522,9 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   // levels
   uint32_t active = n0, nodes_total = n0;
   uint64_t emitted = 0;
-  uint32_t *pin = pa, *pnext = pb;
   for (int depth = 0; active > 0; ++depth) {
     Level &cur = lv[depth & 1], &nxt = lv[(depth + 1) & 1];
-    hipLaunchKernelGGL(kd_select_kernel, dim3(active), dim3(KD_THREADS), 0, s, pos_dev, normal_dev, pin, cur, depth,
+    hipLaunchKernelGGL(kd_select_kernel, dim3(active), dim3(KD_THREADS), 0, s, pos_dev, normal_dev, perm_dev, cur, depth,
                        params->max_depth, params->split_count, params->split_var, tkey, sflag, sel, ctx->err_dev);
     NPG_HIP_CHECK(ctx, hipGetLastError());
     NPG_HIP_CHECK(ctx, npg_scan_u32(sflag, active, srank, stmp, s));
@@ -531,22 +533,22 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
     NPG_HIP_CHECK(ctx, hipStreamSynchronize(s));
     // leaves so far + this level's + at least one per child: the bound keeps
     // the next level's records and every leaf slot within max_leaves
+    const uint32_t leaf_base = (uint32_t)emitted;
     emitted += active - nsplit;
     if (emitted + 2ull * nsplit > cap)
       return npg_fail(ctx, NPG_E_CAPACITY, "build_kdgrid: more than max_leaves %u leaves", max_leaves);
-    hipLaunchKernelGGL(kd_partition_kernel, dim3(active), dim3(KD_THREADS), 0, s, pin, pnext, perm_dev, tkey, cur,
-                       nxt, sflag, srank, sel, nodes_total, nodes_dev, lstart, lnode, ctr + 1, max_leaves);
+    hipLaunchKernelGGL(kd_partition_kernel, dim3(active), dim3(KD_THREADS), 0, s, perm_dev, pa, tkey, cur, nxt,
+                       sflag, srank, sel, nodes_total, nodes_dev, lstart, lnode, leaf_base);
     NPG_HIP_CHECK(ctx, hipGetLastError());
     nodes_total += 2 * nsplit;
     active = 2 * nsplit;
-    std::swap(pin, pnext);
   }
   uint32_t hc[2] = {0, 0}, errw = 0;
   NPG_HIP_CHECK(ctx, hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, s));
   rc = take_err(ctx, s, &errw);
   if (rc) return rc;
   if (errw & ERR_RANGE) return npg_fail(ctx, NPG_E_RANGE, "build_kdgrid: a normal is not finite");  // not reached
-  const uint32_t L = hc[1];
+  const uint32_t L = (uint32_t)emitted;
   if (L > max_leaves)
     return npg_fail(ctx, NPG_E_CAPACITY, "build_kdgrid: %u leaves exceed max_leaves %u", L, max_leaves);
   if (L) {

@@ -188,30 +188,37 @@ def unet5_model(seed: int, levels=(16, 32, 64, 128), random_bias=False) -> bytes
     return pack_model(ARCH_UNET, len(levels), ws, bs)
 
 
-def surface_normals(seed: int, pos: np.ndarray, field_res: int = 32, crease_frac: float = 0.25,
-                    jitter: float = 0.15, chunk: int = 5_000_000) -> np.ndarray:
+def surface_normals(seed: int, pos: np.ndarray, n_creases: int = 16, crease_radius: float = 0.1,
+                    freq: float = 1.5, jitter: float = 0.05, chunk: int = 5_000_000) -> np.ndarray:
     """Unit surface normals at photon hit points, float32 [n,3].
 
-    A fixed field_res^3 lattice of patches over the unit box: each patch has
-    a random normal; a crease_frac share of them is a crease, the half on
-    the far side of a random plane through the patch centre taking a second
-    random normal.  Each photon takes its patch's normal plus Gaussian jitter
+    A smooth random field, normalize(c + sum_k a_k sin(2 pi freq (w_k . p) + phi_k))
+    with four random plane waves, so that normals vary slowly over the
+    scene; plus n_creases crease discs (random centre, plane and radius
+    crease_radius) across which the normal flips sign, standing in for the
+    geometric edges where normals change abruptly; plus Gaussian jitter
     (std `jitter` per component), renormalised.
     """
     rng = rng_for(seed)
-    nf = field_res ** 3
-    n1 = unit_vectors(rng, nf)
-    n2 = unit_vectors(rng, nf)
-    crease = rng.random(nf) < crease_frac
-    plane = unit_vectors(rng, nf)
+    c = unit_vectors(rng, 1)[0]
+    a = 0.6 * rng.standard_normal((4, 3))
+    wv = unit_vectors(rng, 4)
+    ph = rng.uniform(0.0, 2.0 * np.pi, 4)
+    cc = rng.random((n_creases, 3))
+    cm = unit_vectors(rng, n_creases)
     out = np.empty((pos.shape[0], 3), np.float32)
     for s0 in range(0, pos.shape[0], chunk):
         p = pos[s0:s0 + chunk].astype(np.float64)
-        ijk = np.clip((p * field_res).astype(np.int64), 0, field_res - 1)
-        f = ijk[:, 0] + field_res * (ijk[:, 1] + field_res * ijk[:, 2])
-        centre = (ijk + 0.5) / field_res
-        far = crease[f] & (np.sum((p - centre) * plane[f], axis=1) > 0)
-        v = np.where(far[:, None], n2[f], n1[f]) + jitter * rng.standard_normal((p.shape[0], 3))
+        v = np.tile(c, (p.shape[0], 1))
+        for k in range(4):
+            v += a[k] * np.sin(2.0 * np.pi * freq * (p @ wv[k]) + ph[k])[:, None]
+        nv = np.linalg.norm(v, axis=1, keepdims=True)
+        v = np.where(nv > 1e-6, v / np.maximum(nv, 1e-300), c)
+        for j in range(n_creases):
+            d = p - cc[j]
+            far = (np.einsum("ij,ij->i", d, d) < crease_radius ** 2) & (d @ cm[j] > 0)
+            v[far] = -v[far]
+        v = v + jitter * rng.standard_normal((p.shape[0], 3))
         out[s0:s0 + chunk] = (v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
     return out
 

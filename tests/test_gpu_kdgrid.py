@@ -27,7 +27,7 @@ def _case(seed, n, res, ties=True):
     if ties:
         p[:n // 20, 0] = p[0, 0]                          # exact ties on x
         p[n // 20:n // 10, 1] = np.float32(0.5)           # ties on y at a voxel boundary
-    nrm = synth.surface_normals(seed + 1, p, field_res=8, crease_frac=0.5, jitter=0.1)
+    nrm = synth.surface_normals(seed + 1, p, n_creases=8, crease_radius=0.3, freq=3.0)
     valid = (rng.random(res ** 3) < 0.75).astype(np.uint8)
     return p, nrm, valid
 

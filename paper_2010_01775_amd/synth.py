@@ -10,9 +10,9 @@ inputs that the GPU library and the CPU oracle both consume:
 * He-normal network weights, serialised in the ``NPGW`` weight-file format.
 
 The paper's scenes, datasets and trained weights are not available; these
-draws stand in for them with the shapes the paper reports (photons per voxel
-"from several to several thousand", thousands of voxels, 2D maps of a few
-thousand bins) scaled up to the sizes of the benchmark workloads.
+draws stand in for them with the shapes the paper reports (a few to a few
+thousand photons per voxel, thousands of voxels, 2D maps of a few thousand
+bins) scaled up to the sizes of the benchmark workloads.
 
 Random numbers: numpy PCG64 seeded per workload.  vMF sampling follows the
 numerically stable inverse CDF of Wood (1994) as written by Jakob (2012,

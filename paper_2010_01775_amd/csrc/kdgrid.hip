@@ -163,22 +163,65 @@ __device__ __forceinline__ void wg_sum3_i64(long long v[3], long long (*red)[KD_
   }
 }
 
-// Split test and median selection, one workgroup per node of the level.
-// Outputs per node: sflag (1: splits), axis, the split key and the number of
-// photons below it.  tkey receives the node's photon keys on the split axis
-// (aligned with perm) for the partition.
+// Split test of one node from its photons' normals: V > split_var, with V
+// from exact integer sums (the order of the sums does not matter).
+__device__ __forceinline__ bool variance_exceeds(long long sx_, long long sy_, long long sz_, uint32_t M,
+                                                 double split_var) {
+  const double sx = (double)sx_, sy = (double)sy_, sz = (double)sz_;
+  const double num = __dadd_rn(__dadd_rn(__dmul_rn(sx, sx), __dmul_rn(sy, sy)), __dmul_rn(sz, sz));
+  const double den = __dmul_rn(__dmul_rn((double)M, (double)M), KD_QSCALE * KD_QSCALE);
+  return __dsub_rn(1.0, __ddiv_rn(num, den)) > split_var;
+}
+
+// One photon's quantised normal added to s[3]; a non-finite component counts
+// as 0 and sets *bad.
+__device__ __forceinline__ void add_qnormal(const float *__restrict__ nrm, uint32_t ph, long long s[3], bool *bad) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float v = nrm[3 * (size_t)ph + a];
+    if (!isfinite(v)) *bad = true;
+    const double c = isfinite(v) ? fmin(fmax((double)v, -1.0), 1.0) : 0.0;
+    s[a] += (long long)rint(c * KD_QSCALE);
+  }
+}
+
+// Longest axis of a node's box (ties: the lower axis).
+__device__ __forceinline__ uint32_t longest_axis(const double *b) {
+  double ext[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ext[a] = __dsub_rn(b[3 + a], b[a]);
+  uint32_t axis = 0;
+  if (ext[1] > ext[axis]) axis = 1;
+  if (ext[2] > ext[axis]) axis = 2;
+  return axis;
+}
+
+// Nodes of more than KD_WAVE_MAX photons take a whole workgroup; smaller ones
+// one wavefront each.
+constexpr uint32_t KD_WAVE_MAX = 2048;
+
+// Split test and median selection, one workgroup per node of a list (the
+// nodes above KD_WAVE_MAX photons; grid-stride over the list, whose length
+// the wavefront kernel wrote to *nbig).  Outputs per node: sflag (1: splits),
+// axis, the split key and the number of photons below it.  tkey receives the
+// node's photon keys on the split axis (aligned with perm) for the partition.
 __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__restrict__ pos,
                                                                const float *__restrict__ nrm,
                                                                const uint32_t *__restrict__ perm, Level lv,
-                                                               int depth, int max_depth, double split_count,
-                                                               double split_var, uint32_t *__restrict__ tkey,
+                                                               const uint32_t *__restrict__ big,
+                                                               const uint32_t *nbig, int depth, int max_depth,
+                                                               double split_count, double split_var,
+                                                               uint32_t *__restrict__ tkey,
                                                                uint32_t *__restrict__ sflag,
                                                                uint32_t *__restrict__ sel, uint32_t *err) {
   __shared__ long long red[3][KD_THREADS / 64];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[KD_THREADS / 64];
   __shared__ uint32_t pick[2];
-  const uint32_t j = blockIdx.x;
+  const uint32_t nb = *nbig;
+  for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+  __syncthreads();  // shared arrays of the previous node are no longer read
+  const uint32_t j = big[bi];
   const uint32_t start = lv.start[j], M = lv.count[j];
   bool split = false;
   if (depth < max_depth && M >= 2) {
@@ -186,33 +229,15 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
     if (!split && nrm) {
       long long s[3] = {0, 0, 0};
       bool bad = false;
-      for (uint32_t i = threadIdx.x; i < M; i += KD_THREADS) {
-        const uint32_t ph = perm[start + i];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const float v = nrm[3 * (size_t)ph + a];
-          if (!isfinite(v)) bad = true;
-          const double c = isfinite(v) ? fmin(fmax((double)v, -1.0), 1.0) : 0.0;
-          s[a] += (long long)rint(c * KD_QSCALE);
-        }
-      }
+      for (uint32_t i = threadIdx.x; i < M; i += KD_THREADS) add_qnormal(nrm, perm[start + i], s, &bad);
       if (bad) raise_err(err, ERR_RANGE);
       wg_sum3_i64(s, red);
-      const double sx = (double)s[0], sy = (double)s[1], sz = (double)s[2];
-      const double num = __dadd_rn(__dadd_rn(__dmul_rn(sx, sx), __dmul_rn(sy, sy)), __dmul_rn(sz, sz));
-      const double den = __dmul_rn(__dmul_rn((double)M, (double)M), KD_QSCALE * KD_QSCALE);
-      const double V = __dsub_rn(1.0, __ddiv_rn(num, den));
-      split = V > split_var;
+      split = variance_exceeds(s[0], s[1], s[2], M, split_var);
     }
   }
   uint32_t axis = 0, key = 0, less = 0;
   if (split) {
-    const double *b = lv.box + 6 * (size_t)j;
-    double ext[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) ext[a] = __dsub_rn(b[3 + a], b[a]);
-    if (ext[1] > ext[axis]) axis = 1;
-    if (ext[2] > ext[axis]) axis = 2;
+    axis = longest_axis(lv.box + 6 * (size_t)j);
     // exact selection of the (M/2)-th smallest key, 8 bits per pass
     uint32_t m = M / 2, prefix = 0, pmask = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -264,28 +289,145 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
     sel[3 * (size_t)j + 1] = key;
     sel[3 * (size_t)j + 2] = less;
   }
+  }
 }
 
-// Partition / leaf emission, one workgroup per node of the level.  A node
-// that does not split keeps its segment where it is and takes leaf slot
-// leaf_base + (number of non-splitting nodes before it); a splitting node
-// partitions its segment into tmp and copies it back in place.
-__global__ __launch_bounds__(KD_THREADS) void kd_partition_kernel(
-    uint32_t *__restrict__ perm, uint32_t *__restrict__ tmp, const uint32_t *__restrict__ tkey, Level lv, Level nx,
-    const uint32_t *__restrict__ sflag, const uint32_t *__restrict__ srank, const uint32_t *__restrict__ sel,
-    uint32_t node_base_next, npg_kd_node *__restrict__ nodes, uint32_t *__restrict__ leaf_start,
-    uint32_t *__restrict__ leaf_node, uint32_t leaf_base) {
-  __shared__ uint32_t wl[KD_THREADS / 64], wr[KD_THREADS / 64];
-  const uint32_t j = blockIdx.x;
-  const uint32_t start = lv.start[j], M = lv.count[j], id = lv.id[j];
-  if (!sflag[j]) {
-    if (threadIdx.x == 0) {
-      const uint32_t slot = leaf_base + (j - srank[j]);
-      leaf_start[slot] = start;
-      leaf_node[slot] = id;
-    }
+// Orders this wavefront's LDS accesses before and after it (the lanes of a
+// wavefront read what other lanes wrote).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same split test and selection with one wavefront per node (four nodes
+// per workgroup) for nodes of at most KD_WAVE_MAX photons; a larger node is
+// appended to the list `big` for kd_select_kernel.  Each wavefront works
+// alone (its own LDS histogram, no workgroup barrier).
+__global__ __launch_bounds__(KD_THREADS) void kd_select_wave_kernel(
+    const float *__restrict__ pos, const float *__restrict__ nrm, const uint32_t *__restrict__ perm, Level lv,
+    uint32_t active, int depth, int max_depth, double split_count, double split_var, uint32_t *__restrict__ tkey,
+    uint32_t *__restrict__ sflag, uint32_t *__restrict__ sel, uint32_t *__restrict__ big, uint32_t *nbig,
+    uint32_t *err) {
+  __shared__ uint32_t hist_all[KD_THREADS / 64][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t j = blockIdx.x * (KD_THREADS / 64) + wave;
+  if (j >= active) return;
+  const uint32_t start = lv.start[j], M = lv.count[j];
+  if (M > KD_WAVE_MAX) {
+    if (lane == 0) big[atomicAdd(nbig, 1u)] = j;
     return;
   }
+  uint32_t *hist = hist_all[wave];
+  bool split = false;
+  if (depth < max_depth && M >= 2) {
+    split = (double)M > split_count;
+    if (!split && nrm) {
+      long long s[3] = {0, 0, 0};
+      bool bad = false;
+      for (uint32_t i = lane; i < M; i += 64) add_qnormal(nrm, perm[start + i], s, &bad);
+      if (bad) raise_err(err, ERR_RANGE);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s[a] += __shfl_xor(s[a], o);
+      split = variance_exceeds(s[0], s[1], s[2], M, split_var);
+    }
+  }
+  uint32_t axis = 0, key = 0, less = 0;
+  if (split) {
+    axis = longest_axis(lv.box + 6 * (size_t)j);
+    uint32_t m = M / 2, prefix = 0, pmask = 0;
+    for (int pass = 0; pass < 4; ++pass) {
+      const int sh = 24 - 8 * pass;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hist[4 * lane + q] = 0;
+      wave_sync();
+      for (uint32_t i = lane; i < M; i += 64) {
+        uint32_t k;
+        if (pass == 0) {
+          k = okey(pos[3 * (size_t)perm[start + i] + axis]);
+          tkey[start + i] = k;
+        } else {
+          k = tkey[start + i];
+        }
+        if (((k ^ prefix) & pmask) == 0) atomicAdd(&hist[(k >> sh) & 255u], 1u);
+      }
+      wave_sync();
+      // lane l holds digits 4l..4l+3: their counts, the lane total and the
+      // exclusive prefix over lanes
+      uint32_t c[4], tot = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = hist[4 * lane + q];
+        tot += c[q];
+      }
+      uint32_t inc = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+      }
+      uint32_t exc = inc - tot, dsel = 0, bsel = 0;
+      bool hit = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!hit && exc <= m && m < exc + c[q]) {
+          hit = true;
+          dsel = 4 * lane + q;
+          bsel = exc;
+        }
+        exc += c[q];
+      }
+      const uint64_t hb = __ballot(hit);  // exactly one lane holds rank m
+      const int src = __ffsll((long long)hb) - 1;
+      const uint32_t d = __shfl(dsel, src), below = __shfl(bsel, src);
+      m -= below;
+      less += below;
+      prefix |= d << sh;
+      pmask |= 255u << sh;
+      wave_sync();
+    }
+    key = prefix;
+    split = less > 0;
+  }
+  if (lane == 0) {
+    sflag[j] = split ? 1u : 0u;
+    sel[3 * (size_t)j] = axis;
+    sel[3 * (size_t)j + 1] = key;
+    sel[3 * (size_t)j + 2] = less;
+  }
+}
+
+// After the scan of the split flags: the list of splitting nodes, and the
+// leaf record of every other node (slot leaf_base + number of non-splitting
+// nodes before it).
+__global__ __launch_bounds__(256) void kd_lists_kernel(Level lv, uint32_t active, const uint32_t *__restrict__ sflag,
+                                                       const uint32_t *__restrict__ srank,
+                                                       uint32_t *__restrict__ split_list,
+                                                       uint32_t *__restrict__ leaf_start,
+                                                       uint32_t *__restrict__ leaf_node, uint32_t leaf_base) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= active) return;
+  if (sflag[j]) {
+    split_list[srank[j]] = j;
+  } else {
+    const uint32_t slot = leaf_base + (j - srank[j]);
+    leaf_start[slot] = lv.start[j];
+    leaf_node[slot] = lv.id[j];
+  }
+}
+
+// Partition of the splitting nodes, one workgroup per node of split_list:
+// the segment is partitioned stably into tmp and copied back in place; the
+// node's record and its two children are written.
+__global__ __launch_bounds__(KD_THREADS) void kd_partition_kernel(
+    uint32_t *__restrict__ perm, uint32_t *__restrict__ tmp, const uint32_t *__restrict__ tkey, Level lv, Level nx,
+    const uint32_t *__restrict__ split_list, const uint32_t *__restrict__ srank, const uint32_t *__restrict__ sel,
+    uint32_t node_base_next, npg_kd_node *__restrict__ nodes) {
+  __shared__ uint32_t wl[KD_THREADS / 64], wr[KD_THREADS / 64];
+  const uint32_t j = split_list[blockIdx.x];
+  const uint32_t start = lv.start[j], M = lv.count[j], id = lv.id[j];
   const uint32_t axis = sel[3 * (size_t)j], key = sel[3 * (size_t)j + 1], less = sel[3 * (size_t)j + 2];
   const uint32_t c0 = node_base_next + 2 * srank[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -466,7 +608,7 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   size_t bytes = 5 * npg_align(4 * m) + npg_align(4 * (m + 1)) + sort_work;
   bytes += npg_align(4 * npg_scan_tmp_words(std::max<uint64_t>(m, cap)));
   bytes += 2 * (3 * npg_align(4 * cap) + npg_align(48 * cap));   // two levels
-  bytes += 2 * npg_align(4 * (cap + 1)) + npg_align(12 * cap);   // sflag, srank, sel
+  bytes += 2 * npg_align(4 * (cap + 1)) + npg_align(12 * cap) + npg_align(4 * cap);  // sflag, srank, sel, lists
   bytes += 4 * npg_align(4 * cap) + npg_align(16);               // leaves, sorted leaves, counters
   void *scr = nullptr;
   rc = npg_scratch(ctx, bytes, s, &scr);
@@ -487,9 +629,10 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   }
   uint32_t *sflag = cv.take<uint32_t>(cap + 1), *srank = cv.take<uint32_t>(cap + 1);
   uint32_t *sel = cv.take<uint32_t>(3 * cap);
+  uint32_t *big = cv.take<uint32_t>(cap);  // big-node list, then the split list
   uint32_t *lstart = cv.take<uint32_t>(cap), *lnode = cv.take<uint32_t>(cap);
   uint32_t *lstart_s = cv.take<uint32_t>(cap), *lnode_s = cv.take<uint32_t>(cap);
-  uint32_t *ctr = cv.take<uint32_t>(4);  // [0] photons in valid voxels
+  uint32_t *ctr = cv.take<uint32_t>(4);  // [0] photons in valid voxels, [1] big nodes of a level
 
   NPG_HIP_CHECK(ctx, hipMemsetAsync(ctr, 0, 16, s));
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, cell_root_dev, nvox, -1);
@@ -524,8 +667,13 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   uint64_t emitted = 0;
   for (int depth = 0; active > 0; ++depth) {
     Level &cur = lv[depth & 1], &nxt = lv[(depth + 1) & 1];
-    hipLaunchKernelGGL(kd_select_kernel, dim3(active), dim3(KD_THREADS), 0, s, pos_dev, normal_dev, perm_dev, cur, depth,
-                       params->max_depth, params->split_count, params->split_var, tkey, sflag, sel, ctx->err_dev);
+    NPG_HIP_CHECK(ctx, hipMemsetAsync(ctr + 1, 0, 4, s));
+    hipLaunchKernelGGL(kd_select_wave_kernel, dim3((active + 3) / 4), dim3(KD_THREADS), 0, s, pos_dev, normal_dev,
+                       perm_dev, cur, active, depth, params->max_depth, params->split_count, params->split_var, tkey,
+                       sflag, sel, big, ctr + 1, ctx->err_dev);
+    hipLaunchKernelGGL(kd_select_kernel, dim3(std::min<uint32_t>(active, 2048)), dim3(KD_THREADS), 0, s, pos_dev,
+                       normal_dev, perm_dev, cur, big, ctr + 1, depth, params->max_depth, params->split_count,
+                       params->split_var, tkey, sflag, sel, ctx->err_dev);
     NPG_HIP_CHECK(ctx, hipGetLastError());
     NPG_HIP_CHECK(ctx, npg_scan_u32(sflag, active, srank, stmp, s));
     uint32_t nsplit = 0;
@@ -537,8 +685,11 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
     emitted += active - nsplit;
     if (emitted + 2ull * nsplit > cap)
       return npg_fail(ctx, NPG_E_CAPACITY, "build_kdgrid: more than max_leaves %u leaves", max_leaves);
-    hipLaunchKernelGGL(kd_partition_kernel, dim3(active), dim3(KD_THREADS), 0, s, perm_dev, pa, tkey, cur, nxt,
-                       sflag, srank, sel, nodes_total, nodes_dev, lstart, lnode, leaf_base);
+    hipLaunchKernelGGL(kd_lists_kernel, dim3((active + 255) / 256), dim3(256), 0, s, cur, active, sflag, srank, big,
+                       lstart, lnode, leaf_base);
+    if (nsplit)
+      hipLaunchKernelGGL(kd_partition_kernel, dim3(nsplit), dim3(KD_THREADS), 0, s, perm_dev, pa, tkey, cur, nxt, big,
+                         srank, sel, nodes_total, nodes_dev);
     NPG_HIP_CHECK(ctx, hipGetLastError());
     nodes_total += 2 * nsplit;
     active = 2 * nsplit;

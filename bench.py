@@ -325,8 +325,9 @@ def main():
                          "valid-bin mask) with a masked first layer; FP32 or BF16")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(leaves are independent; sharding them over GPUs is a design, not built); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "serving":

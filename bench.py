@@ -151,6 +151,50 @@ def pdf_errors_vs_fp32(npg, ctx, model, energy, precision, maps5=None):
             "kl_median": qs(kl, 0.5), "kl_p99": qs(kl, 0.99), "kl_max": float(kl.max())}
 
 
+def sampling_chi2(npg, ctx, tabs, L, H, W, n_leaves=64, per=100_000, seed=4343):
+    """Chi-square tests of guided samples against the tables they were drawn
+    from: n_leaves leaves evenly spread over the batch, `per` samples each;
+    bins are merged in ascending expectation until each group expects >= 5.
+    Returns the spread of the per-leaf p-values and a KS test of their
+    uniformity (a correct sampler gives uniform p-values)."""
+    import torch
+    from scipy import stats
+    dev = tabs.pdf.device
+    leaves = np.unique(np.linspace(0, L - 1, min(n_leaves, L)).astype(np.int64))
+    q_leaf = torch.from_numpy(np.repeat(leaves, per).astype(np.int32)).to(dev)
+    g = torch.Generator(device=dev).manual_seed(seed)
+    u = torch.rand((q_leaf.shape[0], 2), generator=g, device=dev)
+    _, _, b = npg.sample_dirs(ctx, tabs, q_leaf, u)
+    b = b.cpu().numpy().view(np.uint32).astype(np.int64).reshape(len(leaves), per)
+    pdf = tabs.pdf[torch.from_numpy(leaves).to(dev)].double().cpu().numpy().reshape(len(leaves), -1)
+    pv = []
+    for k in range(len(leaves)):
+        pk = pdf[k] / pdf[k].sum()
+        obs = np.bincount(b[k], minlength=H * W).astype(np.float64)
+        exp = pk * per
+        order = np.argsort(exp)
+        o_m, e_m, oc, ec = [], [], 0.0, 0.0
+        for j in order:
+            if exp[j] == 0:
+                continue
+            oc += obs[j]
+            ec += exp[j]
+            if ec >= 5:
+                o_m.append(oc)
+                e_m.append(ec)
+                oc = ec = 0.0
+        if ec > 0 and o_m:
+            o_m[-1] += oc
+            e_m[-1] += ec
+        o_m, e_m = np.array(o_m), np.array(e_m)
+        chi = float(((o_m - e_m) ** 2 / e_m).sum())
+        pv.append(float(stats.chi2.sf(chi, len(o_m) - 1)))
+    pv = np.array(pv)
+    return {"leaves": int(len(leaves)), "samples_per_leaf": per, "pvalue_min": float(pv.min()),
+            "pvalue_median": float(np.median(pv)), "frac_below_0.01": float((pv < 0.01).mean()),
+            "ks_uniform_p": float(stats.kstest(pv, "uniform").pvalue)}
+
+
 def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False):
     """The FP64 oracle, as it stands, on a bounded sample of the workload."""
     from oracle import oracle as orc
@@ -158,7 +202,7 @@ def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     if workload == "uniform":
-        L = max(16, threads * 40)
+        L = max(16, threads * 120)                 # about 15 s of CPU work on 16 cores
         b = synth.uniform_batch(L=L, n_queries=L * 1024)
     else:
         raise ValueError(workload)
@@ -635,6 +679,7 @@ def main():
                      "intensity_flop_per_byte": flops / bytes_alg, "ridge_flop_per_byte": ridge,
                      "avg_launch_ms": avg["recon"], "source_sha": src_sha},
     }
+    res["sampling_chi2"] = sampling_chi2(npg, ctx, tabs, L, H, W)
     if args.precision != "fp32":
         res["precision_vs_fp32"] = pdf_errors_vs_fp32(npg, ctx, model, energy, args.precision,
                                                       (count, *prev) if prev is not None else None)

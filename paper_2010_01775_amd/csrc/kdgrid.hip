@@ -239,21 +239,46 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
   if (split) {
     axis = longest_axis(lv.box + 6 * (size_t)j);
     // exact selection of the (M/2)-th smallest key, 8 bits per pass
-    uint32_t m = M / 2, prefix = 0, pmask = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int pass = 0; pass < 4; ++pass) {
-      const int sh = 24 - 8 * pass;
+    // keys of the split axis, and their range: bits above the highest one
+    // where min and max differ are common to every key (and to the median)
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
+    for (uint32_t i = threadIdx.x; i < M; i += KD_THREADS) {
+      const uint32_t k = okey(pos[3 * (size_t)perm[start + i] + axis]);
+      tkey[start + i] = k;
+      kmin = min(kmin, k);
+      kmax = max(kmax, k);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      kmin = min(kmin, (uint32_t)__shfl_xor(kmin, o));
+      kmax = max(kmax, (uint32_t)__shfl_xor(kmax, o));
+    }
+    if (lane == 0) {
+      wsum[wave] = kmin;
+      hist[wave] = kmax;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < KD_THREADS / 64; ++w) {
+      kmin = min(kmin, wsum[w]);
+      kmax = max(kmax, hist[w]);
+    }
+    __syncthreads();
+    // exact selection of the (M/2)-th smallest key, 8 bits per pass from the
+    // highest differing bit down
+    uint32_t m = M / 2;
+    const int h = kmin == kmax ? -1 : 31 - __clz(kmin ^ kmax);
+    uint32_t pmask = h < 0 ? 0xFFFFFFFFu : (h >= 31 ? 0u : ~((2u << h) - 1u));
+    uint32_t prefix = kmin & pmask;
+    for (int hi = h; hi >= 0; hi -= 8) {
+      const int sh = hi >= 7 ? hi - 7 : 0;
+      const uint32_t dmask = (2u << (hi - sh)) - 1u;
       hist[threadIdx.x] = 0;
       __syncthreads();
       for (uint32_t i = threadIdx.x; i < M; i += KD_THREADS) {
-        uint32_t k;
-        if (pass == 0) {
-          k = okey(pos[3 * (size_t)perm[start + i] + axis]);
-          tkey[start + i] = k;
-        } else {
-          k = tkey[start + i];
-        }
-        if (((k ^ prefix) & pmask) == 0) atomicAdd(&hist[(k >> sh) & 255u], 1u);
+        const uint32_t k = tkey[start + i];
+        if (((k ^ prefix) & pmask) == 0) atomicAdd(&hist[(k >> sh) & dmask], 1u);
       }
       __syncthreads();
       // inclusive scan of the 256 digit counts (one per thread)
@@ -277,10 +302,10 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_kernel(const float *__re
       m -= below;
       less += below;
       prefix |= d << sh;
-      pmask |= 255u << sh;
+      pmask |= dmask << sh;
       __syncthreads();
     }
-    key = prefix;
+    key = prefix;  // all keys equal (h < 0): the common key, nothing below it
     split = less > 0;
   }
   if (threadIdx.x == 0) {
@@ -325,7 +350,17 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_wave_kernel(
     if (!split && nrm) {
       long long s[3] = {0, 0, 0};
       bool bad = false;
-      for (uint32_t i = lane; i < M; i += 64) add_qnormal(nrm, perm[start + i], s, &bad);
+      for (uint32_t i0 = 0; i0 < M; i0 += 4 * 64) {  // four photons in flight per lane
+        uint32_t ph[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t i = i0 + 64 * q + lane;
+          ph[q] = i < M ? perm[start + i] : KD_NONE;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (ph[q] != KD_NONE) add_qnormal(nrm, ph[q], s, &bad);
+      }
       if (bad) raise_err(err, ERR_RANGE);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -337,21 +372,51 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_wave_kernel(
   uint32_t axis = 0, key = 0, less = 0;
   if (split) {
     axis = longest_axis(lv.box + 6 * (size_t)j);
-    uint32_t m = M / 2, prefix = 0, pmask = 0;
-    for (int pass = 0; pass < 4; ++pass) {
-      const int sh = 24 - 8 * pass;
+    // keys of the split axis and their range (as in kd_select_kernel)
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
+    for (uint32_t i0 = 0; i0 < M; i0 += 4 * 64) {  // four keys in flight per lane
+      uint32_t ph[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + 64 * q + lane;
+        ph[q] = i < M ? perm[start + i] : KD_NONE;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (ph[q] == KD_NONE) continue;
+        const uint32_t k = okey(pos[3 * (size_t)ph[q] + axis]);
+        tkey[start + i0 + 64 * q + lane] = k;
+        kmin = min(kmin, k);
+        kmax = max(kmax, k);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      kmin = min(kmin, (uint32_t)__shfl_xor(kmin, o));
+      kmax = max(kmax, (uint32_t)__shfl_xor(kmax, o));
+    }
+    uint32_t m = M / 2;
+    const int h = kmin == kmax ? -1 : 31 - __clz(kmin ^ kmax);
+    uint32_t pmask = h < 0 ? 0xFFFFFFFFu : (h >= 31 ? 0u : ~((2u << h) - 1u));
+    uint32_t prefix = kmin & pmask;
+    for (int hi = h; hi >= 0; hi -= 8) {
+      const int sh = hi >= 7 ? hi - 7 : 0;
+      const uint32_t dmask = (2u << (hi - sh)) - 1u;
 #pragma unroll
       for (int q = 0; q < 4; ++q) hist[4 * lane + q] = 0;
       wave_sync();
-      for (uint32_t i = lane; i < M; i += 64) {
-        uint32_t k;
-        if (pass == 0) {
-          k = okey(pos[3 * (size_t)perm[start + i] + axis]);
-          tkey[start + i] = k;
-        } else {
-          k = tkey[start + i];
+      for (uint32_t i0 = 0; i0 < M; i0 += 4 * 64) {
+        uint32_t k[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t i = i0 + 64 * q + lane;
+          k[q] = i < M ? tkey[start + i] : 0u;
         }
-        if (((k ^ prefix) & pmask) == 0) atomicAdd(&hist[(k >> sh) & 255u], 1u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t i = i0 + 64 * q + lane;
+          if (i < M && ((k[q] ^ prefix) & pmask) == 0) atomicAdd(&hist[(k[q] >> sh) & dmask], 1u);
+        }
       }
       wave_sync();
       // lane l holds digits 4l..4l+3: their counts, the lane total and the
@@ -385,10 +450,10 @@ __global__ __launch_bounds__(KD_THREADS) void kd_select_wave_kernel(
       m -= below;
       less += below;
       prefix |= d << sh;
-      pmask |= 255u << sh;
+      pmask |= dmask << sh;
       wave_sync();
     }
-    key = prefix;
+    key = prefix;  // all keys equal (h < 0): the common key, nothing below it
     split = less > 0;
   }
   if (lane == 0) {

@@ -266,6 +266,35 @@ static int net_parse(const unsigned char *buf, size_t len, or_net *net) {
     }
     or_layer *h = &net->layer[li];
     if (h->k != 1 || h->cout != 1 || h->cin != net->layer[0].cout) { net_free(net); return OR_E_ARG; }
+  } else if (net->arch == 3) {
+    /* the paper-style U-Net: five input channels, per level two 3x3 convs
+     * (the deepest: one 3x3 conv and two dilated ones), decoder levels of two
+     * convs on [upsampled, skip], a 1x1 head */
+    int D = net->levels;
+    if (D < 2 || net->n != 4 * D) { net_free(net); return OR_E_ARG; }
+    net->in_ch = 5;
+    int prev = 5, li = 0;
+    for (int d = 0; d < D; d++) {
+      int nconv = d == D - 1 ? 3 : 2;
+      or_layer *a = &net->layer[li];
+      if (a->cin != prev || a->k != 3) { net_free(net); return OR_E_ARG; }
+      for (int j = 1; j < nconv; j++) {
+        or_layer *b = &net->layer[li + j];
+        if (b->cin != a->cout || b->cout != a->cout || b->k != 3) { net_free(net); return OR_E_ARG; }
+      }
+      prev = a->cout;
+      li += nconv;
+    }
+    for (int d = D - 2; d >= 0; d--) {
+      int cd = net->layer[2 * d].cout, cu = net->layer[d == D - 2 ? 2 * (D - 1) : 2 * (d + 1)].cout;
+      or_layer *a = &net->layer[li], *b = &net->layer[li + 1];
+      if (a->cin != cu + cd || a->cout != cd || a->k != 3 || b->cin != cd || b->cout != cd || b->k != 3) {
+        net_free(net); return OR_E_ARG;
+      }
+      li += 2;
+    }
+    or_layer *h = &net->layer[li];
+    if (h->k != 1 || h->cout != 1 || h->cin != net->layer[0].cout) { net_free(net); return OR_E_ARG; }
   } else {
     net_free(net);
     return OR_E_ARG;
@@ -318,6 +347,34 @@ static void pconv2d(const or_layer *y, const double *in, int mask_ch, int H, int
       }
 }
 
+/* 3x3 (or 1x1) convolution with dilation `dil`: taps at offsets
+ * (ky - r) * dil, (kx - r) * dil, zero padding. */
+static void conv2d_dil(const or_layer *y, const double *in, int H, int W, int dil, double *out) {
+  int k = y->k, r = k / 2;
+  for (int co = 0; co < y->cout; co++)
+    for (int yy = 0; yy < H; yy++)
+      for (int xx = 0; xx < W; xx++) {
+        double acc = y->b[co];
+        for (int ci = 0; ci < y->cin; ci++)
+          for (int ky = 0; ky < k; ky++)
+            for (int kx = 0; kx < k; kx++) {
+              int sy = yy + (ky - r) * dil, sx = xx + (kx - r) * dil;
+              if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+              acc += y->w[((co * y->cin + ci) * k + ky) * k + kx] * in[((size_t)ci * H + sy) * W + sx];
+            }
+        out[((size_t)co * H + yy) * W + xx] = acc;
+      }
+}
+
+/* ELU (Clevert et al. 2016): x for x > 0, e^x - 1 otherwise. */
+static void elu(double *a, size_t n) {
+  for (size_t i = 0; i < n; i++) a[i] = a[i] > 0.0 ? a[i] : expm1(a[i]);
+}
+
+static void add_to(double *a, const double *b, size_t n) {
+  for (size_t i = 0; i < n; i++) a[i] += b[i];
+}
+
 static void relu(double *a, size_t n) {
   for (size_t i = 0; i < n; i++) a[i] = a[i] > 0.0 ? a[i] : 0.0;
 }
@@ -346,8 +403,92 @@ static void upcat(const double *lo, int Cu, const double *skip, int Cs, int H, i
   memcpy(out + (size_t)Cu * H * W, skip, sizeof(double) * (size_t)Cs * H * W);
 }
 
+/* The paper-style U-Net (Sec. 6.1: masked first convolution on the five
+ * channels, ELU activations, residual links, a dilated bottleneck, skip
+ * connections, at most 64 channels in the paper).  Encoder level d < D-1:
+ * a = ELU(conv(x)), o = ELU(conv(a)) + a (residual), skip_d = o, next input
+ * avgpool2(o).  Deepest level: a = ELU(conv(x)), b = ELU(conv_dil2(a)) + a,
+ * o = ELU(conv_dil4(b)) + b.  Decoder level d: c = [up(o), skip_d],
+ * a = ELU(conv(c)), o = ELU(conv(a)) + a.  Head: softplus(conv1x1(o)).  The
+ * first conv is the masked (partial) convolution on the valid-bin mask. */
+static void paper_forward_leaf(const or_net *net, const double *x, int H, int W, double *s) {
+  size_t HW = (size_t)H * W;
+  int D = net->levels;
+  double **skip = calloc((size_t)D, sizeof(double *));
+  int *hs = calloc((size_t)D, sizeof(int)), *wsz = calloc((size_t)D, sizeof(int));
+  const double *cur = x;
+  double *owned = NULL;
+  int h = H, w = W, li = 0;
+  for (int d = 0; d < D; d++) {
+    const or_layer *la = &net->layer[li];
+    double *pooled = NULL;
+    if (d > 0) {
+      pooled = malloc(sizeof(double) * (size_t)la->cin * (h / 2) * (w / 2));
+      avgpool2(cur, la->cin, h, w, pooled);
+      h /= 2; w /= 2;
+      cur = pooled;
+    }
+    size_t n = (size_t)la->cout * h * w;
+    double *a = malloc(sizeof(double) * n);
+    if (d == 0)
+      pconv2d(la, cur, 4, h, w, a);
+    else
+      conv2d(la, cur, h, w, a);
+    elu(a, n);
+    free(pooled);
+    int nres = d == D - 1 ? 2 : 1;
+    for (int j = 1; j <= nres; j++) {
+      double *o = malloc(sizeof(double) * n);
+      conv2d_dil(&net->layer[li + j], a, h, w, d == D - 1 ? 2 * j : 1, o);
+      elu(o, n);
+      add_to(o, a, n);
+      free(a);
+      a = o;
+    }
+    li += 1 + nres;
+    if (d < D - 1) {
+      skip[d] = a;
+    } else {
+      owned = a;
+    }
+    hs[d] = h; wsz[d] = w;
+    cur = a;
+  }
+  for (int d = D - 2; d >= 0; d--) {
+    const or_layer *la = &net->layer[li], *lb = &net->layer[li + 1];
+    li += 2;
+    h = hs[d]; w = wsz[d];
+    int cs = net->layer[2 * d].cout, cu = la->cin - cs;
+    double *cat = malloc(sizeof(double) * (size_t)la->cin * h * w);
+    upcat(cur, cu, skip[d], cs, h, w, cat);
+    size_t n = (size_t)la->cout * h * w;
+    double *a = malloc(sizeof(double) * n);
+    conv2d(la, cat, h, w, a);
+    elu(a, n);
+    double *o = malloc(sizeof(double) * n);
+    conv2d(lb, a, h, w, o);
+    elu(o, n);
+    add_to(o, a, n);
+    free(cat); free(a);
+    free(owned);
+    owned = o;
+    cur = o;
+  }
+  double *head = malloc(sizeof(double) * HW);
+  conv2d(&net->layer[li], cur, H, W, head);
+  for (size_t k = 0; k < HW; k++) s[k] = softplus(head[k]);
+  free(head);
+  free(owned);
+  for (int d = 0; d < D - 1; d++) free(skip[d]);
+  free(skip); free(hs); free(wsz);
+}
+
 static void net_forward_leaf(const or_net *net, const double *x, int H, int W, double *s) {
   size_t HW = (size_t)H * W;
+  if (net->arch == 3) {
+    paper_forward_leaf(net, x, H, W, s);
+    return;
+  }
   if (net->arch == 1) {
     size_t cmax = 1;
     for (int i = 0; i < net->n; i++) if ((size_t)net->layer[i].cout > cmax) cmax = net->layer[i].cout;
@@ -450,7 +591,7 @@ int or_net_forward5(const unsigned char *model, size_t model_len, const double *
   int rc = net_parse(model, model_len, &net);
   if (rc) return rc;
   int D = net.levels;
-  if (net.arch != 2 || net.in_ch != 5 || (H % (1 << (D - 1))) || (W % (1 << (D - 1)))) {
+  if ((net.arch != 2 && net.arch != 3) || net.in_ch != 5 || (H % (1 << (D - 1))) || (W % (1 << (D - 1)))) {
     net_free(&net);
     return OR_E_ARG;
   }
@@ -506,6 +647,16 @@ void or_pconv2d(const float *w, const float *b, int cout, int cin, int k, const 
 
 /* Raw layer access for brute-force conv checks: one conv of a single
  * layer (weights OIHW f32, bias f32) on in[C][H][W] (FP64). */
+void or_conv2d_dil(const float *w, const float *b, int cout, int cin, int k, const double *in, int dil, int H,
+                   int W, double *out) {
+  or_layer y = {cout, cin, k, malloc(sizeof(double) * (size_t)cout * cin * k * k), malloc(sizeof(double) * cout)};
+  for (size_t i = 0; i < (size_t)cout * cin * k * k; i++) y.w[i] = (double)w[i];
+  for (int i = 0; i < cout; i++) y.b[i] = b ? (double)b[i] : 0.0;
+  conv2d_dil(&y, in, H, W, dil, out);
+  free(y.w);
+  free(y.b);
+}
+
 void or_conv2d(const float *w, const float *b, int cout, int cin, int k,
                const double *in, int H, int W, double *out) {
   or_layer y;

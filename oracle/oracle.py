@@ -44,6 +44,7 @@ def lib():
             "or_normalize_input": (None, [P, I64, I, I, P]),
             "or_net_forward": (I, [P, C.c_size_t, P, I64, I, I, P]),
             "or_conv2d": (None, [P, P, I, I, I, P, I, I, P]),
+            "or_conv2d_dil": (None, [P, P, I, I, I, P, I, I, I, P]),
             "or_net_forward5": (I, [P, C.c_size_t, P, I64, I, I, P]),
             "or_input5": (None, [P, P, P, P, I64, I, I, P]),
             "or_pconv2d": (None, [P, P, I, I, I, P, I, I, I, P]),
@@ -152,6 +153,18 @@ def conv2d(w, b, x):
     out = np.empty((co, H, W), np.float64)
     bb = None if b is None else _c(b, np.float32)
     lib().or_conv2d(_p(w), _p(bb), co, ci, k, _p(x), H, W, _p(out))
+    return out
+
+
+def conv2d_dil(w, b, x, dil):
+    """One conv layer with dilation `dil` (taps at offsets of dil pixels)."""
+    w = _c(w, np.float32)
+    co, ci, k, _ = w.shape
+    x = _c(x, np.float64)
+    _, H, W = x.shape
+    out = np.empty((co, H, W), np.float64)
+    bb = None if b is None else _c(b, np.float32)
+    lib().or_conv2d_dil(_p(w), _p(bb), co, ci, k, _p(x), int(dil), H, W, _p(out))
     return out
 
 

@@ -114,6 +114,7 @@ def two_lobe_mixture(rng: np.random.Generator, n: int, mu1, mu2,
 # --------------------------------------------------------------------------
 ARCH_CNN = 1
 ARCH_UNET = 2
+ARCH_PAPER = 3
 
 
 def cnn_layers(channels=(1, 16, 16, 1)):
@@ -132,6 +133,26 @@ def unet_layers(levels=(16, 32, 64, 128), cin: int = 1):
     prev = cin
     for c in levels:
         out += [(c, prev, 3), (c, c, 3)]
+        prev = c
+    for d in range(len(levels) - 2, -1, -1):
+        c = levels[d]
+        out += [(c, levels[d + 1] + c, 3), (c, c, 3)]
+    out.append((1, levels[0], 1))
+    return out
+
+
+def paper_unet_layers(levels=(16, 32, 64), cin: int = 5):
+    """(cout, cin, k) of the paper-style U-Net in file order.
+
+    Encoder level d (not the deepest): two 3x3 convs (in -> c_d -> c_d).
+    Deepest level: one 3x3 conv and two dilated 3x3 convs (c -> c -> c).
+    Decoder level d: two 3x3 convs (c_{d+1} + c_d -> c_d -> c_d).  Head:
+    1x1 conv c_0 -> 1.
+    """
+    out = []
+    prev = cin
+    for i, c in enumerate(levels):
+        out += [(c, prev, 3)] + [(c, c, 3)] * (2 if i == len(levels) - 1 else 1)
         prev = c
     for d in range(len(levels) - 2, -1, -1):
         c = levels[d]
@@ -186,6 +207,13 @@ def unet5_model(seed: int, levels=(16, 32, 64, 128), random_bias=False) -> bytes
     """The U-Net with the five input channels of the paper (masked first layer)."""
     ws, bs = he_weights(seed, unet_layers(levels, cin=5), random_bias)
     return pack_model(ARCH_UNET, len(levels), ws, bs)
+
+
+def paper_unet_model(seed: int, levels=(16, 32, 64), random_bias=False) -> bytes:
+    """The paper-style U-Net (five input channels, ELU, residual links,
+    dilated bottleneck), He-init stand-in weights."""
+    ws, bs = he_weights(seed, paper_unet_layers(levels), random_bias)
+    return pack_model(ARCH_PAPER, len(levels), ws, bs)
 
 
 def surface_normals(seed: int, pos: np.ndarray, n_creases: int = 16, crease_radius: float = 0.1,

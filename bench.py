@@ -195,7 +195,7 @@ def sampling_chi2(npg, ctx, tabs, L, H, W, n_leaves=64, per=100_000, seed=4343):
             "ks_uniform_p": float(stats.kstest(pv, "uniform").pvalue)}
 
 
-def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False):
+def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False, model5: bytes | None = None):
     """The FP64 oracle, as it stands, on a bounded sample of the workload."""
     from oracle import oracle as orc
     from paper_2010_01775_amd import synth
@@ -212,7 +212,7 @@ def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False
         half = (off[1:] - off[:-1]) // 2
         perm_p = np.concatenate([np.arange(off[l], off[l] + half[l]) for l in range(L)]).astype(np.uint32)
         off_p = np.concatenate([[0], np.cumsum(half)]).astype(np.uint32)
-        model5 = synth.unet5_model(1003)
+        model5 = model5 or synth.unet5_model(1003)
         rc, Ep, Pp = orc.splat(b.dirs, b.w, off_p, b.H, b.W, perm=perm_p)   # resident, not timed
     t0 = time.perf_counter()
     if input5:
@@ -225,7 +225,7 @@ def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False
     rc, d, p, bins = orc.sample(ref["pdf"], ref["marg"], ref["cond"], b.q_leaf, b.q_u)
     dt = time.perf_counter() - t0
     return {"value": L / dt, "unit": "leaves/s", "cores": min(threads, L), "kind": "oracle",
-            "sample": f"{L} leaves x 4096 photons (64x64, {'five-channel ' if input5 else ''}U-Net, FP64) "
+            "sample": f"{L} leaves x 4096 photons (64x64, {'five-channel ' if input5 else ''}network, FP64) "
                       f"end to end plus {L * 1024} samples; {dt:.1f} s"}
 
 
@@ -364,10 +364,15 @@ def main():
                     help="clustered workload: the count-threshold octree, or the paper's hierarchical grid "
                          "(100^3 voxels, valid voxels from bounce points, local KD trees split by photon count "
                          "> 500 sqrt(2) or normal variance > 0.5, depth <= 8)")
+    ap.add_argument("--paper-net", action="store_true",
+                    help="the paper-style U-Net (16/32/64 channels, ELU, residual links, dilated bottleneck) "
+                         "on the five-channel input (implies --input5)")
     ap.add_argument("--input5", action="store_true",
                     help="the five-channel network input (maps and photon counts of iterations t and t-1, "
                          "valid-bin mask) with a masked first layer; FP32 or BF16")
     args = ap.parse_args()
+    if args.paper_net:
+        args.input5 = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(leaves are independent; sharding them over GPUs is a design, not built); run with --gpus 1",
@@ -422,7 +427,7 @@ def main():
         desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, {hier_desc} "
                 f"({L} leaves), {H}x{W} maps, U-Net 16/32/64/128, 1e8 guided samples")
     if args.input5:
-        model_bytes = synth.unet5_model(1003)
+        model_bytes = synth.paper_unet_model(1006) if args.paper_net else synth.unet5_model(1003)
     model = npg.Model(ctx, model_bytes)
     experts = [model] + [npg.Model(ctx, synth.unet_model(2000 + k)) for k in range(4)] if args.experts else None
     nq = q_leaf.shape[0]
@@ -660,7 +665,9 @@ def main():
                   | ({"experts": "5 U-Nets by leaf photon count [0,100) [100,500) [500,1000) [1000,5000) "
                                  "[5000,inf)", "expert_leaves": expert_leaves} if experts else {})
                   | ({"input": "5 channels: maps and photon counts of iterations t and t-1 (t-1: first half of "
-                               "each leaf's photons), valid-bin mask; masked first layer"} if args.input5 else {}),
+                               "each leaf's photons), valid-bin mask; masked first layer"} if args.input5 else {})
+                  | ({"network": "paper-style U-Net 16/32/64, ELU, residual links, bottleneck dilations 2 and 4, "
+                                 "1x1 softplus head"} if args.paper_net else {}),
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
         "one_sample_mis": mis,
@@ -684,7 +691,8 @@ def main():
         res["precision_vs_fp32"] = pdf_errors_vs_fp32(npg, ctx, model, energy, args.precision,
                                                       (count, *prev) if prev is not None else None)
     if not args.no_cpu_baseline and args.workload == "uniform":
-        res["cpu_baseline"] = cpu_baseline(args.workload, input5=args.input5)
+        res["cpu_baseline"] = cpu_baseline(args.workload, input5=args.input5,
+                                           model5=model_bytes if args.input5 else None)
     print(json.dumps(res))
     model.free()
     ctx.close()

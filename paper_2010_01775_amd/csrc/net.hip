@@ -53,6 +53,7 @@ struct LayerDev {
   uint8_t *pk8s = nullptr;     // [chunk][tap][cout][kc16]
   float *wsc8 = nullptr;       // [cout]
   float a8 = 1.0f;             // value of one e4m3 unit of this layer's output
+  int dil = 1;                 // dilation of a 3x3 layer (the paper-style bottleneck: 2, 4)
 };
 
 struct npg_model {
@@ -198,6 +199,37 @@ static int parse_model(npg_ctx *ctx, const unsigned char *buf, size_t len, npg_m
     const LayerDev &h = m->layer[li];
     if (h.k != 1 || h.cout != 1 || h.cin != m->layer[0].cout)
       return npg_fail(ctx, NPG_E_ARG, "model: U-Net head");
+  } else if (m->arch == 3) {
+    // the paper-style U-Net: five input channels; encoder levels of two 3x3
+    // convs, the deepest of one 3x3 conv and two convs of dilation 2 and 4;
+    // decoder levels of two convs on [upsampled, skip]; a 1x1 head
+    const int D = m->levels;
+    if (D < 2 || D > 10 || n != 4 * D) return npg_fail(ctx, NPG_E_ARG, "model: paper U-Net layer count");
+    m->in_ch = 5;
+    int prev = 5, li = 0;
+    for (int d = 0; d < D; ++d) {
+      const int nconv = d == D - 1 ? 3 : 2;
+      const LayerDev &a = m->layer[li];
+      if (a.cin != prev || a.k != 3) return npg_fail(ctx, NPG_E_ARG, "model: paper U-Net encoder level %d", d);
+      for (int j = 1; j < nconv; ++j) {
+        LayerDev &b = m->layer[li + j];
+        if (b.cin != a.cout || b.cout != a.cout || b.k != 3)
+          return npg_fail(ctx, NPG_E_ARG, "model: paper U-Net encoder level %d", d);
+        if (d == D - 1) b.dil = 2 * j;
+      }
+      prev = a.cout;
+      li += nconv;
+    }
+    for (int d = D - 2; d >= 0; --d) {
+      const int cd = m->layer[2 * d].cout, cu = m->layer[2 * (d + 1)].cout;
+      const LayerDev &a = m->layer[li], &b = m->layer[li + 1];
+      if (a.cin != cu + cd || a.cout != cd || a.k != 3 || b.cin != cd || b.cout != cd || b.k != 3)
+        return npg_fail(ctx, NPG_E_ARG, "model: paper U-Net decoder level %d", d);
+      li += 2;
+    }
+    const LayerDev &h = m->layer[li];
+    if (h.k != 1 || h.cout != 1 || h.cin != m->layer[0].cout)
+      return npg_fail(ctx, NPG_E_ARG, "model: paper U-Net head");
   } else {
     return npg_fail(ctx, NPG_E_ARG, "model: unknown arch %d", m->arch);
   }
@@ -294,7 +326,19 @@ extern "C" void npg_model_free(npg_model *m) {
 namespace {
 
 enum SrcMode : int { SRC_PLAIN = 0, SRC_POOL = 1, SRC_UPCAT = 2, SRC_ENERGY = 3, SRC_FIVE = 4 };
-enum Act : int { ACT_RELU = 0, ACT_SOFTPLUS = 1 };
+enum Act : int { ACT_RELU = 0, ACT_SOFTPLUS = 1, ACT_ELU = 2 };
+
+// ReLU, or ELU (Clevert et al. 2016: x for x > 0, e^x - 1 otherwise).
+template <class A>
+__device__ __forceinline__ A act_fn(A v, int act) {
+  if (act == ACT_ELU) {
+    if constexpr (sizeof(A) == 8)
+      return v > (A)0 ? v : (A)expm1((double)v);
+    else
+      return v > (A)0 ? v : (A)expm1f((float)v);
+  }
+  return v > (A)0 ? v : (A)0;
+}
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -387,7 +431,7 @@ constexpr int F5_LDS = 774;  // (TR + 2) * (TW + 2) for TR * TW = 256, at most 3
 template <class T, class Acc, int COUT>
 __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__restrict__ w,
                                                           const float *__restrict__ b, int H, int W, int TW,
-                                                          int TR, void *out) {
+                                                          int TR, int act, void *out) {
   __shared__ float4 tile[F5_LDS];
   const int tiles_x = W / TW;
   const int tx0 = (int)(blockIdx.x % (unsigned)tiles_x) * TW, ty0 = (int)(blockIdx.x / (unsigned)tiles_x) * TR;
@@ -452,9 +496,8 @@ __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__
   T o[COUT];
 #pragma unroll
   for (int c = 0; c < COUT; ++c) {
-    Acc v = S > 0 ? (Acc)b[c] + sc * acc[c] : (Acc)0;
-    v = v > (Acc)0 ? v : (Acc)0;
-    o[c] = from_d<T>((double)v);
+    const Acc v = S > 0 ? (Acc)b[c] + sc * acc[c] : (Acc)0;
+    o[c] = from_d<T>((double)act_fn(v, act));
   }
   const size_t pix = base + (size_t)(ty0 + ly) * W + tx0 + lx;
   T *dst = static_cast<T *>(out) + pix * COUT;
@@ -501,13 +544,15 @@ __global__ __launch_bounds__(256) void leaf_totals5_kernel(const uint64_t *__res
   }
 }
 
-// Direct convolution, one thread per output pixel, binary64 sums.
-// out: T [L][H][W][Cout] (ACT_RELU) or float [L][H][W] (ACT_SOFTPLUS, Cout 1).
+// Direct convolution, one thread per output pixel, binary64 sums; taps
+// `dil` pixels apart.  out: T [L][H][W][Cout] (ACT_RELU / ACT_ELU, plus the
+// residual res of the same layout if given) or float [L][H][W]
+// (ACT_SOFTPLUS, Cout 1).
 template <class T>
 __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *__restrict__ w,
                                                           const float *__restrict__ bias, int Cin, int Cout,
                                                           int k, int H, int W, size_t npix, int act,
-                                                          float oinv, void *out) {
+                                                          float oinv, void *out, int dil, const void *res) {
   const size_t pix = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (pix >= npix) return;
   const int HW = H * W;
@@ -522,10 +567,10 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
     for (int j = 0; j < 16; ++j) acc[j] = j < nco ? (double)bias[co0 + j] : 0.0;
     for (int ci = 0; ci < Cin; ++ci)
       for (int ky = 0; ky < k; ++ky) {
-        const int sy = y + ky - r;
+        const int sy = y + (ky - r) * dil;
         if (sy < 0 || sy >= H) continue;
         for (int kx = 0; kx < k; ++kx) {
-          const int sx = x + kx - r;
+          const int sx = x + (kx - r) * dil;
           if (sx < 0 || sx >= W) continue;
           const double v = (double)src_at<T>(src, leaf, sy, sx, ci, H, W);
           const float *wp = w + ((size_t)co0 * Cin + ci) * k * k + ky * k + kx;
@@ -538,8 +583,10 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(Src src, const float *
       static_cast<float *>(out)[pix] = (float)softplus_f(acc[0]);
     } else {
       T *o = static_cast<T *>(out) + pix * Cout + co0;
+      const T *rs = res ? static_cast<const T *>(res) + pix * Cout + co0 : nullptr;
       for (int j = 0; j < nco; ++j) {
-        const double r = fmax(acc[j], 0.0);
+        double r = act_fn(acc[j], act);
+        if (rs) r = to_d<T>(from_d<T>(r)) + to_d<T>(rs[j]);  // the stored activation plus the residual
         o[j] = from_d<T>(sizeof(T) == 1 ? r * (double)oinv : r);
       }
     }
@@ -690,6 +737,9 @@ struct ConvArgs {
   const float *w0, *b0;
   float oinv0;
   int wbytes;            // LDS bytes of the weight tile (the energy tile follows it)
+  int dil = 1;           // tap spacing (dilated convolutions); the patch halo is dil pixels
+  int act = 0;           // ACT_RELU or ACT_ELU (8/16-bit and FP64 tiles without a fused head)
+  const void *res = nullptr;  // residual added after the activation, same layout as out
 };
 
 // The input channels of one K chunk (plain or upsampled + concatenated
@@ -786,6 +836,20 @@ __device__ __forceinline__ uint4 pool_combine(const uint4 &a, const uint4 &b, co
 // Staging modes: 0 plain or upsampled+concatenated input, 1 2x2-pooled
 // input, 2 the first layer (one input channel, 16 outputs, ReLU) computed
 // into the patch from the energy map, as conv_first_kernel would store it.
+// 16 bytes of stored activations plus 16 bytes of the residual, element by
+// element in binary64, rounded once to the storage type.
+template <class T>
+__device__ __forceinline__ uint4 add_res(uint4 v, uint4 r) {
+  constexpr int N = 16 / (int)sizeof(T);
+  T x[N], y[N];
+  __builtin_memcpy(x, &v, 16);
+  __builtin_memcpy(y, &r, 16);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = from_d<T>(to_d<T>(x[i]) + to_d<T>(y[i]));
+  __builtin_memcpy(&v, x, 16);
+  return v;
+}
+
 template <class P, int MW, int NW, int MODE>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
@@ -804,7 +868,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   constexpr int BNP = BN + ((16 - BN) & 63);
   constexpr int KCP = P::KCP;  // 8/16-bit B tile: [tap][n][KCP]
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2, PH = TR + 2;
+  const int DIL = a.dil, TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2 * DIL, PH = TR + 2 * DIL;
   const int H = a.H, W = a.W;
   T *patch = reinterpret_cast<T *>(smem);
   const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), 16);
@@ -845,7 +909,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     }
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
-      const int toff = (tap / 3) * PW + (tap % 3);
+      const int toff = ((tap / 3) * PW + (tap % 3)) * DIL;
       if constexpr (WGLB) {
         if (tap < 8) {
 #pragma unroll
@@ -890,7 +954,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
         // tap has zero weights; its patch reads stay inside the patch)
         const int tl = tap + (lg >> 1);
-        const int tofl = tl < 9 ? (tl / 3) * PW + (tl % 3) : 0;
+        const int tofl = tl < 9 ? ((tl / 3) * PW + (tl % 3)) * DIL : 0;
         const int cofs = (lg & 1) * 8;
         using Frag = typename P::Frag;
         Frag av[MW], bv[NW];
@@ -928,7 +992,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
       auto load_px = [&](int ch, uint4 (&v)[G]) {
         const ChunkSrc<T> cs = chunk_src<T>(a, leaf0, ch * KC);
-        const uint32_t o = tid < npx ? cs.off(ls, ty0 - 1 + py, tx0 - 1 + px, H, W) : 0x80000000u;
+        const uint32_t o = tid < npx ? cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) : 0x80000000u;
 #pragma unroll
         for (int g = 0; g < G; ++g) v[g] = g * VEC < cs.cleft ? cs.load(o + 16 * g) : make_uint4(0, 0, 0, 0);
       };
@@ -1003,7 +1067,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       for (int pp = tid; pp < np; pp += 256) {
         const int ls = pp / (PH * PW), r = pp - ls * PH * PW;
         const int py = r / PW, px = r - py * PW;
-        const int y = ty0 - 1 + py, x = tx0 - 1 + px, leaf = leaf0 + ls;
+        const int y = ty0 - DIL + py, x = tx0 - DIL + px, leaf = leaf0 + ls;
         T res[KC];  // the pixel's KC channels, written as 16-byte pieces
         if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
           const float *xp = xt + ls * EH * EW + py * EW + px;
@@ -1048,7 +1112,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           const int pp = it / G, g = it - pp * G;
           const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
           const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-          const int y = ty0 - 1 + py, x = tx0 - 1 + px, c = c0 + g * VEC;
+          const int y = ty0 - DIL + py, x = tx0 - DIL + px, c = c0 + g * VEC;
           const bool in = it < items && (uint32_t)y < (uint32_t)H && (uint32_t)x < (uint32_t)W && c < C0;
           const uint32_t o = in ? (uint32_t)(ls * plane + (2 * y * W2 + 2 * x) * C0 + c) * (uint32_t)sizeof(T)
                                 : 0x80000000u;
@@ -1080,7 +1144,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           const int pp = base + k * 256 + tid;
           const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
           const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-          const uint32_t o = pp < npx ? cs.off(ls, ty0 - 1 + py, tx0 - 1 + px, H, W) : 0x80000000u;
+          const uint32_t o = pp < npx ? cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) : 0x80000000u;
 #pragma unroll
           for (int g = 0; g < G; ++g) v[k][g] = g * VEC < cs.cleft ? cs.load(o + 16 * g) : make_uint4(0, 0, 0, 0);
         }
@@ -1236,8 +1300,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
             const AS v = acc[mi][ni][r] * ws[r] + bn[r];
             q[r] = (v > (AS)0 ? v : (AS)0) * a.oinv;
           } else {
-            const AS v = acc[mi][ni][r] + bn[r];
-            q[r] = v > (AS)0 ? v : (AS)0;
+            q[r] = act_fn(acc[mi][ni][r] + bn[r], a.act);
           }
         }
         T *o = ol + m * BN + 16 * ni + 4 * lg;  // four consecutive channels: one store
@@ -1254,9 +1317,13 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     for (int i = tid; i < BM * PPR; i += 256) {
       const int m = i / PPR, pc = i - m * PPR;
       const long g = gpix(m);
-      if (g >= 0)
-        *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) =
-            *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+      if (g >= 0) {
+        uint4 v = *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+        if (a.res)
+          v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(a.res) + g * BN +
+                                                             pc * (16 / sizeof(T))));
+        *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) = v;
+      }
     }
     return;
   }
@@ -1320,8 +1387,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           const AS v = acc[mi][ni][r] * ws + bn;
           ol[m * BN + n] = e4m3_enc_d((v > (AS)0 ? v : (AS)0) * a.oinv);
         } else {
-          const AS v = acc[mi][ni][r] + bn;
-          ol[m * BN + n] = from_d<T>((double)(v > (AS)0 ? v : (AS)0));
+          ol[m * BN + n] = from_d<T>((double)act_fn(acc[mi][ni][r] + bn, a.act));
         }
       }
   }
@@ -1331,15 +1397,20 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   for (int i = tid; i < BM * PPR; i += 256) {
     const int m = i / PPR, pc = i - m * PPR;
     const long g = gpix(m);
-    if (g >= 0)
-      *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) =
-          *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+    if (g >= 0) {
+      uint4 v = *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+      if (a.res)
+        v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(a.res) + g * BN +
+                                                           pc * (16 / sizeof(T))));
+      *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) = v;
+    }
   }
 }
 
 // Tiling of a layer: returns false if the MFMA kernel does not fit it.
 struct Tiling {
   int MW, NW, TW, TR, TL;
+  int dil = 1;  // patch halo (dilated convolutions)
 };
 
 // Bytes of the weight tile a workgroup stages in LDS.
@@ -1356,7 +1427,8 @@ template <class P>
 size_t conv_lds_bytes(const Tiling &t, bool first = false) {
   using T = typename P::T;
   const int BN = 16 * t.NW;
-  const size_t patch = npg_align((size_t)t.TL * (t.TR + 2) * (t.TW + 2) * P::PSTR * sizeof(T), 16);
+  const size_t patch =
+      npg_align((size_t)t.TL * (t.TR + 2 * t.dil) * (t.TW + 2 * t.dil) * P::PSTR * sizeof(T), 16);
   size_t wts;
   using WT = typename P::WT;
   if (P::F64) wts = P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
@@ -1371,7 +1443,7 @@ size_t conv_lds_bytes(const Tiling &t, bool first = false) {
 // Largest pixel tile (64*MW pixels) whose accumulators and LDS fit; maps
 // smaller than the tile are batched TL whole leaves per tile.
 template <class P>
-bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
+bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4, int dil = 1) {
   if (Cout % 16 || Cout > 128) return false;
   const int NW = Cout / 16;
   if (NW > P::MAX_TILES) return false;
@@ -1380,16 +1452,16 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4) {
     if (MW > mw_max) continue;
     if (MW * NW > P::MAX_TILES || (MW == 8 && NW > 2)) continue;
     const int BM = 64 * MW;
-    Tiling c{MW, NW, 0, 0, 1};
+    Tiling c{MW, NW, 0, 0, 1, dil};
     if (BM <= HW) {
       // the TR x TW shape (TW >= 8, a power of two like W and H) with the
-      // smallest halo patch (TR + 2) x (TW + 2): fewer bytes staged per pixel
+      // smallest halo patch (TR + 2 dil) x (TW + 2 dil): fewer bytes staged per pixel
       c.TW = std::min(W, BM);
       c.TR = BM / c.TW;
       for (int tw = c.TW / 2; tw >= 8; tw /= 2) {
         const int tr = BM / tw;
         if (tr > H) break;
-        if ((tr + 2) * (tw + 2) < (c.TR + 2) * (c.TW + 2)) {
+        if ((tr + 2 * dil) * (tw + 2 * dil) < (c.TR + 2 * dil) * (c.TW + 2 * dil)) {
           c.TW = tw;
           c.TR = tr;
         }
@@ -1487,13 +1559,13 @@ struct Runner {
   // 16-lane group, 4*MW <= 16)
   bool tiling(const LayerDev &y, int H, int W, Tiling *t, int mw_lim = 8) const {
     const int c = std::min(cap(), mw_lim);
-    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t, c);
+    if (prec == NPG_FP32) return pick_tiling<F32P>(y.cout, H, W, t, c, y.dil);
     if (prec == NPG_FP8) {
-      if (y.cin % KC8 == 0) return pick_tiling<FP8P>(y.cout, H, W, t, c);
-      return pick_tiling<FP8S>(y.cout, H, W, t, c);
+      if (y.cin % KC8 == 0) return pick_tiling<FP8P>(y.cout, H, W, t, c, y.dil);
+      return pick_tiling<FP8S>(y.cout, H, W, t, c, y.dil);
     }
-    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t, c);
-    return pick_tiling<BF16S>(y.cout, H, W, t, c);
+    if (y.cin % KC16 == 0) return pick_tiling<BF16P>(y.cout, H, W, t, c, y.dil);
+    return pick_tiling<BF16S>(y.cout, H, W, t, c, y.dil);
   }
   // channel granularity of the tiled kernel's 16-byte input loads
   int vec() const { return prec == NPG_FP32 ? 2 : prec == NPG_FP8 ? 16 : 8; }
@@ -1578,12 +1650,14 @@ struct Runner {
     return NPG_OK;
   }
 
+  // res: a tensor of the output's layout added after the activation (a
+  // residual link), or null
   int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
-           int act) {
+           int act, const void *res = nullptr) {
     if (ev) {
       if (hipEventRecord((*ev)[2 * call], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
     }
-    int rc = conv_impl(y, src, Lc, H, W, out, head, act);
+    int rc = conv_impl(y, src, Lc, H, W, out, head, act, res);
     if (ev && !rc) {
       if (hipEventRecord((*ev)[2 * call + 1], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
     }
@@ -1601,11 +1675,14 @@ struct Runner {
     return rc;
   }
 
-  // One 3x3 conv (+ReLU) or the last layer (+head / softplus).
+  // One 3x3 conv (+ReLU / ELU, + residual) or the last layer (+head / softplus).
   int conv_impl(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
-                int act) {
+                int act, const void *res) {
+    if ((act == ACT_ELU || res || y.dil != 1) && (prec == NPG_FP8 || head))
+      return npg_fail(ctx, NPG_E_ARG, "internal: ELU, residual and dilated layers run in FP32 or BF16, unfused");
     Tiling t;
-    const bool mfma_ok = act == ACT_RELU && mfma_fits(y, src, H, W, &t, head ? 4 : 8) && (!head || y.cout == 16);
+    const bool mfma_ok = (act == ACT_RELU || act == ACT_ELU) && mfma_fits(y, src, H, W, &t, head ? 4 : 8) &&
+                         (!head || y.cout == 16);
     if (mfma_ok) {
       ConvArgs a;
       a.src = src;
@@ -1617,8 +1694,11 @@ struct Runner {
       a.TR = t.TR;
       a.TL = t.TL;
       a.Lc = Lc;
-      a.fPW = make_fastdiv((uint32_t)(t.TW + 2));
-      a.fPP = make_fastdiv((uint32_t)((t.TW + 2) * (t.TR + 2)));
+      a.dil = y.dil;
+      a.act = act;
+      a.res = res;
+      a.fPW = make_fastdiv((uint32_t)(t.TW + 2 * y.dil));
+      a.fPP = make_fastdiv((uint32_t)((t.TW + 2 * y.dil) * (t.TR + 2 * y.dil)));
       a.fTW = make_fastdiv((uint32_t)t.TW);
       a.fTPX = make_fastdiv((uint32_t)(t.TW * t.TR));
       a.tiles_x = W / t.TW;
@@ -1657,7 +1737,7 @@ struct Runner {
       return NPG_OK;
     }
     if (src.mode == SRC_FIVE) {
-      if (y.k != 3 || y.cin != 5 || act != ACT_RELU || head || prec == NPG_FP8)
+      if (y.k != 3 || y.cin != 5 || (act != ACT_RELU && act != ACT_ELU) || head || res || prec == NPG_FP8)
         return npg_fail(ctx, NPG_E_ARG, "internal: five-channel first layer");
       // tile of TR x TW pixels per workgroup (H, W powers of two, 4..1024)
       const int TW = std::min(W, 256), TR = std::min(H, 256 / TW);
@@ -1669,7 +1749,7 @@ struct Runner {
         using AA = decltype(tag_acc);
         constexpr int C = decltype(tag_c)::value;
         hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C>), grid, dim3(256), 0, s, src, y.w, y.b, H, W, TW, TR,
-                           out);
+                           act, out);
       };
       auto by_c = [&](auto tag_t, auto tag_acc) {
         switch (y.cout) {
@@ -1687,7 +1767,7 @@ struct Runner {
       return NPG_OK;
     }
     if (!force_direct && src.mode == SRC_ENERGY && y.k == 3 && y.cin == 1 && y.cout <= 16 && act == ACT_RELU &&
-        H * W >= 256 && !head) {
+        H * W >= 256 && !head && !res) {
       const int TW = std::min(W, 256), TR = 256 / TW;
       if (TR <= H) {
         const unsigned blocks = (unsigned)Lc * (H / TR) * (W / TW);
@@ -1719,13 +1799,13 @@ struct Runner {
     const unsigned blocks = (unsigned)((npix + 255) / 256);
     if (prec == NPG_FP32)
       hipLaunchKernelGGL(conv_direct_kernel<double>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
-                         y.cout, y.k, H, W, npix, act, 1.0f, dst);
+                         y.cout, y.k, H, W, npix, act, 1.0f, dst, y.dil, res);
     else if (prec == NPG_FP8)
       hipLaunchKernelGGL(conv_direct_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,
-                         y.cout, y.k, H, W, npix, act, 1.0f / y.a8, dst);
+                         y.cout, y.k, H, W, npix, act, 1.0f / y.a8, dst, 1, nullptr);
     else
       hipLaunchKernelGGL(conv_direct_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b,
-                         y.cin, y.cout, y.k, H, W, npix, act, 1.0f, dst);
+                         y.cin, y.cout, y.k, H, W, npix, act, 1.0f, dst, y.dil, res);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "direct conv launch: %s", hipGetErrorString(e));
     return NPG_OK;
@@ -1787,6 +1867,63 @@ NetBufs carve_net(Carver &cv, const NetPlan &p, size_t chunk, size_t esz) {
   return B;
 }
 
+// The paper-style U-Net on one chunk (FP32 or BF16 activations): ELU after
+// every 3x3 conv, residual links around the second conv of each level and
+// around both dilated convs of the bottleneck, the 1x1 softplus head.
+// Buffers: level outputs of the encoder in the skip buffers, everything
+// else alternates between tA and tB (a conv never writes its own input or
+// residual).
+int paper_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const NetBufs &B) {
+  const npg_model *m = R.m;
+  const int D = m->levels;
+  int h = H, w = W, li = 0, rc;
+  const void *prev = nullptr;
+  int prevC = 0;
+  for (int d = 0; d < D; ++d) {  // encoder
+    const LayerDev &la = m->layer[li];
+    Src sa = in;
+    if (d > 0) {
+      h /= 2;
+      w /= 2;
+      sa = pooled(prev, prevC, 1.0f);
+    }
+    rc = R.conv(la, sa, Lc, h, w, B.tA, nullptr, ACT_ELU);
+    if (rc) return rc;
+    if (d < D - 1) {
+      const LayerDev &lb = m->layer[li + 1];
+      rc = R.conv(lb, plain(B.tA, la.cout, 1.0f), Lc, h, w, B.skip[d], nullptr, ACT_ELU, B.tA);
+      if (rc) return rc;
+      prev = B.skip[d];
+      li += 2;
+    } else {  // bottleneck: dilations 2 and 4, each with its residual link
+      const LayerDev &l2 = m->layer[li + 1], &l4 = m->layer[li + 2];
+      rc = R.conv(l2, plain(B.tA, la.cout, 1.0f), Lc, h, w, B.tB, nullptr, ACT_ELU, B.tA);
+      if (rc) return rc;
+      rc = R.conv(l4, plain(B.tB, la.cout, 1.0f), Lc, h, w, B.tA, nullptr, ACT_ELU, B.tB);
+      if (rc) return rc;
+      prev = B.tA;
+      li += 3;
+    }
+    prevC = la.cout;
+  }
+  for (int d = D - 2; d >= 0; --d) {  // decoder
+    const LayerDev &la = m->layer[li], &lb = m->layer[li + 1];
+    li += 2;
+    h *= 2;
+    w *= 2;
+    const int cs = m->layer[2 * d].cout;
+    char *ta = prev == B.tA ? B.tB : B.tA;
+    char *tb = ta == B.tA ? B.tB : B.tA;  // held the level below, read by the first conv only
+    rc = R.conv(la, upcat(prev, prevC, B.skip[d], cs, 1.0f, 1.0f), Lc, h, w, ta, nullptr, ACT_ELU);
+    if (rc) return rc;
+    rc = R.conv(lb, plain(ta, la.cout, 1.0f), Lc, h, w, tb, nullptr, ACT_ELU, ta);
+    if (rc) return rc;
+    prev = tb;
+    prevC = lb.cout;
+  }
+  return R.conv(m->layer[li], plain(prev, prevC, 1.0f), Lc, H, W, dens, nullptr, ACT_SOFTPLUS);
+}
+
 // The network on one chunk of Lc leaves: `in` is the energy source (with
 // per-leaf totals), `dens` receives the softplus densities.
 int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const NetBufs &B) {
@@ -1817,6 +1954,7 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
     }
     return NPG_OK;
   }
+  if (m->arch == 3) return paper_chunk(R, in, Lc, H, W, dens, B);
   const int D = m->levels;
   int h = H, w = W;
   const void *prev = nullptr;
@@ -1896,7 +2034,7 @@ int check_net_args(npg_ctx *ctx, const npg_model *m, int H, int W, npg_precision
     return npg_fail(ctx, NPG_E_ARG, "reconstruct: bad precision %d", (int)precision);
   if (precision == NPG_FP8 && !m->fp8_ready)
     return npg_fail(ctx, NPG_E_ARG, "reconstruct: FP8 needs npg_model_calibrate_fp8 first");
-  if (m->arch == 2) {
+  if (m->arch == 2 || m->arch == 3) {
     const int f = 1 << (m->levels - 1);
     if (H % f || W % f) return npg_fail(ctx, NPG_E_ARG, "reconstruct: %dx%d not divisible by 2^%d", H, W, m->levels - 1);
   }
@@ -2134,7 +2272,7 @@ bool npg_model_fp8_ready(const npg_model *m) { return m && m->fp8_ready; }
 int npg_model_in_channels(const npg_model *m) { return m ? m->in_ch : 0; }
 
 bool npg_model_fits(const npg_model *m, int H, int W) {
-  if (m->arch != 2) return true;
+  if (m->arch != 2 && m->arch != 3) return true;
   const int f = 1 << (m->levels - 1);
   return H % f == 0 && W % f == 0;
 }

@@ -850,7 +850,9 @@ __device__ __forceinline__ uint4 add_res(uint4 v, uint4 r) {
   return v;
 }
 
-template <class P, int MW, int NW, int MODE>
+// X: the extended form (dilation, ELU, residual link); without it the
+// layer is a plain 3x3 conv + ReLU and none of that code is compiled in.
+template <class P, int MW, int NW, int MODE, bool X = false>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using T = typename P::T;
   using AccV = typename P::Acc;
@@ -868,7 +870,9 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   constexpr int BNP = BN + ((16 - BN) & 63);
   constexpr int KCP = P::KCP;  // 8/16-bit B tile: [tap][n][KCP]
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int DIL = a.dil, TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2 * DIL, PH = TR + 2 * DIL;
+  const int DIL = X ? a.dil : 1, TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2 * DIL, PH = TR + 2 * DIL;
+  const int ACT = X ? a.act : ACT_RELU;
+  const void *const RES = X ? a.res : nullptr;
   const int H = a.H, W = a.W;
   T *patch = reinterpret_cast<T *>(smem);
   const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), 16);
@@ -1300,7 +1304,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
             const AS v = acc[mi][ni][r] * ws[r] + bn[r];
             q[r] = (v > (AS)0 ? v : (AS)0) * a.oinv;
           } else {
-            q[r] = act_fn(acc[mi][ni][r] + bn[r], a.act);
+            q[r] = act_fn(acc[mi][ni][r] + bn[r], ACT);
           }
         }
         T *o = ol + m * BN + 16 * ni + 4 * lg;  // four consecutive channels: one store
@@ -1319,8 +1323,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       const long g = gpix(m);
       if (g >= 0) {
         uint4 v = *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
-        if (a.res)
-          v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(a.res) + g * BN +
+        if (RES)
+          v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(RES) + g * BN +
                                                              pc * (16 / sizeof(T))));
         *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) = v;
       }
@@ -1387,7 +1391,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           const AS v = acc[mi][ni][r] * ws + bn;
           ol[m * BN + n] = e4m3_enc_d((v > (AS)0 ? v : (AS)0) * a.oinv);
         } else {
-          ol[m * BN + n] = from_d<T>((double)act_fn(acc[mi][ni][r] + bn, a.act));
+          ol[m * BN + n] = from_d<T>((double)act_fn(acc[mi][ni][r] + bn, ACT));
         }
       }
   }
@@ -1399,8 +1403,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     const long g = gpix(m);
     if (g >= 0) {
       uint4 v = *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
-      if (a.res)
-        v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(a.res) + g * BN +
+      if (RES)
+        v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(RES) + g * BN +
                                                            pc * (16 / sizeof(T))));
       *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) = v;
     }
@@ -1480,17 +1484,28 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4, int dil = 1)
   return false;
 }
 
-template <class P, int MW, int NW, int MODE>
-hipError_t launch_mfma_k(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
+template <class P, int MW, int NW, int MODE, bool X>
+hipError_t launch_mfma_kx(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW, MODE>,
+    hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW, MODE, X>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW, MODE>), dim3(tiles), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW, MODE, X>), dim3(tiles), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+template <class P, int MW, int NW, int MODE>
+hipError_t launch_mfma_k(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
+  // the extended form only for the layers that need it (8/16-bit and FP64
+  // tiles on plain, concatenated or pooled inputs; never FP8)
+  if (a.dil != 1 || a.act != ACT_RELU || a.res) {
+    if constexpr (MODE != 2 && !P::Q8) return launch_mfma_kx<P, MW, NW, MODE, true>(a, lds, tiles, s);
+    return hipErrorInvalidValue;
+  }
+  return launch_mfma_kx<P, MW, NW, MODE, false>(a, lds, tiles, s);
 }
 
 template <class P, int MW, int NW>

@@ -129,7 +129,13 @@ int npg_set_option(npg_ctx *ctx, const char *name, int64_t value);
  * conv + ReLU on [nearest x2 upsample of level d+1, skip of level d];
  * head = 1x1 conv to one channel + softplus (the compact U-Net of Sec. 6.1,
  * whose published figure and weights are not available, so the file's
- * weights are stand-ins).  Zero padding.  The host buffer is not retained.
+ * weights are stand-ins).  arch 3 = the paper-style U-Net of Sec. 6.1 on the
+ * five input channels: ELU after every 3x3 conv; encoder level d: a =
+ * ELU(conv(x)), o = ELU(conv(a)) + a (the first conv being the masked
+ * five-channel layer); the deepest level: a = ELU(conv(x)), b =
+ * ELU(conv_dilation2(a)) + a, o = ELU(conv_dilation4(b)) + b; decoder level
+ * d: a = ELU(conv([up(o), skip_d])), o = ELU(conv(a)) + a; head as arch 2;
+ * 4 * levels layers.  Zero padding.  The host buffer is not retained.
  * Weights are repacked on the device for FP32 and BF16; FP8 needs
  * npg_model_calibrate_fp8 first.  NPG_E_ARG for a malformed file. */
 int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_bytes, npg_model **out);
@@ -307,9 +313,10 @@ int npg_reconstruct_density(npg_ctx *ctx, const npg_model *model, const uint64_t
  * float32), and the mask B of bins holding photons at t; the first layer is
  * a masked (partial) convolution: only taps with B = 1 contribute, the sum
  * is rescaled by 9/S for the S valid in-map taps (0 where S = 0), then bias
- * and ReLU; the rest is the U-Net of npg_reconstruct_density.  The model is
- * a U-Net whose first layer has 5 input channels (other entry points reject
- * such models and this one rejects the others).
+ * and the activation; the rest is the U-Net of npg_reconstruct_density
+ * (arch 2 with a 5-channel first layer, ReLU) or the paper-style U-Net
+ * (arch 3, ELU).  Other entry points reject five-channel models and this
+ * one rejects the others.
  *   energy_dev, energy_prev_dev [L][H][W] uint64;  count_dev, count_prev_dev
  *   [L][H][W] uint32 (as written by npg_splat_histograms for iterations t
  *   and t-1);  density_dev [L][H][W] float32 out

@@ -428,10 +428,10 @@ __device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, i
 // out T [L][H][W][COUT].
 constexpr int F5_LDS = 774;  // (TR + 2) * (TW + 2) for TR * TW = 256, at most 3 * 258
 
-template <class T, class Acc, int COUT>
+template <class T, class Acc, int COUT, int ACT>
 __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__restrict__ w,
                                                           const float *__restrict__ b, int H, int W, int TW,
-                                                          int TR, int act, void *out) {
+                                                          int TR, void *out) {
   __shared__ float4 tile[F5_LDS];
   const int tiles_x = W / TW;
   const int tx0 = (int)(blockIdx.x % (unsigned)tiles_x) * TW, ty0 = (int)(blockIdx.x / (unsigned)tiles_x) * TR;
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__
 #pragma unroll
   for (int c = 0; c < COUT; ++c) {
     const Acc v = S > 0 ? (Acc)b[c] + sc * acc[c] : (Acc)0;
-    o[c] = from_d<T>((double)act_fn(v, act));
+    o[c] = from_d<T>((double)act_fn(v, ACT));
   }
   const size_t pix = base + (size_t)(ty0 + ly) * W + tx0 + lx;
   T *dst = static_cast<T *>(out) + pix * COUT;
@@ -1763,8 +1763,12 @@ struct Runner {
         using TT = decltype(tag_t);
         using AA = decltype(tag_acc);
         constexpr int C = decltype(tag_c)::value;
-        hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C>), grid, dim3(256), 0, s, src, y.w, y.b, H, W, TW, TR,
-                           act, out);
+        if (act == ACT_ELU)
+          hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C, ACT_ELU>), grid, dim3(256), 0, s, src, y.w, y.b, H, W,
+                             TW, TR, out);
+        else
+          hipLaunchKernelGGL((conv_first5_kernel<TT, AA, C, ACT_RELU>), grid, dim3(256), 0, s, src, y.w, y.b, H,
+                             W, TW, TR, out);
       };
       auto by_c = [&](auto tag_t, auto tag_acc) {
         switch (y.cout) {

@@ -39,9 +39,7 @@ PEAK = {  # MI355X published dense peaks
 }
 
 
-def model_flops_per_leaf(model: bytes, H: int, W: int) -> float:
-    """Algorithmic FLOPs of one leaf: 2*Cin*Cout*k*k per output pixel and
-    layer, at each layer's resolution (pool/upsample/ReLU not counted)."""
+def _model_shapes(model: bytes):
     arch, levels, n = struct.unpack_from("<III", model, 8)
     off = 20
     shapes = []
@@ -49,7 +47,39 @@ def model_flops_per_leaf(model: bytes, H: int, W: int) -> float:
         co, ci, k = struct.unpack_from("<III", model, off)
         shapes.append((co, ci, k))
         off += 12 + 4 * (co * ci * k * k + co)
+    return arch, levels, shapes
+
+
+def _paper_schedule(shapes, D: int, px: int):
+    """The paper-style U-Net's convs in execution order: (cout, cin, k,
+    output pixels, kind) with kind 'first', 'pool' (2x2-pooled input),
+    'res' (residual link), 'cat' (upsampled + skip input) or 'head'."""
+    out, li = [], 0
+    for d in range(D):
+        p = px >> (2 * d)
+        for j in range(3 if d == D - 1 else 2):
+            co, ci, k = shapes[li + j]
+            out.append((co, ci, k, p, "res" if j else ("first" if d == 0 else "pool")))
+        li += 3 if d == D - 1 else 2
+    for d in range(D - 2, -1, -1):
+        p = px >> (2 * d)
+        for j in range(2):
+            co, ci, k = shapes[li + j]
+            out.append((co, ci, k, p, "res" if j else "cat"))
+        li += 2
+    co, ci, k = shapes[li]
+    out.append((co, ci, k, px, "head"))
+    return out
+
+
+def model_flops_per_leaf(model: bytes, H: int, W: int) -> float:
+    """Algorithmic FLOPs of one leaf: 2*Cin*Cout*k*k per output pixel and
+    layer, at each layer's resolution (pool/upsample/activations and
+    residual adds not counted)."""
+    arch, levels, shapes = _model_shapes(model)
     px = H * W
+    if arch == 3:
+        return float(sum(2 * ci * co * k * k * p for co, ci, k, p, _ in _paper_schedule(shapes, levels, px)))
     if arch == 1:
         return float(sum(2 * ci * co * k * k * px for co, ci, k in shapes))
     D = levels
@@ -74,15 +104,33 @@ def model_bytes_per_leaf(model: bytes, H: int, W: int, esz: int, in_bytes: float
     input once (in_bytes per pixel for the first layer: the u64 energy map,
     or u64 + u32 maps of two iterations for the five-channel input; pooled
     and concatenated inputs at their stored resolution) and writes its output
-    once (esz bytes per activation, float32 densities for the last layer)."""
-    arch, levels, n = struct.unpack_from("<III", model, 8)
-    off = 20
-    shapes = []
-    for _ in range(n):
-        co, ci, k = struct.unpack_from("<III", model, off)
-        shapes.append((co, ci, k))
-        off += 12 + 4 * (co * ci * k * k + co)
+    once (esz bytes per activation, float32 densities for the last layer);
+    a residual link reads its tensor once more."""
+    arch, levels, shapes = _model_shapes(model)
+    n = len(shapes)
     px = H * W
+    if arch == 3:
+        b, prev = 0.0, None                        # prev: (channels, pixels) of the last output
+        skips = {}
+        sched = _paper_schedule(shapes, levels, px)
+        for i, (co, ci, k, p, kind) in enumerate(sched):
+            if kind == "first":
+                b += in_bytes * p
+            elif kind == "pool":
+                b += prev[0] * prev[1] * esz       # the pooled input read at full size
+            elif kind == "res":
+                b += 2 * prev[0] * prev[1] * esz   # input and residual
+            elif kind == "cat":
+                b += prev[0] * prev[1] * esz + skips[p] * p * esz
+            else:                                  # head
+                b += prev[0] * prev[1] * esz + 4 * p
+                break
+            b += co * p * esz
+            prev = (co, p)
+            nxt = sched[i + 1][4] if i + 1 < len(sched) else None
+            if kind == "res" and nxt == "pool":
+                skips[p] = co                      # an encoder level's output is its skip
+        return b
     if arch == 1:
         b = in_bytes * px
         for i, (co, ci, k) in enumerate(shapes):

@@ -1,7 +1,7 @@
 """GPU tests of the paper-style U-Net (five-channel masked first layer, ELU,
 residual links, dilated bottleneck) through npg_reconstruct_density5:
 FP32 densities within 1e-5 of the FP64 oracle on the tiled path and on the
-direct path, at square maps and at the paper's 32x64 shape (bins that
+direct path, at square maps and at the paper's 32x64 and 64x128 shapes (bins that
 underflow float32 compared in absolute terms); BF16 error
 stated; results independent of chunking and of autotuned tiles; FP8
 rejected."""
@@ -40,7 +40,8 @@ def _dev(e_t, p_t, e_p, p_p):
 
 
 @pytest.mark.parametrize("H,W,levels,direct", [(32, 32, (16, 32, 64), False), (32, 64, (16, 32, 64), False),
-                                              (16, 16, (8, 16), False), (32, 64, (16, 32, 64), True)])
+                                              (64, 128, (16, 32, 64), False), (16, 16, (8, 16), False),
+                                              (32, 64, (16, 32, 64), True)])
 def test_paper_net_fp32_parity(ctx, npg, orc, H, W, levels, direct):
     counts = [3000, 40, 0, 1500, 7, 2200]
     maps = _maps(orc, 100 + H + W, counts, H, W)

@@ -8,13 +8,16 @@
 //      key), stable radix sort of (voxel, photon index): the photons of a
 //      voxel become one contiguous segment, in ascending photon index;
 //   2. segment starts = the roots, in ascending voxel id;
-//   3. per level, one workgroup per node: the split test (count, and the
-//      normal variance from exact integer sums), the median coordinate on
-//      the longest axis by an exact 4 x 8-bit radix select over the
-//      segment, then a stable partition of the segment into the two child
-//      segments (child slots from a scan of the split flags, so node ids do
-//      not depend on scheduling); a node that does not split copies its
-//      segment to the output permutation as a leaf;
+//   3. per level: the split test of each node (count, and the normal
+//      variance from exact integer sums) and, for a splitting node, the
+//      median coordinate on the longest axis by an exact radix select over
+//      its segment (8 bits per pass from the highest bit where the node's
+//      keys differ), one wavefront per node of up to 2048 photons and one
+//      workgroup per larger node; then a stable partition of each
+//      splitting node's segment into its two child segments, in place
+//      (child slots from a scan of the split flags, so node ids do not
+//      depend on scheduling); a node that does not split keeps its segment
+//      where it is and becomes a leaf;
 //   4. leaves sorted by segment start: depth-first order inside a voxel,
 //      voxels ascending, since every split keeps its children inside the
 //      parent's segment, first child first.
@@ -763,7 +766,8 @@ extern "C" int npg_build_kdgrid(npg_ctx *ctx, const npg_kdgrid_params *params, c
   NPG_HIP_CHECK(ctx, hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, s));
   rc = take_err(ctx, s, &errw);
   if (rc) return rc;
-  if (errw & ERR_RANGE) return npg_fail(ctx, NPG_E_RANGE, "build_kdgrid: a normal is not finite");  // not reached
+  // the key pass has checked every position and every normal it needed
+  if (errw & ERR_RANGE) return npg_fail(ctx, NPG_E_RANGE, "build_kdgrid: a normal is not finite");
   const uint32_t L = (uint32_t)emitted;
   if (L > max_leaves)
     return npg_fail(ctx, NPG_E_CAPACITY, "build_kdgrid: %u leaves exceed max_leaves %u", L, max_leaves);

@@ -20,9 +20,15 @@
 // (encoder) and the nearest upsample + skip concatenation (decoder) are
 // folded into the patch loads; bias and ReLU into the epilogue; the 1x1 head
 // and softplus into the epilogue of the last decoder convolution.  The first
-// layer (one input channel) and any layer the tiling does not fit run as a
-// direct convolution; the first layer computes the normalised input map
-// from the energy map on the fly.
+// layer (one input channel) is computed into the second layer's patch, or
+// runs as a direct convolution like any layer the tiling does not fit; it
+// computes the normalised input map from the energy map on the fly.  FP8
+// mode: e4m3 activations and weights with static per-layer scales.
+// Five-channel models (maps and photon counts of two iterations and the
+// valid-bin mask) start with a masked (partial) convolution kernel; the
+// paper-style U-Net adds ELU, residual links and dilated convolutions, which
+// the tiles take in an extended form (a wider halo, the activation and the
+// residual add in the epilogue) compiled only for the layers that use it.
 #include <math.h>
 #include <string.h>
 

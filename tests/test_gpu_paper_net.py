@@ -117,3 +117,39 @@ def test_paper_net_rejections(ctx, npg):
         assert ex.value.code == npg.E_ARG
     assert npg.sync_status(ctx) == 0
     m.free()
+
+
+@pytest.mark.parametrize("paper", [False, True])
+def test_five_channel_full_size_sampled(ctx, npg, orc, paper):
+    """The uniform-batch workload (1024 leaves x 4096 photons, 64x64) in the
+    launch configuration bench.py times (autotuned tiles, default chunking):
+    iteration t-1 = the first half of each leaf's photons; the maps of both
+    iterations bit-exact on every leaf, the densities of sampled leaves
+    against the oracle run on those leaves alone."""
+    b = synth.uniform_batch()
+    L, H, W = b.L, b.H, b.W
+    off = b.leaf_off.astype(np.int64)
+    half = (off[1:] - off[:-1]) // 2
+    perm_p = np.concatenate([np.arange(off[l], off[l] + half[l]) for l in range(L)]).astype(np.uint32)
+    off_p = np.concatenate([[0], np.cumsum(half)]).astype(np.uint32)
+    tf = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+    t32 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(DEV)
+    e_t, p_t = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), H, W)
+    e_p, p_p = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(off_p), H, W, perm=t32(perm_p))
+    rc, e_ref, c_ref = orc.splat(b.dirs, b.w, b.leaf_off, H, W)
+    rc2, ep_ref, cp_ref = orc.splat(b.dirs, b.w, off_p, H, W, perm=perm_p)
+    assert rc == 0 and rc2 == 0
+    assert np.array_equal(e_t.cpu().numpy().view(np.uint64), e_ref)
+    assert np.array_equal(p_t.cpu().numpy().view(np.uint32), c_ref)
+    assert np.array_equal(e_p.cpu().numpy().view(np.uint64), ep_ref)
+    assert np.array_equal(p_p.cpu().numpy().view(np.uint32), cp_ref)
+    model = synth.paper_unet_model(1006) if paper else synth.unet5_model(1003)
+    m = npg.Model(ctx, model)
+    npg.autotune(ctx, m, H, W, "fp32", probe_leaves=1024)
+    s = npg.reconstruct_density5(ctx, m, e_t, p_t, e_p, p_p, "fp32").cpu().numpy()
+    assert npg.sync_status(ctx) == 0
+    pick = np.array([0, 1, 200, 511, 512, 777, 900, 1023])
+    rc, s_ref = orc.net_forward5(model, orc.input5(e_ref[pick], ep_ref[pick], c_ref[pick], cp_ref[pick]))
+    assert rc == 0
+    _check_fp32(s[pick], s_ref)
+    m.free()

@@ -10,26 +10,38 @@
 namespace {
 
 // largest i in [0, n-1] with t[i] <= u, for t non-decreasing with
-// t[0] <= u < t[n].  The search starts at the entry a linear table would
-// hold u at, gallops outwards until u is bracketed and bisects the bracket:
-// for smooth tables the first probe and its neighbour share a cache line.
-__device__ __forceinline__ int last_le(const float *__restrict__ t, int n, float u) {
+// t[0] <= u < t[n]; *tl = t[i], *th = t[i+1].  The eight entries around the
+// one a linear table would hold u at are loaded together (one memory round
+// trip) and settle the search when they bracket u; otherwise the search
+// gallops outwards from the window's side and bisects the bracket.
+__device__ __forceinline__ int last_le(const float *__restrict__ t, int n, float u, float *tl, float *th) {
   int g = (int)(u * (float)n);
   g = g < n - 1 ? g : n - 1;
-  int lo, hi;  // t[lo] <= u < t[hi]
-  if (t[g] <= u) {
-    lo = g;
-    for (int step = 1;; step <<= 1) {
-      hi = lo + step;
-      if (hi >= n) {
-        hi = n;
-        break;
+  int a = g - 3;
+  a = a > n - 7 ? n - 7 : a;
+  a = a < 0 ? 0 : a;
+  const int m = n - a < 7 ? n - a : 7;  // the window is t[a .. a+m], m >= 1
+  float w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = t[a + (k < m ? k : m)];
+  if (w[0] <= u && u < w[m]) {
+    int c = 0;  // entries t[a+1 .. a+m-1] that are <= u
+#pragma unroll
+    for (int k = 1; k < 7; ++k) c += (k < m && w[k] <= u) ? 1 : 0;
+    float lo_v = w[0], hi_v = w[1];
+#pragma unroll
+    for (int k = 1; k < 7; ++k)
+      if (k == c) {
+        lo_v = w[k];
+        hi_v = w[k + 1];
       }
-      if (t[hi] > u) break;
-      lo = hi;
-    }
-  } else {
-    hi = g;
+    *tl = lo_v;
+    *th = hi_v;
+    return a + c;
+  }
+  int lo, hi;  // t[lo] <= u < t[hi]
+  if (w[0] > u) {  // left of the window (then a > 0, since t[0] <= u)
+    hi = a;
     for (int step = 1;; step <<= 1) {
       lo = hi - step;
       if (lo <= 0) {
@@ -39,12 +51,25 @@ __device__ __forceinline__ int last_le(const float *__restrict__ t, int n, float
       if (t[lo] <= u) break;
       hi = lo;
     }
+  } else {  // right of the window: t[a + m] <= u (then a + m < n)
+    lo = a + m;
+    for (int step = 1;; step <<= 1) {
+      hi = lo + step;
+      if (hi >= n) {
+        hi = n;
+        break;
+      }
+      if (t[hi] > u) break;
+      lo = hi;
+    }
   }
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (t[mid] <= u) lo = mid;
     else hi = mid;
   }
+  *tl = t[lo];
+  *th = t[lo + 1];
   return lo;
 }
 
@@ -57,11 +82,10 @@ __device__ __forceinline__ void guided_sample(const float *__restrict__ pdf, con
   const float two_over_h = 2.0f / (float)H;
   const float dphi = 6.283185307179586f / (float)W;
   const float *M = marg + (size_t)l * (H + 1);
-  const int i = last_le(M, H, u1);
+  float m0, m1, c0, c1;
+  const int i = last_le(M, H, u1, &m0, &m1);
   const float *C = cond + ((size_t)l * H + i) * (W + 1);
-  const int j = last_le(C, W, u2);
-  const float m0 = M[i], m1 = M[i + 1];
-  const float c0 = C[j], c1 = C[j + 1];
+  const int j = last_le(C, W, u2, &c0, &c1);
   float t1 = (u1 - m0) / (m1 - m0);
   float t2 = (u2 - c0) / (c1 - c0);
   t1 = fminf(fmaxf(t1, 0.0f), below1);

@@ -520,6 +520,31 @@ __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__
   }
 }
 
+// The 1x1 head + softplus on a C-channel activation (channel-last, type T)
+// when it is not fused into the previous layer (the paper-style network,
+// whose last conv adds a residual after its activation): one thread per
+// pixel, the pixel's channels in 16-byte loads, the bias plus the products
+// in channel order in binary64 (as the direct convolution sums them).
+template <class T, int C>
+__global__ __launch_bounds__(256) void head_kernel(const T *__restrict__ in, const float *__restrict__ w,
+                                                   const float *__restrict__ b, size_t npix,
+                                                   float *__restrict__ out) {
+  const size_t pix = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (pix >= npix) return;
+  constexpr int NV = C * (int)sizeof(T) / 16;
+  T v[C];
+  const uint4 *src = reinterpret_cast<const uint4 *>(in + pix * C);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const uint4 q = src[k];
+    __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * k, &q, 16);
+  }
+  double acc = (double)b[0];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc = fma((double)w[c], to_d<T>(v[c]), acc);
+  out[pix] = (float)softplus_f(acc);
+}
+
 // Sums of the four maps of the five-channel input per leaf (exact integer
 // sums, stored as binary64): tot[L][4] = (E_t, E_t-1, P_t, P_t-1).
 __global__ __launch_bounds__(256) void leaf_totals5_kernel(const uint64_t *__restrict__ e_t,
@@ -1813,8 +1838,26 @@ struct Runner {
         return NPG_OK;
       }
     }
-    // direct path; a fused head becomes a separate 1x1 direct layer
     const size_t npix = (size_t)Lc * H * W;
+    // an unfused 1x1 head on 16 or 32 channels (FP32 or BF16 activations)
+    if (!force_direct && act == ACT_SOFTPLUS && y.k == 1 && y.cout == 1 && src.mode == SRC_PLAIN && !res &&
+        !head && prec != NPG_FP8 && (y.cin == 16 || y.cin == 32)) {
+      const unsigned blocks = (unsigned)((npix + 255) / 256);
+      float *o = static_cast<float *>(out);
+      if (prec == NPG_FP32) {
+        const double *in = static_cast<const double *>(src.s0);
+        if (y.cin == 16) hipLaunchKernelGGL((head_kernel<double, 16>), dim3(blocks), dim3(256), 0, s, in, y.w, y.b, npix, o);
+        else hipLaunchKernelGGL((head_kernel<double, 32>), dim3(blocks), dim3(256), 0, s, in, y.w, y.b, npix, o);
+      } else {
+        const uint16_t *in = static_cast<const uint16_t *>(src.s0);
+        if (y.cin == 16) hipLaunchKernelGGL((head_kernel<uint16_t, 16>), dim3(blocks), dim3(256), 0, s, in, y.w, y.b, npix, o);
+        else hipLaunchKernelGGL((head_kernel<uint16_t, 32>), dim3(blocks), dim3(256), 0, s, in, y.w, y.b, npix, o);
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "head launch: %s", hipGetErrorString(e));
+      return NPG_OK;
+    }
+    // direct path; a fused head becomes a separate 1x1 direct layer
     void *dst = out;
     if (head) {
       // intermediate activation is written into the head's output region's

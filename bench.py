@@ -99,6 +99,25 @@ def model_flops_per_leaf(model: bytes, H: int, W: int) -> float:
     return tot
 
 
+def phase_saved_flops_per_leaf(model: bytes, H: int, W: int) -> float:
+    """FLOPs that the FP32-mode decoder convolutions do not issue: on their
+    nearest-upsampled channels (as many as the previous conv's outputs) a
+    3x3 conv takes 4 phase-merged taps per output pixel instead of 9."""
+    arch, levels, shapes = _model_shapes(model)
+    px = H * W
+    if arch == 1:
+        return 0.0
+    if arch == 3:
+        sched = _paper_schedule(shapes, levels, px)
+        return float(sum(2 * sched[i - 1][0] * co * 5 * p
+                         for i, (co, ci, k, p, kind) in enumerate(sched) if kind == "cat"))
+    saved, li = 0.0, 2 * levels
+    for d in range(levels - 2, -1, -1):
+        saved += 2 * shapes[li - 1][0] * shapes[li][0] * 5 * (px >> (2 * d))
+        li += 2
+    return saved
+
+
 def model_bytes_per_leaf(model: bytes, H: int, W: int, esz: int, in_bytes: float = 8.0) -> float:
     """Algorithmic HBM bytes of one leaf's network pass: every layer reads its
     input once (in_bytes per pixel for the first layer: the u64 energy map,
@@ -680,6 +699,8 @@ def main():
     else:
         peak, peak_name = PEAK["bf16_mfma_TFLOPs"], "BF16 MFMA"
     achieved = flops / recon_s / 1e12
+    # what the matrix cores execute (FP32 mode: phase-merged decoder taps)
+    issued = flops - (phase_saved_flops_per_leaf(model, H, W) * L if args.precision == "fp32" else 0.0)
     esz = {"fp32": 8, "bf16": 2, "fp8": 1}[args.precision]
     bytes_alg = model_bytes_per_leaf(model_bytes, H, W, esz, 24.0 if args.input5 else 8.0) * L
     ridge = peak * 1e12 / (PEAK["hbm_GBps"] * 1e9)
@@ -732,6 +753,8 @@ def main():
                      "kernel": f"reconstruct_density (implicit-GEMM conv stack), {peak_name}",
                      "flops_per_launch": flops, "bytes_per_launch": bytes_alg,
                      "intensity_flop_per_byte": flops / bytes_alg, "ridge_flop_per_byte": ridge,
+                     "issued_flops_per_launch": issued, "issued_TFLOPs": issued / recon_s / 1e12,
+                     "issued_frac": issued / recon_s / 1e12 / peak,
                      "avg_launch_ms": avg["recon"], "source_sha": src_sha},
     }
     res["sampling_chi2"] = sampling_chi2(npg, ctx, tabs, L, H, W)

@@ -114,6 +114,10 @@ void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak);
  *   "fuse_first"   0: store the first layer's activations instead of
  *                  computing them inside the second layer's input staging
  *                  (default 1; the results are identical)
+ *   "upsample_taps9" 1: FP32-mode decoder convolutions take all nine taps on
+ *                  their nearest-upsampled channels instead of four
+ *                  phase-merged taps per output phase (testing; default 0;
+ *                  the results agree to rounding)
  * NPG_E_ARG for an unknown name or a negative value. */
 int npg_set_option(npg_ctx *ctx, const char *name, int64_t value);
 

@@ -51,6 +51,9 @@ struct LayerDev {
   float *w = nullptr;          // OIHW float32
   float *b = nullptr;          // [cout]
   float *pk32 = nullptr;       // [chunk][tap][kc16][cout]
+  double *pkp = nullptr;       // [chunk][phase][tap 2x2][kc16][cout]: weights of a 3x3 conv on a
+                               // nearest-upsampled input, merged per output phase (exact sums)
+  double *pk64 = nullptr;      // pk32 in binary64 (the concatenated chunks of such a conv)
   uint16_t *pk16 = nullptr;    // [chunk][tap][cout][kc32] (bf16 bits)
   uint16_t *pk16s = nullptr;   // [chunk][tap][cout][kc16] (bf16 bits)
   // FP8 (after calibration): e4m3 weights with the input channels' activation
@@ -255,7 +258,7 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
   }
   // host-side repacking into one blob
   std::vector<char> blob;
-  struct Off { size_t w, b, p32, p16, p16s; };
+  struct Off { size_t w, b, p32, p16, p16s, pp, p64; };
   std::vector<Off> offs(m->layer.size());
   auto put = [&](const void *src, size_t bytes) {
     size_t at = npg_align(blob.size());
@@ -268,7 +271,7 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
     const std::vector<float> &w = m->host_w[i];
     offs[i].w = put(w.data(), 4 * w.size());
     offs[i].b = put(m->host_b[i].data(), 4 * (size_t)y.cout);
-    offs[i].p32 = offs[i].p16 = offs[i].p16s = (size_t)-1;
+    offs[i].p32 = offs[i].p16 = offs[i].p16s = offs[i].pp = offs[i].p64 = (size_t)-1;
     if (y.k == 3) {
       const int nch32 = (y.cin + KC32 - 1) / KC32, nch16 = (y.cin + KC16 - 1) / KC16;
       const int nch16s = (y.cin + KC16S - 1) / KC16S;
@@ -287,6 +290,29 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
             p16s[(((size_t)c16s * 9 + t) * y.cout + co) * KC16S + k16s] = f32_to_bf16_host(v);
           }
       offs[i].p32 = put(p32.data(), 4 * p32.size());
+      if (y.cin >= 16) {
+        // On a nearest-upsampled input, output pixel (2i + a, 2j + b) reads
+        // low-resolution rows {i - 1, i} (a = 0: kernel row 0, then rows
+        // 1 + 2) or {i, i + 1} (a = 1: rows 0 + 1, then row 2), and columns
+        // likewise: per phase (a, b) a 2x2 conv whose taps are sums of the
+        // 3x3 taps; the sums of float32 weights are exact in binary64.
+        static const int lo[2][2] = {{0, 1}, {0, 2}}, hi[2][2] = {{0, 2}, {1, 2}};  // [a][i]: rows lo..hi
+        std::vector<double> pp((size_t)nch32 * 16 * KC32 * y.cout, 0.0);
+        for (int co = 0; co < y.cout; ++co)
+          for (int ci = 0; ci < y.cin; ++ci)
+            for (int ph = 0; ph < 4; ++ph)
+              for (int t = 0; t < 4; ++t) {
+                const int pa = ph >> 1, pb = ph & 1, ti = t >> 1, tj = t & 1;
+                double v = 0.0;
+                for (int r = lo[pa][ti]; r <= hi[pa][ti]; ++r)
+                  for (int c = lo[pb][tj]; c <= hi[pb][tj]; ++c) v += (double)w[((size_t)co * y.cin + ci) * 9 + r * 3 + c];
+                const int c32 = ci / KC32, k32 = ci % KC32;
+                pp[((((size_t)c32 * 4 + ph) * 4 + t) * KC32 + k32) * y.cout + co] = v;
+              }
+        offs[i].pp = put(pp.data(), 8 * pp.size());
+        const std::vector<double> p64(p32.begin(), p32.end());
+        offs[i].p64 = put(p64.data(), 8 * p64.size());
+      }
       offs[i].p16 = put(p16.data(), 2 * p16.size());
       offs[i].p16s = put(p16s.data(), 2 * p16s.size());
     }
@@ -310,6 +336,8 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
     y.b = reinterpret_cast<float *>(base + offs[i].b);
     if (offs[i].p32 != (size_t)-1) {
       y.pk32 = reinterpret_cast<float *>(base + offs[i].p32);
+      if (offs[i].pp != (size_t)-1) y.pkp = reinterpret_cast<double *>(base + offs[i].pp);
+      if (offs[i].p64 != (size_t)-1) y.pk64 = reinterpret_cast<double *>(base + offs[i].p64);
       y.pk16 = reinterpret_cast<uint16_t *>(base + offs[i].p16);
       y.pk16s = reinterpret_cast<uint16_t *>(base + offs[i].p16s);
     }
@@ -757,6 +785,8 @@ struct ConvArgs {
   int Lc;                 // leaves in this launch
   int tiles_x, tiles_per_leaf;
   const void *wpk;
+  const void *wpp = nullptr;   // phase-merged weights (upsampled chunks, staging mode 3)
+  const void *wpk64 = nullptr; // binary64 weights of the concatenated chunks (mode 3)
   const float *bias;
   const float *head_w;   // non-null: fuse the 1x1 head + softplus (Cout == 16)
   float head_b;
@@ -866,7 +896,11 @@ __device__ __forceinline__ uint4 pool_combine(const uint4 &a, const uint4 &b, co
 // then shared by TL leaves).
 // Staging modes: 0 plain or upsampled+concatenated input, 1 2x2-pooled
 // input, 2 the first layer (one input channel, 16 outputs, ReLU) computed
-// into the patch from the energy map, as conv_first_kernel would store it.
+// into the patch from the energy map, as conv_first_kernel would store it,
+// 3 (FP64 tiles) upsampled+concatenated input with the output pixels in
+// phase order: wavefront w holds the pixels of row parity w / 2 and column
+// parity w % 2, and the upsampled channels take four phase-merged taps
+// instead of nine (the concatenated ones keep nine).
 // 16 bytes of stored activations plus 16 bytes of the residual, element by
 // element in binary64, rounded once to the storage type.
 template <class T>
@@ -921,10 +955,17 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   int bp[MW];
 #pragma unroll
   for (int mi = 0; mi < MW; ++mi) {
-    const int m = wave * 16 * MW + mi * 16 + lr;
-    const int ls = (int)fdiv((uint32_t)m, a.fTPX), rem = m - ls * TPX;
-    const int ry = (int)fdiv((uint32_t)rem, a.fTW);
-    bp[mi] = ls * PH * PW + ry * PW + (rem - ry * TW);
+    if constexpr (MODE == 3) {
+      // pixel mi * 16 + lr of the wavefront's phase: TPX / 4 per leaf
+      const int m = mi * 16 + lr, Q = TPX >> 2, hw2 = TW >> 1;
+      const int ls = m / Q, rem = m - ls * Q, qy = rem / hw2;
+      bp[mi] = ls * PH * PW + (2 * qy + (wave >> 1)) * PW + 2 * (rem - qy * hw2) + (wave & 1);
+    } else {
+      const int m = wave * 16 * MW + mi * 16 + lr;
+      const int ls = (int)fdiv((uint32_t)m, a.fTPX), rem = m - ls * TPX;
+      const int ry = (int)fdiv((uint32_t)rem, a.fTW);
+      bp[mi] = ls * PH * PW + ry * PW + (rem - ry * TW);
+    }
   }
   AccV acc[MW][NW];
 #pragma unroll
@@ -932,26 +973,37 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
     for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = AccV{0, 0, 0, 0};
 
-  // the nine taps of one K chunk on the staged patch (weights wg of the chunk)
-  auto taps = [&](const WT *wg) {
-    // WGLB: this lane's B values of a tap, [k step][n tile]
-    float wcur[WGLB ? KC / 4 : 1][WGLB ? NW : 1], wnxt[WGLB ? KC / 4 : 1][WGLB ? NW : 1];
+  // the nine taps of one K chunk on the staged patch (weights wg of the
+  // chunk); NT = 4: the four phase-merged taps of an upsampled chunk (mode 3)
+  auto taps = [&](const WT *wg, int NT) {
+    // WGLB: this lane's B values of a tap, [k step][n tile]; mode 3 reads
+    // binary64 weights (its phase-merged taps are binary64 sums)
+    using WR = std::conditional_t<MODE == 3, double, float>;
+    WR wcur[WGLB ? KC / 4 : 1][WGLB ? NW : 1], wnxt[WGLB ? KC / 4 : 1][WGLB ? NW : 1];
+    auto wld = [&](int i) -> WR {
+      if constexpr (MODE == 3) return reinterpret_cast<const double *>(wg)[i];
+      return wg[i];
+    };
     if constexpr (WGLB) {
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks)
 #pragma unroll
-        for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wg[(ks * 4 + lg) * BN + ni * 16 + lr];
+        for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wld((ks * 4 + lg) * BN + ni * 16 + lr);
     }
 #pragma unroll 1
-    for (int tap = 0; tap < 9; ++tap) {
-      const int toff = ((tap / 3) * PW + (tap % 3)) * DIL;
+    for (int tap = 0; tap < NT; ++tap) {
+      int toff;
+      if constexpr (MODE == 3)
+        toff = NT == 4 ? (tap >> 1) * PW + (tap & 1) + (wave >> 1) * PW + (wave & 1) : (tap / 3) * PW + (tap % 3);
+      else
+        toff = ((tap / 3) * PW + (tap % 3)) * DIL;
       if constexpr (WGLB) {
-        if (tap < 8) {
+        if (tap + 1 < NT) {
 #pragma unroll
           for (int ks = 0; ks < KC / 4; ++ks)
 #pragma unroll
             for (int ni = 0; ni < NW; ++ni)
-              wnxt[ks][ni] = wg[((tap + 1) * KC + ks * 4 + lg) * BN + ni * 16 + lr];
+              wnxt[ks][ni] = wld(((tap + 1) * KC + ks * 4 + lg) * BN + ni * 16 + lr);
         }
       }
       if constexpr (IS_F32) {
@@ -1013,12 +1065,24 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     }
   };
 
+  // the taps of chunk ch: phase-merged for upsampled channels in mode 3
+  auto chunk_taps = [&](int ch, const WT *wg) {
+    int nt = 9;
+    if constexpr (MODE == 3) {
+      const bool up = ch * KC < a.src.C0;
+      nt = up ? 4 : 9;
+      wg = reinterpret_cast<const WT *>(up ? static_cast<const double *>(a.wpp) + ((size_t)ch * 4 + wave) * 4 * KC * BN
+                                           : static_cast<const double *>(a.wpk64) + (size_t)ch * 9 * KC * BN);
+    }
+    taps(wg, nt);  // one call site: one copy of the tap loop
+  };
+
   // FP64 tiles on plain or concatenated inputs whose patch has at most one
   // pixel per thread: the next chunk's pixel is loaded into registers while
   // the matrix cores work on the current chunk (their weights come straight
   // from global memory, so the patch is all there is to stage)
   bool piped = false;
-  if constexpr (WGLB && MODE == 0) {
+  if constexpr (WGLB && (MODE == 0 || MODE == 3)) {
     const int npx = TL * PH * PW;
     if (npx <= 256) {
       piped = true;
@@ -1043,7 +1107,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       __syncthreads();
       for (int ch = 0; ch < a.nchunk; ++ch) {
         if (ch + 1 < a.nchunk) load_px(ch + 1, nv);
-        taps(static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN);
+        chunk_taps(ch, static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN);
         __syncthreads();
         if (ch + 1 < a.nchunk) {
           store_px(nv);
@@ -1250,7 +1314,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     }
     __syncthreads();
-    taps(wg);
+    chunk_taps(ch, wg);
     __syncthreads();
   }
 
@@ -1258,6 +1322,12 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // barrier) so that global stores are whole 16-byte pieces of output rows
   const int BM = 64 * MW;
   auto gpix = [&](int m) -> long {  // global pixel index of tile pixel m, -1 if past the last leaf
+    if constexpr (MODE == 3) {
+      const int w = m / (16 * MW), mp = m - w * 16 * MW, Q = TPX >> 2, hw2 = TW >> 1;
+      const int ls = mp / Q, rem = mp - ls * Q, qy = rem / hw2;
+      if (leaf0 + ls >= a.Lc) return -1;
+      return ((long)(leaf0 + ls) * H + ty0 + 2 * qy + (w >> 1)) * W + tx0 + 2 * (rem - qy * hw2) + (w & 1);
+    }
     const int ls = (int)fdiv((uint32_t)m, a.fTPX), rem = m - ls * TPX;
     if (leaf0 + ls >= a.Lc) return -1;
     const int ry = (int)fdiv((uint32_t)rem, a.fTW);
@@ -1542,6 +1612,10 @@ hipError_t launch_mfma_k(const ConvArgs &a, size_t lds, unsigned tiles, hipStrea
 template <class P, int MW, int NW>
 hipError_t launch_mfma_t(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
   if (a.src.mode == SRC_POOL) return launch_mfma_k<P, MW, NW, 1>(a, lds, tiles, s);
+  if (a.wpp) {
+    if constexpr (P::F64) return launch_mfma_k<P, MW, NW, 3>(a, lds, tiles, s);
+    return hipErrorInvalidValue;
+  }
   if (a.src.mode == SRC_ENERGY) {
     if constexpr (NW == 1 && P::KC <= 16 && 16 % P::KC == 0) return launch_mfma_k<P, MW, NW, 2>(a, lds, tiles, s);
     return hipErrorInvalidValue;
@@ -1588,6 +1662,7 @@ struct Runner {
   hipStream_t s;
   size_t esz;  // bytes per activation element
   int force_direct = 0;
+  int upsample_taps9 = 0;                    // 1: upsampled channels with nine taps (testing)
   const std::vector<int> *mw_cap = nullptr;  // per conv call of a chunk (autotuned)
   int mw_all = 4;                            // cap for every call (autotuner probes)
   std::vector<hipEvent_t> *ev = nullptr;     // per-call begin/end events (autotuner)
@@ -1761,6 +1836,12 @@ struct Runner {
       if (prec == NPG_FP32) {
         a.nchunk = (y.cin + KC32 - 1) / KC32;
         a.wpk = y.pk32;
+        // upsampled channels by phase (every tile here has even TR and TW)
+        if (src.mode == SRC_UPCAT && !head && y.dil == 1 && y.pkp && y.pk64 && !upsample_taps9 && t.TR % 2 == 0 &&
+            t.TW % 2 == 0 && t.TL * t.TR * t.TW == 64 * t.MW) {
+          a.wpp = y.pkp;
+          a.wpk64 = y.pk64;
+        }
         e = launch_mfma<F32P>(a, t, tiles, s);
       } else if (prec == NPG_FP8 && y.cin % KC8 == 0) {
         a.nchunk = y.cin / KC8;
@@ -2118,6 +2199,7 @@ std::string tune_key(const npg_model *m, npg_precision p, int H, int W) {
 Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStream_t s) {
   Runner R{ctx, m, prec, s, prec == NPG_FP32 ? sizeof(double) : prec == NPG_FP8 ? (size_t)1 : (size_t)2};
   R.force_direct = (int)ctx->opt("force_direct", 0);
+  R.upsample_taps9 = (int)ctx->opt("upsample_taps9", 0);
   R.fuse_first = ctx->opt("fuse_first", 1) ? 1 : 0;
   return R;
 }

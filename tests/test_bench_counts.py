@@ -40,6 +40,19 @@ def test_cnn_flops_per_leaf():
     assert bench.model_flops_per_leaf(synth.cnn_model(1), 32, 32) == _flops(L, [1024] * 3)
 
 
+def test_phase_saved_flops():
+    """FP32-mode decoder convs skip 5 of 9 taps on their upsampled channels:
+    U-Net 16/32/64/128 at 64x64: 128, 64, 32 upsampled channels into 64,
+    32, 16 outputs at 16x16, 32x32, 64x64; paper-style 16/32/64: 64 and 32
+    into 32 and 16 at 32x32 and 64x64."""
+    px = 64 * 64
+    want = 2 * 5 * (128 * 64 * px // 16 + 64 * 32 * px // 4 + 32 * 16 * px)
+    assert bench.phase_saved_flops_per_leaf(synth.unet_model(1), 64, 64) == want
+    want3 = 2 * 5 * (64 * 32 * px // 4 + 32 * 16 * px)
+    assert bench.phase_saved_flops_per_leaf(synth.paper_unet_model(1), 64, 64) == want3
+    assert bench.phase_saved_flops_per_leaf(synth.cnn_model(1), 32, 32) == 0.0
+
+
 def test_paper_net_bytes_per_leaf():
     """Every conv reads its input and writes its output once; residual convs
     read their residual too; the first reads 24 B per pixel (two u64 energy

@@ -700,7 +700,7 @@ def main():
         peak, peak_name = PEAK["bf16_mfma_TFLOPs"], "BF16 MFMA"
     achieved = flops / recon_s / 1e12
     # what the matrix cores execute (FP32 mode: phase-merged decoder taps)
-    issued = flops - (phase_saved_flops_per_leaf(model, H, W) * L if args.precision == "fp32" else 0.0)
+    issued = flops - (phase_saved_flops_per_leaf(model_bytes, H, W) * L if args.precision == "fp32" else 0.0)
     esz = {"fp32": 8, "bf16": 2, "fp8": 1}[args.precision]
     bytes_alg = model_bytes_per_leaf(model_bytes, H, W, esz, 24.0 if args.input5 else 8.0) * L
     ridge = peak * 1e12 / (PEAK["hbm_GBps"] * 1e9)

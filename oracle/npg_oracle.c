@@ -603,10 +603,9 @@ int or_net_forward5(const unsigned char *model, size_t model_len, const double *
 }
 
 /* The five input channels of Sec. 6 for each leaf: the raw sampling maps of
- * iterations t and t-1 (energies E, mean 1: H*W*E/sum(E), 0 for an empty
- * map), their photon-count maps normalised the same way, and the mask of
- * bins holding photons at iteration t; each map value rounded to float32
- * (as the one-channel raw map).  x[L][5][H][W]. */
+ * iterations t and t-1 (energies E, mean 1: H*W*E/sum(E) in FP64, 0 for an
+ * empty map), their photon-count maps normalised the same way, and the mask
+ * of bins holding photons at iteration t.  x[L][5][H][W], FP64 throughout. */
 void or_input5(const uint64_t *e_t, const uint64_t *e_p, const uint32_t *p_t, const uint32_t *p_p,
                int64_t L, int H, int W, double *x) {
   size_t HW = (size_t)H * W;
@@ -622,8 +621,8 @@ void or_input5(const uint64_t *e_t, const uint64_t *e_p, const uint32_t *p_t, co
         T += (double)P[c][k];
       }
       for (size_t k = 0; k < HW; k++) {
-        xl[(size_t)c * HW + k] = S > 0.0 ? (double)(float)((double)HW * (double)E[c][k] / S) : 0.0;
-        xl[(size_t)(2 + c) * HW + k] = T > 0.0 ? (double)(float)((double)HW * (double)P[c][k] / T) : 0.0;
+        xl[(size_t)c * HW + k] = S > 0.0 ? (double)HW * (double)E[c][k] / S : 0.0;
+        xl[(size_t)(2 + c) * HW + k] = T > 0.0 ? (double)HW * (double)P[c][k] / T : 0.0;
       }
     }
     for (size_t k = 0; k < HW; k++) xl[4 * HW + k] = P[0][k] > 0 ? 1.0 : 0.0;

@@ -447,26 +447,32 @@ __device__ __forceinline__ double src_at(const Src &s, int leaf, int y, int x, i
 
 // The paper's first layer on its five input channels (Sec. 6): raw maps of
 // iterations t and t-1 (mean-1 energies), their photon counts normalised the
-// same way (each value rounded to float32, as the one-channel raw map), and
-// the mask B of bins with photons at t, as a masked (partial) convolution:
-// only taps with B = 1 contribute, and the sum is rescaled by 9/S for the
-// S valid in-map taps (zero output where S = 0), then bias and ReLU.
+// same way, and the mask B of bins with photons at t, as a masked (partial)
+// convolution: only taps with B = 1 contribute, and the sum is rescaled by
+// 9/S for the S valid in-map taps (zero output where S = 0), then bias and
+// the activation.
 //
 // One workgroup per tile of TR x TW output pixels of one leaf (TW = min(W,
 // 256), TR = min(H, 256 / TW); grid = (tiles per leaf, leaves)).  The tile
-// and its one-pixel halo are normalised once into LDS as float4 (x0..x3);
-// bins without photons at t and bins outside the map hold zeros, so their
-// taps add exact zeros, and B = [x2 > 0] (a bin with P > 0 has x2 >= 2^-32 *
-// H*W / H*W > 0).  Each thread then sums its nine taps from LDS in tap-major,
-// channel-minor order and writes its COUT outputs as 16-byte stores;
-// out T [L][H][W][COUT].
+// and its one-pixel halo are normalised once into LDS as four values of the
+// accumulation type (binary64 in FP32 mode, so the normalised maps are never
+// rounded to float32; float in BF16 mode); bins without photons at t and
+// bins outside the map hold zeros, so their taps add exact zeros, and B =
+// [x2 > 0] (a bin with P > 0 has x2 >= H*W / 2^32 > 0).  Each thread then
+// sums its nine taps from LDS in tap-major, channel-minor order and writes
+// its COUT outputs as 16-byte stores; out T [L][H][W][COUT].
 constexpr int F5_LDS = 774;  // (TR + 2) * (TW + 2) for TR * TW = 256, at most 3 * 258
+
+template <class A>
+struct alignas(16) Quad {
+  A x, y, z, w;
+};
 
 template <class T, class Acc, int COUT, int ACT>
 __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__restrict__ w,
                                                           const float *__restrict__ b, int H, int W, int TW,
                                                           int TR, void *out) {
-  __shared__ float4 tile[F5_LDS];
+  __shared__ Quad<Acc> tile[F5_LDS];
   const int tiles_x = W / TW;
   const int tx0 = (int)(blockIdx.x % (unsigned)tiles_x) * TW, ty0 = (int)(blockIdx.x / (unsigned)tiles_x) * TR;
   const size_t leaf = blockIdx.y, HW = (size_t)H * W, base = leaf * HW;
@@ -501,10 +507,10 @@ __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__
   for (int j = 0; j < 4; ++j) {
     const int i = (int)threadIdx.x + 256 * j;
     if (j < nj && i < n_in) {
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      Quad<Acc> v{(Acc)0, (Acc)0, (Acc)0, (Acc)0};
       if (ok[j] && vp[j][0] != 0)
-        v = make_float4((float)((double)ve[j][0] * inv[0]), (float)((double)ve[j][1] * inv[1]),
-                        (float)((double)vp[j][0] * inv[2]), (float)((double)vp[j][1] * inv[3]));
+        v = Quad<Acc>{(Acc)((double)ve[j][0] * inv[0]), (Acc)((double)ve[j][1] * inv[1]),
+                      (Acc)((double)vp[j][0] * inv[2]), (Acc)((double)vp[j][1] * inv[3])};
       tile[i] = v;
     }
   }
@@ -517,10 +523,10 @@ __global__ __launch_bounds__(256) void conv_first5_kernel(Src s, const float *__
   int S = 0;
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    const float4 v = tile[(ly + t / 3) * LW + lx + t % 3];
-    const int m = v.z > 0.0f;
+    const Quad<Acc> v = tile[(ly + t / 3) * LW + lx + t % 3];
+    const int m = v.z > (Acc)0;
     S += m;
-    const Acc xv[5] = {(Acc)v.x, (Acc)v.y, (Acc)v.z, (Acc)v.w, (Acc)m};
+    const Acc xv[5] = {v.x, v.y, v.z, v.w, (Acc)m};
 #pragma unroll
     for (int c = 0; c < COUT; ++c)
 #pragma unroll
@@ -1752,6 +1758,10 @@ struct Runner {
     a.oinv0 = prec == NPG_FP8 ? 1.0f / l0.a8 : 1.0f;
     a.out = out;
     const unsigned tiles = (unsigned)((Lc + t.TL - 1) / t.TL) * a.tiles_per_leaf;
+    // layer 1 on the matrix cores; layer 0 recomputed on the vector ALUs for
+    // every patch pixel (the tile and its one-pixel halo)
+    ctx->conv_flops[0] += 2.0 * Lc * H * W * 16.0 * 9.0 * 16.0;
+    ctx->conv_flops[1] += 2.0 * tiles * t.TL * (t.TR + 2.0) * (t.TW + 2.0) * 16.0 * 9.0;
     hipError_t e;
     if (prec == NPG_FP32) {
       a.wpk = l1.pk32;
@@ -1832,6 +1842,8 @@ struct Runner {
       a.asc = y.a8;
       a.out = out;
       const unsigned tiles = (unsigned)((Lc + t.TL - 1) / t.TL) * a.tiles_per_leaf;
+      const double px = (double)Lc * H * W;
+      double taps_x_cin = 9.0 * y.cin;  // multiply-adds per output channel and pixel
       hipError_t e;
       if (prec == NPG_FP32) {
         a.nchunk = (y.cin + KC32 - 1) / KC32;
@@ -1841,29 +1853,37 @@ struct Runner {
             t.TW % 2 == 0 && t.TL * t.TR * t.TW == 64 * t.MW) {
           a.wpp = y.pkp;
           a.wpk64 = y.pk64;
+          taps_x_cin = 4.0 * src.C0 + 9.0 * src.C1;
         }
+        ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         e = launch_mfma<F32P>(a, t, tiles, s);
       } else if (prec == NPG_FP8 && y.cin % KC8 == 0) {
+        ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = y.cin / KC8;
         a.wpk = y.pk8;
         e = launch_mfma<FP8P>(a, t, tiles, s);
       } else if (prec == NPG_FP8) {
+        ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = (y.cin + KC8S - 1) / KC8S;
         a.wpk = y.pk8s;
         e = launch_mfma<FP8S>(a, t, tiles, s);
       } else if (y.cin % KC16 == 0) {
+        ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = y.cin / KC16;
         a.wpk = y.pk16;
         e = launch_mfma<BF16P>(a, t, tiles, s);
       } else {
+        ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = (y.cin + KC16S - 1) / KC16S;
         a.wpk = y.pk16s;
         e = launch_mfma<BF16S>(a, t, tiles, s);
       }
+      if (head) ctx->conv_flops[1] += 2.0 * px * head->cin;  // 1x1 head in the epilogue
       if (e != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "conv launch: %s", hipGetErrorString(e));
       return NPG_OK;
     }
     if (src.mode == SRC_FIVE) {
+      ctx->conv_flops[1] += 2.0 * Lc * H * W * y.cout * 5.0 * 9.0;
       if (y.k != 3 || y.cin != 5 || (act != ACT_RELU && act != ACT_ELU) || head || res || prec == NPG_FP8)
         return npg_fail(ctx, NPG_E_ARG, "internal: five-channel first layer");
       // tile of TR x TW pixels per workgroup (H, W powers of two, 4..1024)
@@ -1901,6 +1921,7 @@ struct Runner {
         H * W >= 256 && !head && !res) {
       const int TW = std::min(W, 256), TR = 256 / TW;
       if (TR <= H) {
+        ctx->conv_flops[1] += 2.0 * Lc * H * W * y.cout * 9.0;
         const unsigned blocks = (unsigned)Lc * (H / TR) * (W / TW);
         if (prec == NPG_FP32)
           hipLaunchKernelGGL((conv_first_kernel<double, double>), dim3(blocks), dim3(256), 0, s,
@@ -1923,6 +1944,7 @@ struct Runner {
     // an unfused 1x1 head on 16 or 32 channels (FP32 or BF16 activations)
     if (!force_direct && act == ACT_SOFTPLUS && y.k == 1 && y.cout == 1 && src.mode == SRC_PLAIN && !res &&
         !head && prec != NPG_FP8 && (y.cin == 16 || y.cin == 32)) {
+      ctx->conv_flops[1] += 2.0 * npix * y.cin;
       const unsigned blocks = (unsigned)((npix + 255) / 256);
       float *o = static_cast<float *>(out);
       if (prec == NPG_FP32) {
@@ -1945,6 +1967,7 @@ struct Runner {
       // companion buffer provided by the caller through `out` of this call:
       return npg_fail(ctx, NPG_E_ARG, "internal: head fusion without MFMA tiling");
     }
+    ctx->conv_flops[1] += 2.0 * npix * y.cout * y.cin * y.k * y.k;
     const unsigned blocks = (unsigned)((npix + 255) / 256);
     if (prec == NPG_FP32)
       hipLaunchKernelGGL(conv_direct_kernel<double>, dim3(blocks), dim3(256), 0, s, src, y.w, y.b, y.cin,

@@ -69,6 +69,19 @@ def test_input5_hand_case(orc):
     assert np.array_equal(x[0, 4], [[1.0, 0.0], [1.0, 0.0]])
 
 
+def test_input5_stays_binary64(orc):
+    """Three equal bins of a 2x2 map: each normalised value is H*W/3 = 4/3,
+    which float32 cannot hold (nearest float32 1.3333333730697632); the
+    channels are binary64 and keep mean 1 to the last bit."""
+    e_t = np.array([[[5, 5], [5, 0]]], np.uint64)
+    p_t = np.array([[[7, 7], [7, 0]]], np.uint32)
+    x = orc.input5(e_t, e_t, p_t, p_t)
+    for c in range(4):
+        assert np.array_equal(x[0, c], [[4.0 / 3.0, 4.0 / 3.0], [4.0 / 3.0, 0.0]]), c
+        assert float(np.float32(x[0, c, 0, 0])) != x[0, c, 0, 0]
+    assert abs(x[0, 0].sum() - 4.0) <= 4 * np.finfo(np.float64).eps
+
+
 def _torch_unet5(ws, bs, D, x):
     t = lambda a: torch.from_numpy(np.asarray(a, np.float64))
     h = torch.from_numpy(x)

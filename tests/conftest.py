@@ -33,3 +33,18 @@ def ctx(npg):
     c = npg.Context(0)
     yield c
     c.close()
+
+
+@pytest.fixture(scope="session")
+def clustered():
+    """The clustered workload's 5e7 photons (generated once per session)."""
+    from paper_2010_01775_amd import synth
+    return synth.clustered_photons()
+
+
+@pytest.fixture(scope="session")
+def clustered_tree(orc, clustered):
+    """The oracle's octree (split > 8192, depth <= 6) over those photons."""
+    rc, ref = orc.build_tree(clustered.pos, 8192, 6, max_leaves=1 << 20)
+    assert rc == 0
+    return ref

@@ -115,11 +115,6 @@ def test_autotune_keeps_results(ctx, npg):
     m.free()
 
 
-@pytest.fixture(scope="module")
-def clustered():
-    return synth.clustered_photons()
-
-
 def test_clustered_full_size_sampled_leaves(ctx, npg, orc, clustered):
     """5e7 clustered photons, octree (split > 8192, depth <= 6), 128x128 maps,
     U-Net FP32 through the fused path as the benchmark launches it; tables of

@@ -1,0 +1,167 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration
+bench.py times (build_hierarchy -> splat_histograms through the permutation
+-> reconstruct_density with autotuned tiles -> build_cdf):
+
+* uniform batch (1024 leaves x 4096 photons, 64x64, U-Net, FP32 mode): maps
+  bit-exact and densities within 1e-5 of the oracle on every leaf;
+* clustered workload (5e7 photons, octree split > 8192, depth <= 6, 128x128):
+  energy and count maps bit-exact on every leaf against the oracle's own tree
+  and splat; CDF tables on every leaf within one float32 rounding of the
+  oracle's, on the oracle's normalised maps as densities (spiky, sparse rows,
+  the workload's structure); the network's densities on a photon-count
+  stratified sample of leaves against the oracle, and the chain's tables on
+  every leaf checked for the properties any valid table has.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2010_01775_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(DEV)
+
+
+def tf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def _check_pdf(pdf, ref, where):
+    """1e-5 relative on bins with p >= 1e-6 * (leaf max); below that (spiky
+    leaves push some densities towards float32 underflow), 1e-5 of the
+    threshold, absolute."""
+    L = ref.shape[0]
+    pdf = pdf.astype(np.float64)
+    thr = np.broadcast_to(1e-6 * ref.reshape(L, -1).max(1)[:, None, None], ref.shape)
+    big = ref >= thr
+    rel = np.abs(pdf - ref)[big] / ref[big]
+    small = (np.abs(pdf - ref) / thr)[~big]
+    print(f"{where}: max rel pdf err {rel.max():.2e} on {big.sum()} bins; {(~big).sum()} bins below "
+          f"1e-6 max (max err/threshold {small.max() if small.size else 0:.2e})")
+    assert rel.max() < 1e-5, rel.max()
+    assert small.size == 0 or small.max() < 1e-5
+
+
+def _table_properties(tabs, L, H, W):
+    """Every leaf: tables finite, marginal and conditionals non-decreasing from
+    exactly 0 to exactly 1, pdf >= 0 and integrating to 1 over the sphere."""
+    marg, cond = tabs.marg, tabs.cond
+    assert torch.isfinite(tabs.pdf).all() and torch.isfinite(marg).all() and torch.isfinite(cond).all()
+    assert (marg[:, 0] == 0).all() and (marg[:, H] == 1).all()
+    assert (cond[:, :, 0] == 0).all() and (cond[:, :, W] == 1).all()
+    assert (marg[:, 1:] >= marg[:, :-1]).all() and (cond[:, :, 1:] >= cond[:, :, :-1]).all()
+    assert (tabs.pdf >= 0).all()
+    integral = tabs.pdf.double().sum((1, 2)) * (4 * np.pi / (H * W))
+    assert torch.allclose(integral, torch.ones_like(integral), rtol=0, atol=1e-5), \
+        float((integral - 1).abs().max())
+
+
+def test_uniform_batch_every_leaf(ctx, npg, orc):
+    b = synth.uniform_batch()
+    L, H, W = b.L, b.H, b.W
+    m = npg.Model(ctx, b.model)
+    npg.autotune(ctx, m, H, W, "fp32", probe_leaves=1024)
+    e, c = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), H, W)
+    s = npg.reconstruct_density(ctx, m, e, "fp32", count=c)
+    tabs = npg.build_cdf(ctx, s)
+    assert npg.sync_status(ctx) == 0
+    rc, e_ref, c_ref = orc.splat(b.dirs, b.w, b.leaf_off, H, W)
+    assert rc == 0
+    assert np.array_equal(e.cpu().numpy().view(np.uint64), e_ref)
+    assert np.array_equal(c.cpu().numpy().view(np.uint32), c_ref)
+    rc, s_ref = orc.net_forward(b.model, orc.normalize_input(e_ref))
+    assert rc == 0
+    rc, pdf_ref, marg_ref, cond_ref, _ = orc.build_cdf(s_ref)
+    assert rc == 0
+    pdf = tabs.pdf.cpu().numpy()
+    rel = np.abs(pdf.astype(np.float64) - pdf_ref) / pdf_ref
+    print(f"uniform batch, all {L} leaves: max rel pdf err {rel.max():.2e}")
+    assert rel.max() < 1e-5
+    # the tables follow the densities: prefixes within 1e-5 (absolute, they
+    # lie in [0, 1]) plus one float32 rounding of the oracle's
+    for got, want in ((tabs.marg, marg_ref), (tabs.cond, cond_ref)):
+        g = got.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(g - want) <= 1e-5 * np.abs(want) + np.spacing(np.float32(1.0))), \
+            np.abs(g - want).max()
+    _table_properties(tabs, L, H, W)
+    m.free()
+
+
+@pytest.fixture(scope="module")
+def clustered_maps(ctx, npg, orc, clustered, clustered_tree):
+    """GPU maps of the benchmark's path and the oracle's maps over its own tree."""
+    cp, ref = clustered, clustered_tree
+    pos, dirs, w = tf(cp.pos), tf(cp.dirs), t32(cp.w)
+    hier = npg.build_hierarchy(ctx, pos, 8192, 6, max_leaves=65536)
+    L = hier["n_leaves"]
+    assert L == ref["n_leaves"]
+    e, c = npg.splat_histograms(ctx, dirs, w, hier["leaf_off"], 128, 128, perm=hier["perm"])
+    assert npg.sync_status(ctx) == 0
+    rc, e_ref, c_ref = orc.splat(cp.dirs, cp.w, ref["leaf_off"], 128, 128, perm=ref["perm"])
+    assert rc == 0
+    del pos
+    return dict(L=L, e=e, c=c, e_ref=e_ref, c_ref=c_ref, hier=hier, dirs=dirs, w=w,
+                counts=np.diff(ref["leaf_off"].astype(np.int64)))
+
+
+def test_clustered_maps_every_leaf(clustered_maps):
+    cm = clustered_maps
+    e = cm["e"].cpu().numpy().view(np.uint64)
+    bad = np.flatnonzero((e != cm["e_ref"]).reshape(cm["L"], -1).any(1))
+    assert bad.size == 0, f"energy maps differ on {bad.size} leaves, first {bad[:8]}"
+    del e
+    c = cm["c"].cpu().numpy().view(np.uint32)
+    bad = np.flatnonzero((c != cm["c_ref"]).reshape(cm["L"], -1).any(1))
+    assert bad.size == 0, f"count maps differ on {bad.size} leaves, first {bad[:8]}"
+    # integer sums: every photon lands in exactly one bin of its leaf
+    assert np.array_equal(c.reshape(cm["L"], -1).sum(1, dtype=np.int64), cm["counts"])
+
+
+def test_clustered_cdf_every_leaf(ctx, npg, orc, clustered_maps):
+    """Densities = the oracle's normalised maps of the workload, rounded to
+    float32 (both sides read the same float32 values)."""
+    cm = clustered_maps
+    L = cm["L"]
+    s = orc.normalize_input(cm["e_ref"]).astype(np.float32)
+    tabs = npg.build_cdf(ctx, tf(s))
+    assert npg.sync_status(ctx) == 0
+    rc, pdf_r, marg_r, cond_r, tot_r = orc.build_cdf(s.astype(np.float64))
+    assert rc == 0
+    del s
+    ulp = lambda a: np.spacing(np.abs(a).astype(np.float32))
+    for name, got, want in (("pdf", tabs.pdf, pdf_r), ("marg", tabs.marg, marg_r), ("cond", tabs.cond, cond_r)):
+        g = got.cpu().numpy()
+        bad = np.flatnonzero((np.abs(g - want) > ulp(want)).reshape(L, -1).any(1))
+        assert bad.size == 0, f"{name}: {bad.size} leaves beyond one float32 rounding, first {bad[:8]}"
+    assert np.allclose(tabs.total.cpu().numpy(), tot_r, rtol=1e-14, atol=0)
+    zero_rows = int((np.diff(marg_r, axis=1) == 0).sum())
+    print(f"clustered CDF: {L} leaves, {zero_rows} zero-mass rows (uniform conditionals)")
+    assert zero_rows > 0
+
+
+def test_clustered_chain_stratified(ctx, npg, orc, clustered, clustered_maps):
+    cm = clustered_maps
+    L = cm["L"]
+    model = synth.unet_model(1002)
+    m = npg.Model(ctx, model)
+    npg.autotune(ctx, m, 128, 128, "fp32", probe_leaves=1024)
+    s = npg.reconstruct_density(ctx, m, cm["e"], "fp32", count=cm["c"])
+    tabs = npg.build_cdf(ctx, s)
+    assert npg.sync_status(ctx) == 0
+    _table_properties(tabs, L, 128, 128)
+    # 64 leaves stratified by photon count: every L/64-th leaf in count order,
+    # plus the smallest and the largest
+    order = np.argsort(cm["counts"], kind="stable")
+    pick = np.unique(np.concatenate([order[np.linspace(0, L - 1, 64).astype(np.int64)], order[[0, -1]]]))
+    rc, s_ref = orc.net_forward(model, orc.normalize_input(cm["e_ref"][pick]))
+    assert rc == 0
+    rc, pdf_ref, *_ = orc.build_cdf(s_ref)
+    assert rc == 0
+    _check_pdf(tabs.pdf[torch.from_numpy(pick).to(DEV)].cpu().numpy(), pdf_ref,
+               f"clustered, {len(pick)} stratified leaves (counts {cm['counts'][pick].min()}.."
+               f"{cm['counts'][pick].max()})")
+    m.free()

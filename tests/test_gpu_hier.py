@@ -17,9 +17,10 @@ def _pts(seed, n, k=4, sig=0.03):
     return np.where((p >= 0) & (p < 1), p, rng.random((n, 3)).astype(np.float32))
 
 
-def _check(npg, ctx, orc, pos, T, D):
-    rc, ref = orc.build_tree(pos, T, D, max_leaves=max(1, pos.shape[0]))
-    assert rc == 0
+def _check(npg, ctx, orc, pos, T, D, ref=None):
+    if ref is None:
+        rc, ref = orc.build_tree(pos, T, D, max_leaves=max(1, pos.shape[0]))
+        assert rc == 0
     out = npg.build_hierarchy(ctx, torch.from_numpy(pos).to(DEV), T, D, max_leaves=max(1, pos.shape[0]))
     L = out["n_leaves"]
     assert L == ref["n_leaves"]
@@ -75,10 +76,9 @@ def test_hierarchy_errors(ctx, npg):
     assert e.value.code == npg.E_ARG
 
 
-def test_hierarchy_clustered_workload_full_size(ctx, npg, orc):
+def test_hierarchy_clustered_workload_full_size(ctx, npg, orc, clustered, clustered_tree):
     """5e7 photons in 64 Gaussian clusters, split above 8192, depth cap 6."""
-    cp = synth.clustered_photons()
-    ref = _check(npg, ctx, orc, cp.pos, 8192, 6)
+    ref = _check(npg, ctx, orc, clustered.pos, 8192, 6, ref=clustered_tree)
     cnt = np.diff(ref["leaf_off"].astype(np.int64))
     print(f"leaves {ref['n_leaves']}, photons per leaf min {cnt.min()} median {np.median(cnt):.0f} max {cnt.max()}")
     assert 15000 < ref["n_leaves"] < 25000

@@ -440,22 +440,3 @@ def test_chain_single_leaf(ctx, npg, orc):
     e_ = pk[keep] * len(b.q_leaf)
     assert stats.chisquare(obs[keep], e_ * obs[keep].sum() / e_.sum()).pvalue > 1e-4
     m.free()
-
-
-def test_chain_uniform_batch_full_size_sampled(ctx, npg, orc):
-    """1024 leaves x 4096 photons at 64x64 (the uniform-batch workload):
-    histograms checked on every leaf, pdfs on a sample of leaves."""
-    b = synth.uniform_batch()
-    rc, e_ref, c_ref = orc.splat(b.dirs, b.w, b.leaf_off, b.H, b.W)
-    m = npg.Model(ctx, b.model)
-    e, c = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), b.H, b.W)
-    s = npg.reconstruct_density(ctx, m, e, "fp32")
-    tabs = npg.build_cdf(ctx, s)
-    assert npg.sync_status(ctx) == 0
-    assert np.array_equal(u64(e), e_ref) and np.array_equal(u32(c), c_ref)
-    pick = np.array([0, 1, 511, 777, 1023])
-    rc, s_ref = orc.net_forward(b.model, orc.normalize_input(e_ref[pick]))
-    rc, pdf_ref, *_ = orc.build_cdf(s_ref)
-    rel = _rel(tabs.pdf.cpu().numpy()[pick], pdf_ref)
-    assert rel.max() < 1e-5, rel.max()
-    m.free()

@@ -170,3 +170,41 @@ def test_release_with_queued_sampling(ctx, npg, pool):
     assert srv.stats()["table_bytes_free"] == 1 << 30
     srv.close()
     m.free()
+
+
+def test_served_fp32_matches_oracle(ctx, npg, orc, pool):
+    """Two FP32 requests (64x64 and 128x128) served in a burst with others,
+    so they run in merged batches on overlapping slots; their tables against
+    the oracle run on the same photon windows."""
+    dirs, w, n_pool = pool
+    model = synth.unet_model(12, random_bias=True)
+    m = npg.Model(ctx, model)
+    srv = npg.Server(ctx, m, n_slots=2, max_batch_leaves=4096, table_bytes=2 << 30, precision="fp32")
+    blocker = srv.submit_recon(dirs, w, *_request(40, n_pool, 600), 128, 128)
+    reqs = [(_request(41 + i, n_pool, L), H) for i, (L, H) in enumerate([(7, 64), (3, 128), (12, 64), (5, 128)])]
+    tickets = [srv.submit_recon(dirs, w, beg, cnt, H, H) for (beg, cnt), H in reqs]
+    host_dirs, host_w = dirs.cpu().numpy(), w.cpu().numpy().view(np.uint32)
+    for k in (0, 1):
+        (beg, cnt), H = reqs[k]
+        srv.wait(tickets[k])
+        got = srv.copy_tables(tickets[k], _tables(npg, len(beg), H, H))
+        torch.cuda.synchronize()
+        idx = np.concatenate([np.arange(b, b + c) for b, c in zip(beg, cnt)]).astype(np.uint32)
+        off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.uint32)
+        rc, e_ref, _ = orc.splat(host_dirs, host_w, off, H, H, perm=idx)
+        assert rc == 0
+        rc, s_ref = orc.net_forward(model, orc.normalize_input(e_ref))
+        assert rc == 0
+        rc, pdf_ref, marg_ref, cond_ref, tot_ref = orc.build_cdf(s_ref)
+        assert rc == 0
+        rel = np.abs(got.pdf.cpu().numpy().astype(np.float64) - pdf_ref) / pdf_ref
+        print(f"served fp32 request {k} ({len(beg)} leaves, {H}x{H}): max rel pdf err {rel.max():.2e}")
+        assert rel.max() < 1e-5
+        for tab, want in ((got.marg, marg_ref), (got.cond, cond_ref)):
+            g = tab.cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(g - want) <= 1e-5 * np.abs(want) + np.spacing(np.float32(1.0)))
+    for t in tickets + [blocker]:
+        srv.wait(t)
+    assert srv.stats()["merged_requests"] > 0
+    srv.close()
+    m.free()

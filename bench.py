@@ -262,38 +262,128 @@ def sampling_chi2(npg, ctx, tabs, L, H, W, n_leaves=64, per=100_000, seed=4343):
             "ks_uniform_p": float(stats.kstest(pv, "uniform").pvalue)}
 
 
-def cpu_baseline(workload: str, seconds_hint: float = 20.0, input5: bool = False, model5: bytes | None = None):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+def _omp(threads: int | None = None) -> int:
+    """Sets (if given) and returns the OpenMP thread count of the oracle
+    library's runtime (libgomp, loaded with it)."""
+    import ctypes as C
+    gomp = C.CDLL("libgomp.so.1")
+    if threads is not None:
+        gomp.omp_set_num_threads(int(threads))
+    return int(gomp.omp_get_max_threads())
+
+
+def host_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+
+
+def _oracle_chain(orc, b_dirs, b_w, leaf_off, H, W, model, n_queries, seed, perm=None, input5=None):
+    """The oracle's whole step on a set of leaves: splat -> normalise ->
+    network -> CDF -> n_queries guided samples -> pdf of the sampled
+    directions."""
+    if input5 is None:
+        rc, E, P = orc.splat(b_dirs, b_w, leaf_off, H, W, perm=perm)
+        rc, dens = orc.net_forward(model, orc.normalize_input(E))
+    else:
+        rc, E, P = orc.splat(b_dirs, b_w, leaf_off, H, W, perm=perm)
+        Ep, Pp = input5
+        rc, dens = orc.net_forward5(model, orc.input5(E, Ep, P, Pp))
+    assert rc == 0
+    rc, pdf, marg, cond, total = orc.build_cdf(dens)
+    assert rc == 0
+    from paper_2010_01775_amd import synth
+    ql, qu = synth.queries(seed, pdf.shape[0], n_queries)
+    rc, d, p, bins = orc.sample(pdf, marg, cond, ql, qu)
+    rc, pe = orc.eval_pdf(pdf, ql, d.astype(np.float32))
+    return pdf
+
+
+def cpu_baseline_uniform(input5: bool = False, model5: bytes | None = None):
+    """The FP64 oracle, as it stands, on a bounded sample of the uniform batch
+    (about 15 s of CPU work on 16 cores)."""
     from oracle import oracle as orc
     from paper_2010_01775_amd import synth
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    if workload == "uniform":
-        L = max(16, threads * 120)                 # about 15 s of CPU work on 16 cores
-        b = synth.uniform_batch(L=L, n_queries=L * 1024)
-    else:
-        raise ValueError(workload)
+    threads = _omp()
+    L = max(16, threads * 120)
+    b = synth.uniform_batch(L=L, n_queries=L * 1024)
+    prev = None
+    model = b.model
     if input5:
         # iteration t-1 = first half of each leaf's photons, as in the GPU run
         off = b.leaf_off.astype(np.int64)
         half = (off[1:] - off[:-1]) // 2
         perm_p = np.concatenate([np.arange(off[l], off[l] + half[l]) for l in range(L)]).astype(np.uint32)
         off_p = np.concatenate([[0], np.cumsum(half)]).astype(np.uint32)
-        model5 = model5 or synth.unet5_model(1003)
+        model = model5 or synth.unet5_model(1003)
         rc, Ep, Pp = orc.splat(b.dirs, b.w, off_p, b.H, b.W, perm=perm_p)   # resident, not timed
+        prev = (Ep, Pp)
     t0 = time.perf_counter()
-    if input5:
-        rc, E, P = orc.splat(b.dirs, b.w, b.leaf_off, b.H, b.W)
-        rc, dens = orc.net_forward5(model5, orc.input5(E, Ep, P, Pp))
-        rc, pdf, marg, cond, total = orc.build_cdf(dens)
-        ref = dict(pdf=pdf, marg=marg, cond=cond)
-    else:
-        ref = orc.pipeline(b)
-    rc, d, p, bins = orc.sample(ref["pdf"], ref["marg"], ref["cond"], b.q_leaf, b.q_u)
+    _oracle_chain(orc, b.dirs, b.w, b.leaf_off, b.H, b.W, model, L * 1024, 77, input5=prev)
     dt = time.perf_counter() - t0
     return {"value": L / dt, "unit": "leaves/s", "cores": min(threads, L), "kind": "oracle",
             "sample": f"{L} leaves x 4096 photons (64x64, {'five-channel ' if input5 else ''}network, FP64) "
-                      f"end to end plus {L * 1024} samples; {dt:.1f} s"}
+                      f"end to end plus {L * 1024} samples and their pdfs; {dt:.1f} s",
+            "host": host_info()}
+
+
+def cpu_baseline_clustered(cp, model: bytes, L_gpu: int, n_queries: int, subset: int = 512,
+                           subset_1t: int = 16):
+    """The FP64 oracle, as it stands, on the clustered workload: its octree
+    over all photons (timed whole), then the rest of the step on `subset`
+    leaves stratified by photon count (every L/subset-th leaf in count order,
+    so the subset's photons per leaf follow the workload's distribution) with
+    the queries scaled by subset/L; extrapolated to the whole step as
+    t_tree + t_subset * L/subset.  The same with one thread (tree timed whole,
+    the chain on `subset_1t` stratified leaves)."""
+    from oracle import oracle as orc
+
+    def run(n_sub):
+        t0 = time.perf_counter()
+        rc, tree = orc.build_tree(cp.pos, 8192, 6, max_leaves=1 << 20)
+        t_tree = time.perf_counter() - t0
+        assert rc == 0
+        L = tree["n_leaves"]
+        off = tree["leaf_off"].astype(np.int64)
+        cnt = np.diff(off)
+        pick = stratified_leaves(cnt, n_sub)
+        sub_perm = np.concatenate([tree["perm"][off[l]:off[l + 1]] for l in pick])
+        sub_off = np.concatenate([[0], np.cumsum(cnt[pick])]).astype(np.uint32)
+        nq = max(1, int(round(n_queries * n_sub / L)))
+        t1 = time.perf_counter()
+        _oracle_chain(orc, cp.dirs, cp.w, sub_off, 128, 128, model, nq, 78, perm=sub_perm)
+        t_sub = time.perf_counter() - t1
+        t_full = t_tree + t_sub * L / n_sub
+        return L, int(cnt[pick].sum()), nq, t_tree, t_sub, t_full
+
+    threads = _omp()
+    L, ph, nq, t_tree, t_sub, t_full = run(subset)
+    if L != L_gpu:
+        raise RuntimeError(f"oracle tree has {L} leaves, the GPU's {L_gpu}")
+    _omp(1)
+    try:
+        _, ph1, nq1, t_tree1, t_sub1, t_full1 = run(subset_1t)
+    finally:
+        _omp(threads)
+    return {"value": L / t_full, "unit": "leaves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"octree over all 5e7 photons ({t_tree:.1f} s), then splat/normalise/network/CDF/"
+                       f"{nq} samples + pdfs on {subset} leaves stratified by photon count ({ph} photons, "
+                       f"128x128, FP64; {t_sub:.1f} s); extrapolated to all {L} leaves and 1e8 samples as "
+                       f"t_tree + t_subset * {L}/{subset} = {t_full:.1f} s per step"),
+            "subset_leaves_per_s": subset / t_sub,
+            "one_thread": {"value": L / t_full1, "unit": "leaves/s", "cores": 1,
+                           "sample": f"octree ({t_tree1:.1f} s) + {subset_1t} stratified leaves "
+                                     f"({ph1} photons, {nq1} samples; {t_sub1:.1f} s), extrapolated "
+                                     f"to {t_full1:.0f} s per step"},
+            "host": host_info()}
 
 
 def run_serving(args):
@@ -414,44 +504,37 @@ def run_serving(args):
     ctx.close()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "clustered", "serving"])
-    ap.add_argument("--requests", type=int, default=400)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--experts", action="store_true",
-                    help="five U-Nets chosen by leaf photon count ([0,100), [100,500), [500,1000), "
-                         "[1000,5000), [5000,inf)) instead of one")
-    ap.add_argument("--hierarchy", default="octree", choices=["octree", "kdgrid"],
-                    help="clustered workload: the count-threshold octree, or the paper's hierarchical grid "
-                         "(100^3 voxels, valid voxels from bounce points, local KD trees split by photon count "
-                         "> 500 sqrt(2) or normal variance > 0.5, depth <= 8)")
-    ap.add_argument("--paper-net", action="store_true",
-                    help="the paper-style U-Net (16/32/64 channels, ELU, residual links, dilated bottleneck) "
-                         "on the five-channel input (implies --input5)")
-    ap.add_argument("--input5", action="store_true",
-                    help="the five-channel network input (maps and photon counts of iterations t and t-1, "
-                         "valid-bin mask) with a masked first layer; FP32 or BF16")
-    args = ap.parse_args()
-    if args.paper_net:
-        args.input5 = True
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(leaves are independent; sharding them over GPUs is a design, not built); run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
+def stage_bytes(stage: str, n_photons: int, L: int, H: int, W: int, nq: int) -> float:
+    """Algorithmic HBM bytes of one stage: what the step must read and write
+    once (no sort passes, no re-reads).
+      hier   positions 12 B read + permutation 4 B written per photon, leaf
+             offsets 4 B per leaf (leaf_of is not requested by the step)
+      splat  direction 12 B + weight 4 B read per photon; energy 8 B + count
+             4 B written per bin
+      cdf    density 4 B read; pdf 4 B, conditional 4 (W+1)/W B written per
+             bin; marginal 4 (H+1) B and total 8 B per leaf
+      sample query 12 B read, direction 12 B + pdf 4 B + bin 4 B written;
+             the tables (pdf, conditional, marginal) read once
+      eval   leaf 4 B + direction 12 B read, pdf 4 B written per query; the
+             pdf table read once"""
+    bins = float(L) * H * W
+    tab = bins * 4 + L * H * (W + 1) * 4.0 + L * (H + 1) * 4.0
+    return {"hier": n_photons * 16.0 + (L + 1) * 4.0,
+            "splat": n_photons * 16.0 + bins * 12.0,
+            "cdf": bins * 4.0 + tab + L * 8.0,
+            "sample": nq * 32.0 + tab,
+            "eval": nq * 20.0 + bins * 4.0}[stage]
 
-    if args.workload == "serving":
-        return run_serving(args)
-    if args.input5 and (args.experts or args.precision == "fp8"):
-        print("--input5 runs one five-channel U-Net in FP32 or BF16", file=sys.stderr)
-        sys.exit(2)
 
+def stratified_leaves(counts: np.ndarray, n: int) -> np.ndarray:
+    """n leaves spread evenly over the photon-count order (sorted ids)."""
+    order = np.argsort(counts, kind="stable")
+    return np.sort(order[np.linspace(0, len(counts) - 1, min(n, len(counts))).astype(np.int64)])
+
+
+def run_path(args, workload: str, with_baseline: bool = True) -> dict:
+    """Times `args.steps` steps of the hot path on one workload; returns the
+    JSON record."""
     import torch
 
     from paper_2010_01775_amd import npg, synth
@@ -462,17 +545,20 @@ def main():
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
 
     ctx = npg.Context(0)
-    if args.workload == "uniform":
+    cp = None
+    if workload == "uniform":
         b = synth.uniform_batch()
         H, W, L = b.H, b.W, b.L
         dirs, w, off = f32(b.dirs), i32(b.w), i32(b.leaf_off)
         q_leaf, q_u = i32(b.q_leaf), f32(b.q_u)
         model_bytes = b.model
         pos = None
+        n_photons = b.dirs.shape[0]
         desc = ("uniform batch: 1024 leaves x 4096 photons (vMF mixtures), 64x64 equal-area maps, "
                 "U-Net 16/32/64/128, 1048576 guided samples")
     else:
         cp = synth.clustered_photons()
+        n_photons = cp.pos.shape[0]
         # the paper's grid yields ~20x more (and smaller) leaves than the
         # octree: 64x64 maps keep their tables within HBM
         H = W = 64 if args.hierarchy == "kdgrid" else 128
@@ -491,6 +577,7 @@ def main():
         L = out["n_leaves"]
         ql, qu = synth.queries(1102, L, 100_000_000)
         q_leaf, q_u = i32(ql), f32(qu)
+        del ql, qu
         desc = (f"clustered: 5e7 photons in 64 Gaussian clusters, {hier_desc} "
                 f"({L} leaves), {H}x{W} maps, U-Net 16/32/64/128, 1e8 guided samples")
     if args.input5:
@@ -593,16 +680,33 @@ def main():
         npg.eval_pdf(ctx, tabs, q_leaf, sd[0], out=pe)
         mark("eval", 1)
 
+    calib = None
     if args.precision == "fp8":
-        # static e4m3 scales from a strided 1/16 subsample of the workload's own
-        # maps (at most 256 leaves), computed once before timing
-        if pos is not None:
-            lo_ = out["leaf_off"][:L + 1]
-            npg.splat_histograms(ctx, dirs, w, lo_, H, W, perm=out["perm"], energy=energy, count=count)
+        # static e4m3 scales from a separate calibration set of the same
+        # workload drawn from seed + 100 (256 leaves; for the clustered
+        # workload stratified by photon count over its own octree), set once
+        # before timing
+        if workload == "uniform":
+            cb = synth.uniform_batch(seed=1101, L=256, n_queries=1, model=b"")
+            ce, _ = npg.splat_histograms(ctx, f32(cb.dirs), i32(cb.w), i32(cb.leaf_off), H, W, want_count=False)
+            calib = "256 leaves of the uniform batch drawn from seed 1101"
         else:
-            npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
+            ccp = synth.clustered_photons(seed=1103)
+            cpos = f32(ccp.pos)
+            chier = npg.build_hierarchy(ctx, cpos, 8192, 6, max_leaves=65536)
+            coff = chier["leaf_off"].cpu().numpy().view(np.uint32).astype(np.int64)
+            cperm = chier["perm"].cpu().numpy().view(np.uint32)
+            pick = stratified_leaves(np.diff(coff), 256)
+            sel = np.concatenate([cperm[coff[l]:coff[l + 1]] for l in pick])
+            soff = np.concatenate([[0], np.cumsum(np.diff(coff)[pick])]).astype(np.uint32)
+            ce, _ = npg.splat_histograms(ctx, f32(ccp.dirs[sel]), i32(ccp.w[sel]), i32(soff), H, W,
+                                         want_count=False)
+            calib = (f"256 leaves stratified by photon count from the clustered workload drawn from seed 1103 "
+                     f"(its own octree, {chier['n_leaves']} leaves)")
+            del ccp, cpos, chier, sel
         for m in experts or [model]:
-            m.calibrate_fp8(energy[::16][:256].contiguous())
+            m.calibrate_fp8(ce)
+        del ce
     tune = None
     if not args.no_autotune:
         # per-layer pixel tiles and leaf-chunk size, chosen once before timing
@@ -644,14 +748,17 @@ def main():
                 te.append(e1.elapsed_time(e2))
         if npg.sync_status(ctx) != 0:
             raise RuntimeError("data-dependent error in the MIS calls")
-        return {"mis_samples_per_s": nq / (np.mean(ts) / 1e3), "mis_eval_per_s": nq / (np.mean(te) / 1e3),
+        res_ = {"mis_samples_per_s": nq / (np.mean(ts) / 1e3), "mis_eval_per_s": nq / (np.mean(te) / 1e3),
                 "bsdf_fraction": float(outs[2].float().mean()), "mean_alpha": float(alpha.mean())}
+        del normal, u3, outs, pe_m
+        return res_
 
     per_step, stage_ms = [], {s: [] for s in stages}
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     s0 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    ctx.conv_flops(reset=True)
     t_start.record(stream)
     for k in range(args.steps):
         s0.record(stream)
@@ -660,12 +767,13 @@ def main():
         per_step.append(s0.elapsed_time(ev["eval"][1]))
         for s in stages:
             stage_ms[s].append(ev[s][0].elapsed_time(ev[s][1]))
-        print(f"step {k}: {per_step[-1]:.2f} ms", file=sys.stderr, flush=True)
+        print(f"{workload} step {k}: {per_step[-1]:.2f} ms", file=sys.stderr, flush=True)
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     if npg.sync_status(ctx) != 0:
         raise RuntimeError("data-dependent error during the timed steps")
+    mat_flops, vec_flops = (f / args.steps for f in ctx.conv_flops(reset=True))
 
     avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
     mis = mis_rates()
@@ -699,19 +807,27 @@ def main():
     else:
         peak, peak_name = PEAK["bf16_mfma_TFLOPs"], "BF16 MFMA"
     achieved = flops / recon_s / 1e12
-    # what the matrix cores execute (FP32 mode: phase-merged decoder taps)
-    issued = flops - (phase_saved_flops_per_leaf(model_bytes, H, W) * L if args.precision == "fp32" else 0.0)
     esz = {"fp32": 8, "bf16": 2, "fp8": 1}[args.precision]
     bytes_alg = model_bytes_per_leaf(model_bytes, H, W, esz, 24.0 if args.input5 else 8.0) * L
     ridge = peak * 1e12 / (PEAK["hbm_GBps"] * 1e9)
-    hbm_bound = flops / bytes_alg < ridge        # arithmetic intensity below the ridge point
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{workload}_{args.precision}.json")
     src_sha = sha_of(os.path.join(ROOT, "paper_2010_01775_amd", "csrc", "net.hip"))
     if os.path.exists(tfile) and not args.experts and not args.input5:
         t = json.load(open(tfile))
         if t.get("source_sha") == src_sha:
             traffic = t.get("bytes_per_launch")
+
+    stage_roof = {}
+    for s_ in stages:
+        if s_ == "recon":
+            continue
+        by = stage_bytes(s_, n_photons, L, H, W, nq)
+        gbps = by / (avg[s_] / 1e3) / 1e9
+        stage_roof[s_] = {"ms": avg[s_], "algorithmic_bytes": by, "GBps": gbps, "frac_hbm": gbps / PEAK["hbm_GBps"]}
+    stage_roof["recon"] = {"ms": avg["recon"], "algorithmic_flops": flops, "TFLOPs": achieved,
+                           "frac_mfma": achieved / peak, "algorithmic_bytes": bytes_alg,
+                           "frac_hbm": bytes_alg / recon_s / 1e9 / PEAK["hbm_GBps"]}
 
     res = {
         "metric": "leaf densities reconstructed/sec + guided samples/sec; p50/p99 batch latency",
@@ -726,11 +842,13 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f64", "bf16": "bf16", "fp8": "fp8-e4m3"}[args.precision],
         "data": "synthetic (seeded vMF-mixture photons, He-init weights)",
-        "config": {"workload": desc, "leaves": L, "H": H, "W": W, "queries": nq, "autotuned": tune,
+        "config": {"workload": desc, "leaves": L, "photons": n_photons, "H": H, "W": W, "queries": nq,
+                   "autotuned": tune,
                    "precision": {"fp32": "fp32 weights, f64 activations and conv accumulation",
                                  "bf16": "bf16 conv, f32 accumulation",
                                  "fp8": "fp8 e4m3 conv (static per-layer activation scales, "
                                         "per-output-channel weight scales), f32 accumulation"}[args.precision]}
+                  | ({"fp8_calibration": calib} if calib else {})
                   | ({"experts": "5 U-Nets by leaf photon count [0,100) [100,500) [500,1000) [1000,5000) "
                                  "[5000,inf)", "expert_leaves": expert_leaves} if experts else {})
                   | ({"input": "5 channels: maps and photon counts of iterations t and t-1 (t-1: first half of "
@@ -744,29 +862,93 @@ def main():
         "p50_ms": float(np.percentile(per_step, 50)),
         "p99_ms": float(np.percentile(per_step, 99)),
         "stage_ms": avg,
-        "roofline": ({"bound": "hbm", "achieved": bytes_alg / recon_s / 1e9, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-                      "frac": bytes_alg / recon_s / 1e9 / PEAK["hbm_GBps"], "traffic": traffic,
-                      "mfma_TFLOPs": achieved, "mfma_peak": peak, "mfma_frac": achieved / peak}
-                     if hbm_bound else
-                     {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                      "frac": achieved / peak, "traffic": traffic, "hbm_GBps": bytes_alg / recon_s / 1e9}) | {
+        "stage_roofline": stage_roof,
+        # the dominant stage: the network (a matrix-core contraction in every
+        # precision; its HBM side beside it)
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": f"reconstruct_density (implicit-GEMM conv stack), {peak_name}",
-                     "flops_per_launch": flops, "bytes_per_launch": bytes_alg,
+                     "frac_is": "algorithmic FLOPs (direct 3x3 convolutions) per second over the peak",
+                     "flops_per_launch": flops, "avg_launch_ms": avg["recon"],
+                     "issued_flops_per_launch": mat_flops, "issued_TFLOPs": mat_flops / recon_s / 1e12,
+                     "issued_frac": mat_flops / recon_s / 1e12 / peak,
+                     "issued_is": "matrix-core FLOPs of the layers as launched (phase-merged decoder taps in "
+                                  "FP32 mode) per second over the peak: the matrix-core utilisation",
+                     "vector_flops_per_launch": vec_flops,
+                     "bytes_per_launch": bytes_alg, "hbm_GBps": bytes_alg / recon_s / 1e9,
+                     "hbm_frac": bytes_alg / recon_s / 1e9 / PEAK["hbm_GBps"],
                      "intensity_flop_per_byte": flops / bytes_alg, "ridge_flop_per_byte": ridge,
-                     "issued_flops_per_launch": issued, "issued_TFLOPs": issued / recon_s / 1e12,
-                     "issued_frac": issued / recon_s / 1e12 / peak,
-                     "avg_launch_ms": avg["recon"], "source_sha": src_sha},
+                     "source_sha": src_sha},
     }
     res["sampling_chi2"] = sampling_chi2(npg, ctx, tabs, L, H, W)
     if args.precision != "fp32":
         res["precision_vs_fp32"] = pdf_errors_vs_fp32(npg, ctx, model, energy, args.precision,
                                                       (count, *prev) if prev is not None else None)
-    if not args.no_cpu_baseline and args.workload == "uniform":
-        res["cpu_baseline"] = cpu_baseline(args.workload, input5=args.input5,
-                                           model5=model_bytes if args.input5 else None)
-    print(json.dumps(res))
-    model.free()
+    del sd, pe, q_leaf, q_u, dirs, w, energy, count, dens, tabs, hier_out, pos, prev
+    for m in (experts or [model]):
+        m.free()
     ctx.close()
+    torch.cuda.empty_cache()
+    if with_baseline and not args.no_cpu_baseline:
+        if workload == "uniform":
+            res["cpu_baseline"] = cpu_baseline_uniform(input5=args.input5,
+                                                       model5=model_bytes if args.input5 else None)
+        elif args.hierarchy == "octree" and not args.experts and not args.input5:
+            res["cpu_baseline"] = cpu_baseline_clustered(cp, model_bytes, L, nq)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered", choices=["uniform", "clustered", "serving"],
+                    help="clustered (default): 5e7 photons, octree, 128x128 maps, 1e8 samples; uniform: 1024 "
+                         "leaves x 4096 photons, 64x64 maps, 2^20 samples; serving: the request stream")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="clustered workload: skip the uniform batch that the default run times after it")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--experts", action="store_true",
+                    help="five U-Nets chosen by leaf photon count ([0,100), [100,500), [500,1000), "
+                         "[1000,5000), [5000,inf)) instead of one")
+    ap.add_argument("--hierarchy", default="octree", choices=["octree", "kdgrid"],
+                    help="clustered workload: the count-threshold octree, or the paper's hierarchical grid "
+                         "(100^3 voxels, valid voxels from bounce points, local KD trees split by photon count "
+                         "> 500 sqrt(2) or normal variance > 0.5, depth <= 8)")
+    ap.add_argument("--paper-net", action="store_true",
+                    help="the paper-style U-Net (16/32/64 channels, ELU, residual links, dilated bottleneck) "
+                         "on the five-channel input (implies --input5)")
+    ap.add_argument("--input5", action="store_true",
+                    help="the five-channel network input (maps and photon counts of iterations t and t-1, "
+                         "valid-bin mask) with a masked first layer; FP32 or BF16")
+    args = ap.parse_args()
+    if args.paper_net:
+        args.input5 = True
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(leaves are independent; sharding them over GPUs is a design, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "serving":
+        return run_serving(args)
+    if args.input5 and (args.experts or args.precision == "fp8"):
+        print("--input5 runs one five-channel U-Net in FP32 or BF16", file=sys.stderr)
+        sys.exit(2)
+    res = run_path(args, args.workload)
+    if args.workload == "clustered" and not args.no_extra and args.hierarchy == "octree" and not args.experts \
+            and not args.input5:
+        # the uniform batch, timed the same way, as an extra key
+        u = run_path(args, "uniform", with_baseline=not args.no_cpu_baseline)
+        res["uniform_batch"] = {k: u[k] for k in ("value", "unit", "ms_per_step", "samples_per_s", "eval_per_s",
+                                                  "p50_ms", "p99_ms", "stage_ms", "stage_roofline", "roofline",
+                                                  "config", "sampling_chi2", "precision_vs_fp32", "cpu_baseline")
+                                if k in u}
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

@@ -104,6 +104,16 @@ int npg_sync_status(npg_ctx *ctx, void *stream);
  * the high-water mark. */
 void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak);
 
+/* FLOPs of the network convolutions launched with ctx since the last reset,
+ * as each layer was launched (2 per multiply-add; host-side count):
+ * *matrix those issued on the matrix cores (a nearest-upsampled input taken
+ * in the phase-merged form counts 4 taps per upsampled channel instead of
+ * 9), *vector those of the first layers, 1x1 heads and direct convolutions
+ * on the vector ALUs (a first layer recomputed inside the next layer's patch
+ * staging counts every patch pixel).  reset != 0 zeroes the counts after
+ * reading them.  Either pointer may be NULL. */
+void npg_conv_flops(npg_ctx *ctx, double *matrix, double *vector, int reset);
+
 /* Context tunables (value >= 0):
  *   "graphs"       1: npg_reconstruct_fused captures its launches into a HIP
  *                  graph on the second call with the same arguments on a

@@ -132,6 +132,12 @@ void npg_memory_usage(const npg_ctx *ctx, uint64_t *current, uint64_t *peak) {
   if (peak) *peak = ctx ? ctx->peak : 0;
 }
 
+void npg_conv_flops(npg_ctx *ctx, double *matrix, double *vector, int reset) {
+  if (matrix) *matrix = ctx ? ctx->conv_flops[0] : 0.0;
+  if (vector) *vector = ctx ? ctx->conv_flops[1] : 0.0;
+  if (ctx && reset) ctx->conv_flops[0] = ctx->conv_flops[1] = 0.0;
+}
+
 int npg_sync_status(npg_ctx *ctx, void *stream) {
   if (!ctx) return NPG_E_ARG;
   int rc = npg_set_device(ctx);

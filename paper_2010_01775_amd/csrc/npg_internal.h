@@ -32,6 +32,9 @@ struct npg_ctx {
   };
   std::vector<Graph> graphs;                      // captured fused calls
   std::set<std::string> graph_seen;
+  // FLOPs of the network convolutions as launched since the last reset
+  // (npg_conv_flops): [0] issued on the matrix cores, [1] on the vector ALUs
+  double conv_flops[2] = {0.0, 0.0};
   long long opt(const char *name, long long def) const {
     auto it = opts.find(name);
     return it == opts.end() ? def : it->second;

@@ -22,7 +22,7 @@ FP32, BF16, FP8 = 0, 1, 2
 PRECISION = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
 
 SYMBOLS = [
-    "npg_create", "npg_destroy", "npg_last_error", "npg_sync_status", "npg_memory_usage",
+    "npg_create", "npg_destroy", "npg_last_error", "npg_sync_status", "npg_memory_usage", "npg_conv_flops",
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
     "npg_build_hierarchy", "npg_mark_valid", "npg_build_kdgrid", "npg_locate",
     "npg_splat_histograms", "npg_normalize_input",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "npg_last_error": (C.c_char_p, [P]),
         "npg_sync_status": (I, [P, P]),
         "npg_memory_usage": (None, [P, C.POINTER(U64), C.POINTER(U64)]),
+        "npg_conv_flops": (None, [P, C.POINTER(C.c_double), C.POINTER(C.c_double), I]),
         "npg_model_load": (I, [P, P, SZ, C.POINTER(P)]),
         "npg_model_free": (None, [P]),
         "npg_model_calibrate_fp8": (I, [P, P, P, U32, I, I, P]),
@@ -187,6 +188,13 @@ class Context:
         cur, peak = C.c_uint64(), C.c_uint64()
         self.lib.npg_memory_usage(self.h, C.byref(cur), C.byref(peak))
         return cur.value, peak.value
+
+    def conv_flops(self, reset: bool = False):
+        """(matrix-core, vector-ALU) FLOPs of the network convolutions launched
+        since the last reset, as each layer was launched."""
+        mat, vec = C.c_double(), C.c_double()
+        self.lib.npg_conv_flops(self.h, C.byref(mat), C.byref(vec), int(bool(reset)))
+        return mat.value, vec.value
 
 
 def sync_status(ctx: Context, stream=None) -> int:

@@ -72,3 +72,25 @@ def test_paper_net_bytes_per_leaf():
             + 2 * 16 * px * e + 16 * px * e
             + 16 * px * e + 4 * px)                    # head
     assert bench.model_bytes_per_leaf(synth.paper_unet_model(1), 64, 64, e, 24.0) == want
+
+
+def test_stage_bytes_per_unit():
+    """Per-stage algorithmic bytes: the uniform batch's splat moves 67.1 MB of
+    photons and 50.3 MB of maps; a query of the sampler reads 12 B and writes
+    20 B; tables are read once."""
+    N, L, H, W, nq = 4096 * 1024, 1024, 64, 64, 1 << 20
+    assert bench.stage_bytes("splat", N, L, H, W, nq) == 16 * N + 12 * L * H * W == 117_440_512
+    tab = L * H * W * 4 + L * H * (W + 1) * 4 + L * (H + 1) * 4
+    assert bench.stage_bytes("sample", N, L, H, W, nq) == 32 * nq + tab
+    assert bench.stage_bytes("eval", N, L, H, W, nq) == 20 * nq + 4 * L * H * W
+    assert bench.stage_bytes("cdf", N, L, H, W, nq) == 4 * L * H * W + tab + 8 * L
+    assert bench.stage_bytes("hier", 50_000_000, 18595, 128, 128, 1) == 16 * 50_000_000 + 4 * 18596
+
+
+def test_stratified_leaves():
+    import numpy as np
+    counts = np.array([5, 1, 9, 3, 7, 2, 8, 4, 6, 0])
+    pick = bench.stratified_leaves(counts, 4)
+    assert list(pick) == sorted(pick) and len(set(pick)) == 4
+    assert counts[pick].min() == 0 and counts[pick].max() == 9       # both ends of the count order
+    assert list(bench.stratified_leaves(counts, 20)) == list(range(10))

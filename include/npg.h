@@ -321,6 +321,24 @@ int npg_reconstruct_density(npg_ctx *ctx, const npg_model *model, const uint64_t
                             const uint32_t *count_dev, uint32_t L, int H, int W,
                             npg_precision precision, float *density_dev, void *stream);
 
+/* npg_reconstruct_density without allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same network, arguments, outputs and
+ * errors as npg_reconstruct_density (one-channel models), but its
+ * activations and per-leaf totals live in a static device array of the
+ * library (256 MiB, of which 255 MiB are used; each GPU the library runs on
+ * holds its own copy until the process ends), and the call allocates
+ * nothing.  The leaves run in chunks that fit the array (the tuned or
+ * "chunk_leaves" chunk, made smaller where needed), so L is unbounded;
+ * results equal npg_reconstruct_density's bit for bit.  A map size whose
+ * single leaf does not fit the array returns NPG_E_BUDGET.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different contexts of that GPU) race and must
+ * be serialised by the caller. */
+int npg_reconstruct_density_noalloc(npg_ctx *ctx, const npg_model *model, const uint64_t *energy_dev,
+                                    uint32_t L, int H, int W, npg_precision precision, float *density_dev,
+                                    void *stream);
+
 /* The network on the paper's five input channels (Sec. 6): the raw maps
  * of iterations t and t-1 (x = H*W*E/sum(E), 0 for an empty map), their
  * photon-count maps normalised the same way (each value rounded to

@@ -96,6 +96,7 @@ int npg_create(npg_ctx **out, int device, uint64_t hbm_budget_bytes) {
         rc = NPG_E_HIP;
     }
   }
+  if (!rc) rc = npg_noalloc_setup(ctx);
   if (rc) {
     npg_destroy(ctx);
     return rc;

@@ -36,6 +36,7 @@
 #include <type_traits>
 #include <cmath>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "npg_internal.h"
@@ -2300,6 +2301,85 @@ extern "C" int npg_reconstruct_density(npg_ctx *ctx, const npg_model *m, const u
   if (rc) return rc;
   return run_density(ctx, m, precision, energy_dev, L, H, W, density_dev, static_cast<hipStream_t>(stream),
                      nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// The network without allocation (npg_reconstruct_density_noalloc): the same
+// chunked network over a file-scope device array instead of the context's
+// scratch arena.  Each GPU the library runs on holds its own copy of the
+// array from the library's load until the process ends.  The host-side name
+// `scratch` is a stand-in, not a device address: host code uses only the
+// address hipGetSymbolAddress returns on each device.
+constexpr size_t NPG_NOALLOC_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[NPG_NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+int npg_noalloc_setup(npg_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= NOALLOC_MAX_DEVICES)
+    return npg_fail(ctx, NPG_E_ARG, "device %d: at most %d devices", ctx->device, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[ctx->device]) {
+    int rc = npg_set_device(ctx);
+    if (rc) return rc;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return npg_fail(ctx, NPG_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_noalloc_ptr[ctx->device] = p;
+  }
+  ctx->noalloc_scratch = g_noalloc_ptr[ctx->device];
+  return NPG_OK;
+}
+
+extern "C" int npg_reconstruct_density_noalloc(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,
+                                               uint32_t L, int H, int W, npg_precision precision,
+                                               float *density_dev, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  int rc = check_net_args(ctx, m, H, W, precision);
+  if (rc) return rc;
+  if (L == 0) return NPG_OK;
+  if (!energy_dev || !density_dev) return npg_fail(ctx, NPG_E_ARG, "reconstruct_noalloc: null pointer");
+  if (!ctx->noalloc_scratch) return npg_fail(ctx, NPG_E_HIP, "reconstruct_noalloc: scratch address not set up");
+  rc = npg_set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Runner R = make_runner(ctx, m, precision, s);
+  std::vector<int> caps;
+  apply_tune(ctx, R, H, W, &caps);
+  const size_t HW = (size_t)H * W;
+  const NetPlan plan = plan_net(m, H, W, R.esz);
+  // per chunk: the leaves' totals, then the activation buffers
+  // (the last MiB of the array stays unused, as the arena keeps a margin
+  // after its buffers)
+  constexpr size_t usable = NPG_NOALLOC_BYTES - ((size_t)1 << 20);
+  auto bytes_for = [&](size_t c) { return npg_align(c * sizeof(double)) + net_bufs_bytes(plan, c, R.esz); };
+  if (bytes_for(1) > usable)
+    return npg_fail(ctx, NPG_E_BUDGET,
+                    "reconstruct_noalloc: one %dx%d leaf needs %zu bytes of scratch, the static array offers %zu",
+                    H, W, bytes_for(1), usable);
+  size_t chunk = 1024;
+  auto it = ctx->tune.find(tune_key(m, precision, H, W));
+  if (it != ctx->tune.end() && !it->second.empty() && it->second[0] > 0) chunk = (size_t)it->second[0];
+  const long long o = ctx->opt("chunk_leaves", 0);
+  if (o > 0) chunk = (size_t)o;
+  chunk = std::min<size_t>(chunk, L);
+  while (chunk > 1 && bytes_for(chunk) > usable) chunk = std::max<size_t>(1, chunk * 7 / 8);
+  Carver cv(ctx->noalloc_scratch);
+  double *tot = cv.take<double>(chunk);
+  const NetBufs B = carve_net(cv, plan, chunk, R.esz);
+  for (size_t l0 = 0; l0 < L; l0 += chunk) {
+    const int Lc = (int)std::min<size_t>(chunk, L - l0);
+    NPG_HIP_CHECK(ctx, launch_leaf_scale(energy_dev + l0 * HW, (uint32_t)Lc, (int)HW, tot, s));
+    const Src in{SRC_ENERGY, energy_dev + l0 * HW, nullptr, tot, 0, 0};
+    rc = net_chunk(R, in, Lc, H, W, density_dev + l0 * HW, B);
+    if (rc) return rc;
+  }
+  return NPG_OK;
 }
 
 extern "C" int npg_reconstruct_density5(npg_ctx *ctx, const npg_model *m, const uint64_t *energy_dev,

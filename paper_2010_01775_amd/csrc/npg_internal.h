@@ -35,6 +35,9 @@ struct npg_ctx {
   // FLOPs of the network convolutions as launched since the last reset
   // (npg_conv_flops): [0] issued on the matrix cores, [1] on the vector ALUs
   double conv_flops[2] = {0.0, 0.0};
+  // device address of the library's static network scratch array on this
+  // context's device (npg_reconstruct_density_noalloc), set by npg_create
+  void *noalloc_scratch = nullptr;
   long long opt(const char *name, long long def) const {
     auto it = opts.find(name);
     return it == opts.end() ? def : it->second;
@@ -58,6 +61,10 @@ int npg_scratch(npg_ctx *ctx, size_t bytes, hipStream_t stream, void **out);
 int npg_device_alloc(npg_ctx *ctx, size_t bytes, void **out);
 void npg_device_free(npg_ctx *ctx, void *p, size_t bytes);
 int npg_set_device(npg_ctx *ctx);
+// Looks up (once per device, with ctx's device current) the device address
+// of the static scratch array of npg_reconstruct_density_noalloc and keeps it
+// in ctx->noalloc_scratch.
+int npg_noalloc_setup(npg_ctx *ctx);
 
 __host__ __device__ static inline size_t npg_align(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 

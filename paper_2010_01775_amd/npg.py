@@ -26,7 +26,7 @@ SYMBOLS = [
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
     "npg_build_hierarchy", "npg_mark_valid", "npg_build_kdgrid", "npg_locate",
     "npg_splat_histograms", "npg_normalize_input",
-    "npg_reconstruct_density", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
+    "npg_reconstruct_density", "npg_reconstruct_density_noalloc", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
     "npg_mis_alpha", "npg_sample_mis", "npg_eval_pdf_mis", "npg_reconstruct_density5",
     "npg_bin_boundaries", "npg_set_option", "npg_reconstruct_fused", "npg_autotune", "npg_tune_table",
     "npg_serve_create", "npg_serve_destroy", "npg_serve_submit_recon", "npg_serve_submit_sample",
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "npg_splat_histograms": (I, [P, P, P, P, P, U32, I, I, P, P, I, P]),
         "npg_normalize_input": (I, [P, P, U32, I, I, P, P]),
         "npg_reconstruct_density": (I, [P, P, P, P, U32, I, I, I, P, P]),
+        "npg_reconstruct_density_noalloc": (I, [P, P, P, U32, I, I, I, P, P]),
         "npg_reconstruct_experts": (I, [P, P, I, P, P, P, U32, I, I, I, P, P, P]),
         "npg_reconstruct_density5": (I, [P, P, P, P, P, P, U32, I, I, I, P, P]),
         "npg_build_cdf": (I, [P, P, U32, I, I, P, P, P, P, P]),
@@ -370,6 +371,18 @@ def reconstruct_density(ctx: Context, model: Model, energy, precision="fp32", co
     p = PRECISION[precision] if isinstance(precision, str) else int(precision)
     ctx.check(ctx.lib.npg_reconstruct_density(ctx.h, model.h, _ptr(energy), _ptr(count), L, H, W, p,
                                               _ptr(density), _stream(stream)))
+    return density
+
+
+def reconstruct_density_noalloc(ctx: Context, model: Model, energy, precision="fp32", density=None, stream=None):
+    """reconstruct_density through the library's static scratch array: the
+    call allocates no device memory (pass `density` to keep it so)."""
+    L, H, W = energy.shape
+    if density is None:
+        density = torch.empty((L, H, W), dtype=torch.float32, device=energy.device)
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.lib.npg_reconstruct_density_noalloc(ctx.h, model.h, _ptr(energy), L, H, W, p, _ptr(density),
+                                                      _stream(stream)))
     return density
 
 

@@ -898,6 +898,21 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
     return res
 
 
+def calibrate_counters(nbytes: int = 1 << 30, reps: int = 8):
+    """Copies of known size, for scaling HBM byte counters (run under
+    rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE): each dispatch reads and
+    writes exactly 2^30 bytes of a buffer 4x larger than the last-level
+    cache, so a counter's bytes per dispatch over 2^30 is its scale."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": nbytes, "dispatches": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -925,7 +940,11 @@ def main():
     ap.add_argument("--input5", action="store_true",
                     help="the five-channel network input (maps and photon counts of iterations t and t-1, "
                          "valid-bin mask) with a masked first layer; FP32 or BF16")
+    ap.add_argument("--calibrate-counters", action="store_true",
+                    help="only run 8 device copies of 1 GiB (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    if args.calibrate_counters:
+        return calibrate_counters()
     if args.paper_net:
         args.input5 = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -2368,7 +2368,8 @@ extern "C" int npg_reconstruct_density_noalloc(npg_ctx *ctx, const npg_model *m,
   const long long o = ctx->opt("chunk_leaves", 0);
   if (o > 0) chunk = (size_t)o;
   chunk = std::min<size_t>(chunk, L);
-  while (chunk > 1 && bytes_for(chunk) > usable) chunk = std::max<size_t>(1, chunk * 7 / 8);
+  chunk = std::min<size_t>(chunk, usable / bytes_for(1) + 1);
+  while (chunk > 1 && bytes_for(chunk) > usable) --chunk;
   Carver cv(ctx->noalloc_scratch);
   double *tot = cv.take<double>(chunk);
   const NetBufs B = carve_net(cv, plan, chunk, R.esz);

@@ -10,20 +10,38 @@
 namespace {
 
 // largest i in [0, n-1] with t[i] <= u, for t non-decreasing with
-// t[0] <= u < t[n]; *tl = t[i], *th = t[i+1].  The eight entries around the
-// one a linear table would hold u at are loaded together (one memory round
-// trip) and settle the search when they bracket u; otherwise the search
-// gallops outwards from the window's side and bisects the bracket.
+// t[0] <= u < t[n]; *tl = t[i], *th = t[i+1].  Eight entries around the one
+// a linear table would hold u at are loaded in one memory round trip and
+// settle the search when they bracket u; otherwise the search gallops
+// outwards from the window's side and bisects the bracket.  Rows of at least
+// 16 entries load a 16-byte aligned window as two 16-byte pieces (the
+// window starts 3 to 6 entries below the guess and is moved by 4 entries to
+// stay inside the row), shorter rows eight clamped single entries: a load
+// instruction whose 64 lanes read 64 different table lines costs the same
+// whatever its width, so the wide loads quarter that cost.
 __device__ __forceinline__ int last_le(const float *__restrict__ t, int n, float u, float *tl, float *th) {
   int g = (int)(u * (float)n);
   g = g < n - 1 ? g : n - 1;
-  int a = g - 3;
-  a = a > n - 7 ? n - 7 : a;
-  a = a < 0 ? 0 : a;
-  const int m = n - a < 7 ? n - a : 7;  // the window is t[a .. a+m], m >= 1
+  int a, m;
   float w[8];
+  if (n >= 15) {
+    const uintptr_t t0 = reinterpret_cast<uintptr_t>(t);
+    a = (int)(((intptr_t)((t0 + 4 * (uintptr_t)(g - 3)) & ~(uintptr_t)15) - (intptr_t)t0) / 4);
+    a = a < 0 ? a + 4 : a;
+    a = a < 0 ? a + 4 : a;
+    a = a + 7 > n ? a - 4 : a;
+    m = 7;
+    const float4 *p = reinterpret_cast<const float4 *>(t + a);
+    const float4 v0 = p[0], v1 = p[1];
+    w[0] = v0.x, w[1] = v0.y, w[2] = v0.z, w[3] = v0.w, w[4] = v1.x, w[5] = v1.y, w[6] = v1.z, w[7] = v1.w;
+  } else {
+    a = g - 3;
+    a = a > n - 7 ? n - 7 : a;
+    a = a < 0 ? 0 : a;
+    m = n - a < 7 ? n - a : 7;  // the window is t[a .. a+m], m >= 1
 #pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = t[a + (k < m ? k : m)];
+    for (int k = 0; k < 8; ++k) w[k] = t[a + (k < m ? k : m)];
+  }
   if (w[0] <= u && u < w[m]) {
     int c = 0;  // entries t[a+1 .. a+m-1] that are <= u
 #pragma unroll
@@ -107,32 +125,48 @@ __device__ __forceinline__ void guided_sample(const float *__restrict__ pdf, con
   *bin = (uint32_t)(i * W + j);
 }
 
+// One query per lane, 256 consecutive queries per workgroup and iteration.
+// The block's directions (3 KiB, contiguous in dir) are staged in LDS and
+// written as 16-byte pieces; pdf and bin are written one lane each
+// (coalesced 4-byte pieces).
 __global__ __launch_bounds__(256) void sample_kernel(
     const float *__restrict__ pdf, const float *__restrict__ marg, const float *__restrict__ cond,
     uint32_t L, int H, int W, const uint32_t *__restrict__ leaf, const float2 *__restrict__ u, uint64_t n,
     float *__restrict__ dir, float *__restrict__ pdf_out, uint32_t *__restrict__ bin_out, uint32_t *err) {
-  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n;
-       q += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t l = leaf[q];
-    const float2 uu = u[q];
-    if (l >= L || !(uu.x >= 0.0f && uu.x < 1.0f) || !(uu.y >= 0.0f && uu.y < 1.0f)) {
-      const float qnan = __int_as_float(0x7fc00000);
-      dir[3 * q] = qnan;
-      dir[3 * q + 1] = qnan;
-      dir[3 * q + 2] = qnan;
-      pdf_out[q] = qnan;
-      if (bin_out) bin_out[q] = 0xffffffffu;
-      raise_err(err, ERR_RANGE);
-      continue;
+  __shared__ float4 sdir[192];  // 256 directions of 3 floats
+  float *sd = reinterpret_cast<float *>(sdir);
+  const int t = (int)threadIdx.x;
+  const bool dir16 = (reinterpret_cast<uintptr_t>(dir) & 15) == 0;
+  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < n; base += (uint64_t)gridDim.x * 256) {
+    const uint64_t q = base + (uint64_t)t;
+    float d[3] = {0.0f, 0.0f, 0.0f}, p = 0.0f;
+    uint32_t b = 0;
+    if (q < n) {
+      const uint32_t l = leaf[q];
+      const float2 uu = u[q];
+      if (l >= L || !(uu.x >= 0.0f && uu.x < 1.0f) || !(uu.y >= 0.0f && uu.y < 1.0f)) {
+        const float qnan = __int_as_float(0x7fc00000);
+        d[0] = d[1] = d[2] = p = qnan;
+        b = 0xffffffffu;
+        raise_err(err, ERR_RANGE);
+      } else {
+        guided_sample(pdf, marg, cond, l, H, W, uu.x, uu.y, d, &p, &b);
+      }
+      pdf_out[q] = p;
+      if (bin_out) bin_out[q] = b;
     }
-    float d[3], p;
-    uint32_t b;
-    guided_sample(pdf, marg, cond, l, H, W, uu.x, uu.y, d, &p, &b);
-    dir[3 * q] = d[0];
-    dir[3 * q + 1] = d[1];
-    dir[3 * q + 2] = d[2];
-    pdf_out[q] = p;
-    if (bin_out) bin_out[q] = b;
+    sd[3 * t] = d[0];
+    sd[3 * t + 1] = d[1];
+    sd[3 * t + 2] = d[2];
+    __syncthreads();
+    const uint64_t nb = n - base < 256 ? n - base : 256;
+    float *dst = dir + 3 * base;  // 16-byte aligned when dir is (3 * 256 * 4 bytes per block)
+    if (nb == 256 && dir16) {
+      if (t < 192) reinterpret_cast<float4 *>(dst)[t] = sdir[t];
+    } else {
+      for (int k = t; k < 3 * (int)nb; k += 256) dst[k] = sd[k];
+    }
+    __syncthreads();
   }
 }
 

@@ -14,7 +14,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "npg_oracle.c")
-LIB = os.path.join(HERE, "libnpg_oracle.so")
+# NPG_ORACLE_SANITIZE=1 selects a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload the ASan runtime)
+SANITIZE = os.environ.get("NPG_ORACLE_SANITIZE") == "1"
+LIB = os.path.join(HERE, "libnpg_oracle_san.so" if SANITIZE else "libnpg_oracle.so")
 
 OK, E_ARG, E_RANGE, E_CAPACITY = 0, -1, -2, -3
 
@@ -23,8 +26,10 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
+        san = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined"] if SANITIZE else []
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"])
+                               "-fno-fast-math", "-Wall", *san, "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 

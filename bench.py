@@ -532,6 +532,33 @@ def stratified_leaves(counts: np.ndarray, n: int) -> np.ndarray:
     return np.sort(order[np.linspace(0, len(counts) - 1, min(n, len(counts))).astype(np.int64)])
 
 
+def fp8_calibration_maps(npg, ctx, workload: str, H: int, W: int):
+    """Energy maps of the FP8 calibration set: 256 leaves of the same
+    workload drawn from seed + 100 (the uniform batch: seed 1101; the
+    clustered workload: seed 1103, its own octree, leaves stratified by
+    photon count).  Returns (maps on cuda:0, description)."""
+    import torch
+
+    from paper_2010_01775_amd import synth
+    dev = "cuda:0"
+    i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    if workload == "uniform":
+        cb = synth.uniform_batch(seed=1101, L=256, n_queries=1, model=b"")
+        ce, _ = npg.splat_histograms(ctx, f32(cb.dirs), i32(cb.w), i32(cb.leaf_off), H, W, want_count=False)
+        return ce, "256 leaves of the uniform batch drawn from seed 1101"
+    ccp = synth.clustered_photons(seed=1103)
+    chier = npg.build_hierarchy(ctx, f32(ccp.pos), 8192, 6, max_leaves=65536)
+    coff = chier["leaf_off"].cpu().numpy().view(np.uint32).astype(np.int64)
+    cperm = chier["perm"].cpu().numpy().view(np.uint32)
+    pick = stratified_leaves(np.diff(coff), 256)
+    sel = np.concatenate([cperm[coff[l]:coff[l + 1]] for l in pick])
+    soff = np.concatenate([[0], np.cumsum(np.diff(coff)[pick])]).astype(np.uint32)
+    ce, _ = npg.splat_histograms(ctx, f32(ccp.dirs[sel]), i32(ccp.w[sel]), i32(soff), H, W, want_count=False)
+    return ce, (f"256 leaves stratified by photon count from the clustered workload drawn from seed 1103 "
+                f"(its own octree, {chier['n_leaves']} leaves)")
+
+
 def run_path(args, workload: str, with_baseline: bool = True) -> dict:
     """Times `args.steps` steps of the hot path on one workload; returns the
     JSON record."""
@@ -683,27 +710,8 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
     calib = None
     if args.precision == "fp8":
         # static e4m3 scales from a separate calibration set of the same
-        # workload drawn from seed + 100 (256 leaves; for the clustered
-        # workload stratified by photon count over its own octree), set once
-        # before timing
-        if workload == "uniform":
-            cb = synth.uniform_batch(seed=1101, L=256, n_queries=1, model=b"")
-            ce, _ = npg.splat_histograms(ctx, f32(cb.dirs), i32(cb.w), i32(cb.leaf_off), H, W, want_count=False)
-            calib = "256 leaves of the uniform batch drawn from seed 1101"
-        else:
-            ccp = synth.clustered_photons(seed=1103)
-            cpos = f32(ccp.pos)
-            chier = npg.build_hierarchy(ctx, cpos, 8192, 6, max_leaves=65536)
-            coff = chier["leaf_off"].cpu().numpy().view(np.uint32).astype(np.int64)
-            cperm = chier["perm"].cpu().numpy().view(np.uint32)
-            pick = stratified_leaves(np.diff(coff), 256)
-            sel = np.concatenate([cperm[coff[l]:coff[l + 1]] for l in pick])
-            soff = np.concatenate([[0], np.cumsum(np.diff(coff)[pick])]).astype(np.uint32)
-            ce, _ = npg.splat_histograms(ctx, f32(ccp.dirs[sel]), i32(ccp.w[sel]), i32(soff), H, W,
-                                         want_count=False)
-            calib = (f"256 leaves stratified by photon count from the clustered workload drawn from seed 1103 "
-                     f"(its own octree, {chier['n_leaves']} leaves)")
-            del ccp, cpos, chier, sel
+        # workload, set once before timing
+        ce, calib = fp8_calibration_maps(npg, ctx, workload, H, W)
         for m in experts or [model]:
             m.calibrate_fp8(ce)
         del ce

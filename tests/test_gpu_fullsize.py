@@ -165,3 +165,42 @@ def test_clustered_chain_stratified(ctx, npg, orc, clustered, clustered_maps):
                f"clustered, {len(pick)} stratified leaves (counts {cm['counts'][pick].min()}.."
                f"{cm['counts'][pick].max()})")
     m.free()
+
+
+def test_clustered_fp8_worst_leaves_vs_oracle(ctx, npg, orc, clustered_maps):
+    """FP8 e4m3 with static scales from the benchmark's calibration set (256
+    leaves of the clustered workload drawn from seed 1103): per-leaf L1 and KL
+    of the pdf against the FP32 path on every leaf, then the eight worst
+    leaves and eight stratified ones against the FP64 oracle: L1 <= 0.2 and
+    KL(oracle || fp8) <= 0.1 on each."""
+    import bench
+    cm = clustered_maps
+    L = cm["L"]
+    model = synth.unet_model(1002)
+    m = npg.Model(ctx, model)
+    ce, _ = bench.fp8_calibration_maps(npg, ctx, "clustered", 128, 128)
+    m.calibrate_fp8(ce)
+    del ce
+    norm = lambda s: s / s.sum((1, 2), keepdim=True)
+    p8 = norm(npg.reconstruct_density(ctx, m, cm["e"], "fp8").double())
+    p32 = norm(npg.reconstruct_density(ctx, m, cm["e"], "fp32").double())
+    assert npg.sync_status(ctx) == 0
+    l1_all = (p8 - p32).abs().sum((1, 2)).cpu().numpy()
+    del p32
+    worst = np.argsort(l1_all)[-8:]
+    pick = np.unique(np.concatenate([worst, stratified(cm["counts"], 8)]))
+    rc, s_ref = orc.net_forward(model, orc.normalize_input(cm["e_ref"][pick]))
+    assert rc == 0
+    q = s_ref / s_ref.sum((1, 2), keepdims=True)
+    p = p8[torch.from_numpy(pick).to(DEV)].cpu().numpy()
+    l1 = np.abs(p - q).sum((1, 2))
+    kl = np.where(q > 0, q * np.log(q / np.maximum(p, 1e-300)), 0.0).sum((1, 2))
+    print(f"fp8 vs fp32 over {L} leaves: L1 median {np.median(l1_all):.3e} max {l1_all.max():.3e}; "
+          f"vs oracle on {len(pick)} leaves (worst {worst.tolist()}): L1 max {l1.max():.3e}, KL max {kl.max():.3e}")
+    assert l1.max() <= 0.2 and kl.max() <= 0.1
+    m.free()
+
+
+def stratified(counts, n):
+    order = np.argsort(counts, kind="stable")
+    return np.sort(order[np.linspace(0, len(counts) - 1, n).astype(np.int64)])

@@ -504,11 +504,13 @@ def run_serving(args):
     ctx.close()
 
 
-def stage_bytes(stage: str, n_photons: int, L: int, H: int, W: int, nq: int) -> float:
+def stage_bytes(stage: str, n_photons: int, L: int, H: int, W: int, nq: int, sorted_photons: bool = False) -> float:
     """Algorithmic HBM bytes of one stage: what the step must read and write
     once (no sort passes, no re-reads).
       hier   positions 12 B read + permutation 4 B written per photon, leaf
-             offsets 4 B per leaf (leaf_of is not requested by the step)
+             offsets 4 B per leaf (leaf_of is not requested by the step);
+             with the photons put in leaf order (the octree) also their
+             direction and weight, 16 B read and 16 B written per photon
       splat  direction 12 B + weight 4 B read per photon; energy 8 B + count
              4 B written per bin
       cdf    density 4 B read; pdf 4 B, conditional 4 (W+1)/W B written per
@@ -519,7 +521,7 @@ def stage_bytes(stage: str, n_photons: int, L: int, H: int, W: int, nq: int) -> 
              pdf table read once"""
     bins = float(L) * H * W
     tab = bins * 4 + L * H * (W + 1) * 4.0 + L * (H + 1) * 4.0
-    return {"hier": n_photons * 16.0 + (L + 1) * 4.0,
+    return {"hier": n_photons * (48.0 if sorted_photons else 16.0) + (L + 1) * 4.0,
             "splat": n_photons * 16.0 + bins * 12.0,
             "cdf": bins * 4.0 + tab + L * 8.0,
             "sample": nq * 32.0 + tab,
@@ -647,6 +649,10 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
         cap = (1 << 20) if args.hierarchy == "kdgrid" else 65536
         hier_out = dict(perm=torch.empty(n, dtype=torch.int32, device=dev),
                         off=torch.empty(cap + 1, dtype=torch.int32, device=dev))
+        if args.hierarchy == "octree":
+            # the photons in leaf order, written by the build
+            hier_out["dirs"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+            hier_out["w"] = torch.empty(n, dtype=torch.int32, device=dev)
         if args.hierarchy == "kdgrid":
             hier_out["root"] = torch.empty(100 ** 3, dtype=torch.int32, device=dev)
             hier_out["nodes"] = torch.empty((2 * cap, 2), dtype=torch.int32, device=dev)
@@ -675,15 +681,20 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
                                                    C.byref(nn), stream.cuda_stream))
             else:
                 prm = npg.HierParams(8192, 6)
-                ctx.check(ctx.lib.npg_build_hierarchy(ctx.h, pos.data_ptr(), pos.shape[0], C.byref(prm),
-                                                      hier_out["perm"].data_ptr(), None,
-                                                      hier_out["off"].data_ptr(), None, None, 65536,
-                                                      C.byref(nl), stream.cuda_stream))
+                ctx.check(ctx.lib.npg_build_hierarchy_sorted(ctx.h, pos.data_ptr(), dirs.data_ptr(), w.data_ptr(),
+                                                             pos.shape[0], C.byref(prm),
+                                                             hier_out["perm"].data_ptr(),
+                                                             hier_out["dirs"].data_ptr(), hier_out["w"].data_ptr(),
+                                                             hier_out["off"].data_ptr(), None, None, 65536,
+                                                             C.byref(nl), stream.cuda_stream))
             assert nl.value == L
             mark("hier", 1)
             lo = hier_out["off"][:L + 1]
             mark("splat", 0)
-            npg.splat_histograms(ctx, dirs, w, lo, H, W, perm=hier_out["perm"], energy=energy, count=count)
+            if args.hierarchy == "octree":   # leaf-ordered photons: contiguous runs per leaf
+                npg.splat_histograms(ctx, hier_out["dirs"], hier_out["w"], lo, H, W, energy=energy, count=count)
+            else:
+                npg.splat_histograms(ctx, dirs, w, lo, H, W, perm=hier_out["perm"], energy=energy, count=count)
         else:
             mark("splat", 0)
             npg.splat_histograms(ctx, dirs, w, off, H, W, energy=energy, count=count)
@@ -830,7 +841,7 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
     for s_ in stages:
         if s_ == "recon":
             continue
-        by = stage_bytes(s_, n_photons, L, H, W, nq)
+        by = stage_bytes(s_, n_photons, L, H, W, nq, sorted_photons=pos is not None and args.hierarchy == "octree")
         gbps = by / (avg[s_] / 1e3) / 1e9
         stage_roof[s_] = {"ms": avg[s_], "algorithmic_bytes": by, "GBps": gbps, "frac_hbm": gbps / PEAK["hbm_GBps"]}
     stage_roof["recon"] = {"ms": avg["recon"], "algorithmic_flops": flops, "TFLOPs": achieved,

@@ -216,6 +216,23 @@ int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n, const np
                         uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev, uint32_t max_leaves,
                         uint32_t *n_leaves_out, void *stream);
 
+/* npg_build_hierarchy that also puts the photons' directions and weights
+ * in leaf order (the photons of Eq. "photon" grouped by voxel, Sec. 7.1):
+ * dir_sorted[i] = dir[perm[i]], w_sorted[i] = w[perm[i]], so that
+ * npg_splat_histograms reads every leaf's photons as one contiguous run
+ * (perm NULL, leaf_off as written here).  The directions and weights move
+ * with the permutation through its sort, read and written in order, instead
+ * of being gathered through perm afterwards.
+ *   dir_dev [n][3] float32, w_dev [n] uint32: the photons in input order
+ *   dir_sorted_dev [n][3], w_sorted_dev [n]: out, leaf order (must not alias
+ *   the inputs)
+ * Every other argument, output and error as in npg_build_hierarchy (no
+ * leaf_of output). */
+int npg_build_hierarchy_sorted(npg_ctx *ctx, const float *pos_dev, const float *dir_dev, const uint32_t *w_dev,
+                               uint64_t n, const npg_hier_params *params, uint32_t *perm_dev, float *dir_sorted_dev,
+                               uint32_t *w_sorted_dev, uint32_t *leaf_off_dev, uint64_t *leaf_key_dev,
+                               uint8_t *leaf_depth_dev, uint32_t max_leaves, uint32_t *n_leaves_out, void *stream);
+
 /* Valid voxels (Sec. 7.1, detecting valid voxels; Algorithm 1, path step):
  * a voxel is valid iff at least one bounce point of the camera paths lies in
  * it.  The voxel of a point p is floor((p - lo) * (res / (hi - lo))) per axis,

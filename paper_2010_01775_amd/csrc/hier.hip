@@ -263,17 +263,41 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *__r
 // The tile is first ordered by digit in LDS (ranks from wavefront ballots,
 // waves and rounds in item order, so equal digits keep their input order),
 // then streamed out: consecutive LDS entries of one digit go to consecutive
-// global positions, so the writes form runs instead of single words.
+// global positions, so the writes form runs instead of single words.  LDS
+// holds each item's key and its index within the tile; the value and the
+// optional payload (a photon's direction and weight, moved with the
+// permutation) are read from the tile's own 4096 items when written out, so
+// those reads stay within a few L2-resident lines.  key_out == NULL: the
+// keys are not written (the last pass).
+// Between two passes the payload is one 16-byte record per photon
+// (direction, weight); the first pass reads the caller's arrays, the last
+// writes them.  Each item then costs one or two wide accesses per pass
+// instead of four single words (a load whose 64 lanes hit 64 different
+// lines costs the same at any width).
+struct Payload {
+  const float *dir_in = nullptr;
+  const uint32_t *w_in = nullptr;
+  const uint4 *rec_in = nullptr;
+  float *dir_out = nullptr;
+  uint32_t *w_out = nullptr;
+  uint4 *rec_out = nullptr;
+  __device__ bool on() const { return dir_in || rec_in; }
+};
+struct Dir3 {
+  float x, y, z;
+};
+
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *__restrict__ key,
                                                                 const uint32_t *__restrict__ vals, uint64_t n,
                                                                 int shift, uint32_t nblocks,
                                                                 const uint32_t *__restrict__ offs,
                                                                 uint32_t *__restrict__ key_out,
-                                                                uint32_t *__restrict__ val_out) {
+                                                                uint32_t *__restrict__ val_out, Payload pl) {
   __shared__ uint32_t cnt[RS_THREADS / 64][256];
   __shared__ uint32_t tile_off[256];  // first LDS slot of each digit
   __shared__ uint32_t gdst[256];      // global position of that slot
-  __shared__ uint32_t lkey[RS_TILE], lval[RS_TILE];
+  __shared__ uint32_t lkey[RS_TILE];
+  __shared__ uint16_t lidx[RS_TILE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int w = 0; w < RS_THREADS / 64; ++w) cnt[w][threadIdx.x] = 0;
   __syncthreads();
@@ -329,7 +353,7 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
     if (act) {
       const uint32_t pos = basev + rank;
       lkey[pos] = kk;
-      lval[pos] = vals ? vals[i] : (uint32_t)i;
+      lidx[pos] = (uint16_t)(i - tbase);
       if (rank == 0) cnt[wave][dg] = basev + tot;
     }
     __builtin_amdgcn_wave_barrier();
@@ -340,8 +364,160 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
     const uint32_t kk = lkey[j];
     const uint32_t dg = (kk >> shift) & 255u;
     const uint32_t pos = gdst[dg] + (j - tile_off[dg]);
-    key_out[pos] = kk;
+    const uint64_t src = tbase + lidx[j];
+    if (key_out) key_out[pos] = kk;
+    val_out[pos] = vals ? vals[src] : (uint32_t)src;
+    if (pl.on()) {
+      Dir3 d;
+      uint32_t ww;
+      if (pl.rec_in) {
+        const uint4 r = pl.rec_in[src];
+        d = Dir3{__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z)};
+        ww = r.w;
+      } else {
+        d = reinterpret_cast<const Dir3 *>(pl.dir_in)[src];
+        ww = pl.w_in[src];
+      }
+      if (pl.rec_out) {
+        pl.rec_out[pos] = make_uint4(__float_as_uint(d.x), __float_as_uint(d.y), __float_as_uint(d.z), ww);
+      } else {
+        reinterpret_cast<Dir3 *>(pl.dir_out)[pos] = d;
+        pl.w_out[pos] = ww;
+      }
+    }
+  }
+}
+
+// The octree build's scatter: as rs_scatter_kernel, but every item's value
+// and payload travel through LDS with its key, so that all global reads are
+// in item order (coalesced) and all writes are runs of one digit.  1024
+// threads (16 wavefronts of 256 items each, a 4096-item tile as in
+// rs_hist_kernel); each wavefront issues the loads of its four rounds before
+// ranking the first.  PL: the payload (direction + weight) is moved too.
+constexpr int RSP_THREADS = 1024;
+constexpr int RSP_WAVES = RSP_THREADS / 64;
+constexpr int RSP_WAVE_ITEMS = RS_TILE / RSP_WAVES;  // 256
+constexpr int RSP_ROUNDS = RSP_WAVE_ITEMS / 64;      // 4
+
+template <bool PL>
+__global__ __launch_bounds__(RSP_THREADS) void rs_scatter_pl_kernel(const uint32_t *__restrict__ key,
+                                                                   const uint32_t *__restrict__ vals, uint64_t n,
+                                                                   int shift, uint32_t nblocks,
+                                                                   const uint32_t *__restrict__ offs,
+                                                                   uint32_t *__restrict__ key_out,
+                                                                   uint32_t *__restrict__ val_out, Payload pl) {
+  __shared__ uint32_t cnt[RSP_WAVES][256];
+  __shared__ uint32_t tile_off[256], gdst[256], ws[4];
+  __shared__ uint32_t lkey[RS_TILE], lval[RS_TILE];
+  __shared__ uint4 lrec[PL ? RS_TILE : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < RSP_WAVES * 256; k += RSP_THREADS) (&cnt[0][0])[k] = 0;
+  const uint64_t tbase = (uint64_t)blockIdx.x * RS_TILE;
+  const uint64_t wbase = tbase + (uint64_t)wave * RSP_WAVE_ITEMS;
+  // this wavefront's items: keys, values and payload, loaded in order
+  uint32_t kk[RSP_ROUNDS], vv[RSP_ROUNDS];
+  uint4 rr[PL ? RSP_ROUNDS : 1];
+#pragma unroll
+  for (int r = 0; r < RSP_ROUNDS; ++r) {
+    const uint64_t i = wbase + r * 64 + lane;
+    const bool act = i < n;
+    kk[r] = act ? key[i] : 0u;
+    vv[r] = act ? (vals ? vals[i] : (uint32_t)i) : 0u;
+    if constexpr (PL) {
+      rr[r] = make_uint4(0, 0, 0, 0);
+      if (act) {
+        if (pl.rec_in) {
+          rr[r] = pl.rec_in[i];
+        } else {
+          const Dir3 d = reinterpret_cast<const Dir3 *>(pl.dir_in)[i];
+          rr[r] = make_uint4(__float_as_uint(d.x), __float_as_uint(d.y), __float_as_uint(d.z), pl.w_in[i]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RSP_ROUNDS; ++r)
+    if (wbase + r * 64 + lane < n) atomicAdd(&cnt[wave][(kk[r] >> shift) & 255u], 1u);
+  __syncthreads();
+  if (threadIdx.x < 256) {  // digit d: its tile count, exclusive scan, per-wave starts
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+    for (int w = 0; w < RSP_WAVES; ++w) c += cnt[w][d];
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) ws[wave] = incl;
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+    for (int w = 0; w < RSP_WAVES; ++w) c += cnt[w][d];
+    uint32_t run = 0;
+    for (int w = 0; w < wave; ++w) run += ws[w];
+    // incl - c recomputed from the wave's scan: the prefix within the wave
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    run += incl - c;
+    tile_off[d] = run;
+    gdst[d] = offs[(uint64_t)d * nblocks + blockIdx.x];
+    for (int w = 0; w < RSP_WAVES; ++w) {
+      const uint32_t cw = cnt[w][d];
+      cnt[w][d] = run;
+      run += cw;
+    }
+  }
+  __syncthreads();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < RSP_ROUNDS; ++r) {
+    const bool act = wbase + r * 64 + lane < n;
+    const uint32_t dg = (kk[r] >> shift) & 255u;
+    uint64_t mask = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot(((dg >> b) & 1u) != 0);
+      mask &= ((dg >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(mask & below);
+    const uint32_t tot = (uint32_t)__popcll(mask);
+    uint32_t basev = 0;
+    if (act) basev = cnt[wave][dg];
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+      const uint32_t pos = basev + rank;
+      lkey[pos] = kk[r];
+      lval[pos] = vv[r];
+      if constexpr (PL) lrec[pos] = rr[r];
+      if (rank == 0) cnt[wave][dg] = basev + tot;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  const uint32_t nt = (uint32_t)min((uint64_t)RS_TILE, n - tbase);
+  for (uint32_t j = threadIdx.x; j < nt; j += RSP_THREADS) {
+    const uint32_t k2 = lkey[j];
+    const uint32_t dg = (k2 >> shift) & 255u;
+    const uint32_t pos = gdst[dg] + (j - tile_off[dg]);
+    if (key_out) key_out[pos] = k2;
     val_out[pos] = lval[j];
+    if constexpr (PL) {
+      const uint4 q = lrec[j];
+      if (pl.rec_out) {
+        pl.rec_out[pos] = q;
+      } else {
+        reinterpret_cast<Dir3 *>(pl.dir_out)[pos] = Dir3{__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z)};
+        pl.w_out[pos] = q.w;
+      }
+    }
   }
 }
 
@@ -396,7 +572,7 @@ hipError_t npg_radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint
     hipError_t e = scan_u32(hist, nhist, offs, btmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(RS_THREADS), 0, s, kin, vin, n, 8 * p, nb, offs, kout,
-                       vout);
+                       vout, Payload{});
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     kin = kout;
@@ -405,11 +581,12 @@ hipError_t npg_radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint
   return hipSuccess;
 }
 
-extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n,
-                                   const npg_hier_params *params, uint32_t *perm_dev,
-                                   uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,
-                                   uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev,
-                                   uint32_t max_leaves, uint32_t *n_leaves_out, void *stream) {
+// The octree build; pl.dir_out non-null: the photons' directions and
+// weights are moved with the permutation into leaf order.
+static int build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n, const npg_hier_params *params,
+                           uint32_t *perm_dev, uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,
+                           uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev, uint32_t max_leaves,
+                           uint32_t *n_leaves_out, void *stream, const Payload &pl) {
   if (!ctx) return NPG_E_ARG;
   if (!params || !n_leaves_out) return npg_fail(ctx, NPG_E_ARG, "build_hierarchy: null argument");
   if (params->max_depth < 0 || params->max_depth > 8)
@@ -436,6 +613,7 @@ extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t 
   bytes += npg_align((uint64_t)ncell + 1);         // ldepth
   bytes += npg_align(4 * (n ? n : 1)) * 3;         // leaf_of (own), keys A, keys B
   bytes += npg_align(4 * (n ? n : 1));             // vals tmp
+  if (pl.dir_out) bytes += 2 * npg_align(16 * (n ? n : 1));  // payload records between the passes
   bytes += npg_align(4 * (nhist + 1)) * 2;         // hist, offs
   bytes += npg_align(4 * ((scan_max + SCAN_TILE - 1) / SCAN_TILE + 1));
   void *scr = nullptr;
@@ -452,6 +630,7 @@ extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t 
   uint32_t *ka = cv.take<uint32_t>(n ? n : 1);
   uint32_t *kb = cv.take<uint32_t>(n ? n : 1);
   uint32_t *vt = cv.take<uint32_t>(n ? n : 1);
+  uint4 *rec[2] = {pl.dir_out ? cv.take<uint4>(n ? n : 1) : nullptr, pl.dir_out ? cv.take<uint4>(n ? n : 1) : nullptr};
   uint32_t *hist = cv.take<uint32_t>(nhist + 1);
   uint32_t *offs = cv.take<uint32_t>(nhist + 1);
   uint32_t *btmp = cv.take<uint32_t>((scan_max + SCAN_TILE - 1) / SCAN_TILE + 1);
@@ -516,15 +695,64 @@ extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t 
   const uint32_t *vin = nullptr;
   for (int p = 0; p < passes; ++p) {
     const bool last = p == passes - 1;
-    uint32_t *kout = (p & 1) ? kb : ka;
+    uint32_t *kout = last ? nullptr : ((p & 1) ? kb : ka);
     uint32_t *vout = last ? perm_dev : ((vin == vt) ? cell : vt);  // cell is free after leaf_of
+    // payload: the caller's arrays into records, records into records
+    // (alternating buffers), the last pass into the caller's outputs
+    Payload step{};
+    if (pl.dir_out) {
+      if (p == 0) {
+        step.dir_in = pl.dir_in;
+        step.w_in = pl.w_in;
+      } else {
+        step.rec_in = rec[(p - 1) & 1];
+      }
+      if (last) {
+        step.dir_out = pl.dir_out;
+        step.w_out = pl.w_out;
+      } else {
+        step.rec_out = rec[p & 1];
+      }
+    }
     hipLaunchKernelGGL(rs_hist_kernel, dim3(nb_rs), dim3(RS_THREADS), 0, s, kin, n, 8 * p, nb_rs, hist);
     NPG_HIP_CHECK(ctx, scan_u32(hist, nhist, offs, btmp, s));
-    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb_rs), dim3(RS_THREADS), 0, s, kin, vin, n, 8 * p, nb_rs, offs,
-                       kout, vout);
+    if (pl.dir_out)
+      hipLaunchKernelGGL(rs_scatter_pl_kernel<true>, dim3(nb_rs), dim3(RSP_THREADS), 0, s, kin, vin, n, 8 * p, nb_rs,
+                         offs, kout, vout, step);
+    else
+      hipLaunchKernelGGL(rs_scatter_pl_kernel<false>, dim3(nb_rs), dim3(RSP_THREADS), 0, s, kin, vin, n, 8 * p,
+                         nb_rs, offs, kout, vout, step);
     NPG_HIP_CHECK(ctx, hipGetLastError());
     kin = kout;
     vin = vout;
   }
   return NPG_OK;
+}
+
+extern "C" int npg_build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n,
+                                   const npg_hier_params *params, uint32_t *perm_dev,
+                                   uint32_t *leaf_of_dev, uint32_t *leaf_off_dev,
+                                   uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev,
+                                   uint32_t max_leaves, uint32_t *n_leaves_out, void *stream) {
+  return build_hierarchy(ctx, pos_dev, n, params, perm_dev, leaf_of_dev, leaf_off_dev, leaf_key_dev,
+                         leaf_depth_dev, max_leaves, n_leaves_out, stream, Payload{});
+}
+
+extern "C" int npg_build_hierarchy_sorted(npg_ctx *ctx, const float *pos_dev, const float *dir_dev,
+                                          const uint32_t *w_dev, uint64_t n, const npg_hier_params *params,
+                                          uint32_t *perm_dev, float *dir_sorted_dev, uint32_t *w_sorted_dev,
+                                          uint32_t *leaf_off_dev, uint64_t *leaf_key_dev, uint8_t *leaf_depth_dev,
+                                          uint32_t max_leaves, uint32_t *n_leaves_out, void *stream) {
+  if (!ctx) return NPG_E_ARG;
+  if (n && (!dir_dev || !w_dev || !dir_sorted_dev || !w_sorted_dev))
+    return npg_fail(ctx, NPG_E_ARG, "build_hierarchy_sorted: null photon array");
+  if (n && (dir_sorted_dev == dir_dev || w_sorted_dev == w_dev))
+    return npg_fail(ctx, NPG_E_ARG, "build_hierarchy_sorted: the sorted photons cannot overwrite the input");
+  Payload pl;
+  pl.dir_in = dir_dev;
+  pl.w_in = w_dev;
+  pl.dir_out = dir_sorted_dev;
+  pl.w_out = w_sorted_dev;
+  return build_hierarchy(ctx, pos_dev, n, params, perm_dev, nullptr, leaf_off_dev, leaf_key_dev, leaf_depth_dev,
+                         max_leaves, n_leaves_out, stream, pl);
 }

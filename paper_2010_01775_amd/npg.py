@@ -24,7 +24,7 @@ PRECISION = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
 SYMBOLS = [
     "npg_create", "npg_destroy", "npg_last_error", "npg_sync_status", "npg_memory_usage", "npg_conv_flops",
     "npg_model_load", "npg_model_free", "npg_model_calibrate_fp8",
-    "npg_build_hierarchy", "npg_mark_valid", "npg_build_kdgrid", "npg_locate",
+    "npg_build_hierarchy", "npg_build_hierarchy_sorted", "npg_mark_valid", "npg_build_kdgrid", "npg_locate",
     "npg_splat_histograms", "npg_normalize_input",
     "npg_reconstruct_density", "npg_reconstruct_density_noalloc", "npg_reconstruct_experts", "npg_build_cdf", "npg_sample_dirs", "npg_eval_pdf",
     "npg_mis_alpha", "npg_sample_mis", "npg_eval_pdf_mis", "npg_reconstruct_density5",
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH):
         "npg_model_load": (I, [P, P, SZ, C.POINTER(P)]),
         "npg_model_free": (None, [P]),
         "npg_model_calibrate_fp8": (I, [P, P, P, U32, I, I, P]),
+        "npg_build_hierarchy_sorted": (I, [P, P, P, P, U64, C.POINTER(HierParams), P, P, P, P, P, P, U32,
+                                           C.POINTER(U32), P]),
         "npg_build_hierarchy": (I, [P, P, U64, C.POINTER(HierParams), P, P, P, P, P, U32,
                                     C.POINTER(U32), P]),
         "npg_mark_valid": (I, [P, C.POINTER(KDGridParams), P, U64, P, P]),
@@ -237,6 +239,37 @@ class CdfTables:
         L, H, W = self.pdf.shape
         return Tables(self.pdf.data_ptr(), self.marg.data_ptr(), self.cond.data_ptr(),
                       self.total.data_ptr() if self.total is not None else None, L, H, W)
+
+
+def build_hierarchy_sorted(ctx: Context, pos, dirs, w, split_count: int = 8192, max_depth: int = 6,
+                           max_leaves: int | None = None, out=None, stream=None):
+    """build_hierarchy plus the photons' directions and weights in leaf order
+    (dirs_sorted[i] = dirs[perm[i]], w_sorted[i] = w[perm[i]]).  out: optional
+    dict of caller tensors perm, dirs, w, leaf_off to write into."""
+    _dev(pos, torch.float32, "pos")
+    _dev(dirs, torch.float32, "dirs")
+    _dev(w, torch.int32, "w (uint32 bits in int32)")
+    n = pos.shape[0]
+    if dirs.shape != (n, 3) or w.shape != (n,):
+        raise ValueError("dirs must be [n][3] and w [n]")
+    dev = pos.device
+    if max_leaves is None:
+        max_leaves = max(1, min(n, 8 ** max_depth))
+    out = out or {}
+    perm = out.get("perm", torch.empty(n, dtype=torch.int32, device=dev))
+    ds = out.get("dirs", torch.empty((n, 3), dtype=torch.float32, device=dev))
+    ws = out.get("w", torch.empty(n, dtype=torch.int32, device=dev))
+    off = out.get("leaf_off", torch.empty(max_leaves + 1, dtype=torch.int32, device=dev))
+    key = torch.empty(max_leaves, dtype=torch.int64, device=dev)
+    depth = torch.empty(max_leaves, dtype=torch.uint8, device=dev)
+    nl = C.c_uint32(0)
+    prm = HierParams(split_count, max_depth)
+    rc = ctx.lib.npg_build_hierarchy_sorted(ctx.h, _ptr(pos), _ptr(dirs), _ptr(w), n, C.byref(prm), _ptr(perm),
+                                            _ptr(ds), _ptr(ws), _ptr(off), _ptr(key), _ptr(depth), max_leaves,
+                                            C.byref(nl), _stream(stream))
+    ctx.check(rc)
+    L = nl.value
+    return dict(perm=perm, dirs=ds, w=ws, leaf_off=off[:L + 1], key=key[:L], depth=depth[:L], n_leaves=L)
 
 
 def build_hierarchy(ctx: Context, pos, split_count: int = 8192, max_depth: int = 6,

@@ -82,3 +82,44 @@ def test_hierarchy_clustered_workload_full_size(ctx, npg, orc, clustered, cluste
     cnt = np.diff(ref["leaf_off"].astype(np.int64))
     print(f"leaves {ref['n_leaves']}, photons per leaf min {cnt.min()} median {np.median(cnt):.0f} max {cnt.max()}")
     assert 15000 < ref["n_leaves"] < 25000
+
+
+@pytest.mark.parametrize("seed,n,T,D", [(11, 30000, 500, 6), (12, 5000, 10000, 4), (13, 70001, 64, 7),
+                                        (14, 3000, 8, 1), (15, 150000, 1, 8)])
+def test_hierarchy_sorted_photons(ctx, npg, orc, seed, n, T, D):
+    """The leaf-ordered photons equal the input gathered through the oracle's
+    permutation, bit for bit; the permutation and offsets equal the oracle's
+    (1-, 2- and 3-byte leaf ids: one, two and three sort passes)."""
+    rng = np.random.default_rng(seed)
+    pos = _pts(seed, n) if T > 1 else rng.random((n, 3)).astype(np.float32)   # T = 1: > 65536 leaves
+    dirs = synth.to_f32_dirs(synth.unit_vectors(rng, n))
+    w = synth.photon_weights(rng, n)
+    rc, ref = orc.build_tree(pos, T, D, max_leaves=n)
+    assert rc == 0
+    tf = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+    out = npg.build_hierarchy_sorted(ctx, tf(pos), tf(dirs), torch.from_numpy(w.view(np.int32)).to(DEV), T, D,
+                                     max_leaves=n)
+    assert npg.sync_status(ctx) == 0
+    assert out["n_leaves"] == ref["n_leaves"]
+    u = lambda t: t.cpu().numpy().view(np.uint32)
+    assert np.array_equal(u(out["perm"]), ref["perm"])
+    assert np.array_equal(u(out["leaf_off"]), ref["leaf_off"])
+    assert np.array_equal(out["dirs"].cpu().numpy().view(np.uint32), dirs[ref["perm"]].view(np.uint32))
+    assert np.array_equal(u(out["w"]), w[ref["perm"]])
+
+
+def test_hierarchy_sorted_clustered_maps(ctx, npg, orc, clustered, clustered_tree):
+    """The clustered workload: maps splatted from the leaf-ordered photons
+    (no permutation) equal the oracle's on every leaf."""
+    cp, ref = clustered, clustered_tree
+    tf = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+    out = npg.build_hierarchy_sorted(ctx, tf(cp.pos), tf(cp.dirs), torch.from_numpy(cp.w.view(np.int32)).to(DEV),
+                                     8192, 6, max_leaves=65536)
+    assert out["n_leaves"] == ref["n_leaves"]
+    e, c = npg.splat_histograms(ctx, out["dirs"], out["w"], out["leaf_off"], 128, 128)
+    assert npg.sync_status(ctx) == 0
+    assert np.array_equal(out["perm"].cpu().numpy().view(np.uint32), ref["perm"])
+    rc, e_ref, c_ref = orc.splat(cp.dirs, cp.w, ref["leaf_off"], 128, 128, perm=ref["perm"])
+    assert rc == 0
+    assert np.array_equal(e.cpu().numpy().view(np.uint64), e_ref)
+    assert np.array_equal(c.cpu().numpy().view(np.uint32), c_ref)

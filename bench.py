@@ -795,6 +795,67 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
     mat_flops, vec_flops = (f / args.steps for f in ctx.conv_flops(reset=True))
 
     avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
+
+    def fused_form(steps):
+        """The same step with the batched-leaf entry: hierarchy (leaf-ordered
+        photons) -> reconstruct_fused (splat, normalisation, network and CDF
+        per leaf chunk, replayed as a HIP graph from its third call) ->
+        sampling -> evaluation, on a side stream; identical results."""
+        import ctypes as C
+        fs = torch.cuda.Stream()
+        ctx.set_option("graphs", 1)
+        fe = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for k in ("step", "recon")}
+
+        def one(record):
+            if pos is not None:
+                nl = C.c_uint32(0)
+                prm = npg.HierParams(8192, 6)
+                ctx.check(ctx.lib.npg_build_hierarchy_sorted(ctx.h, pos.data_ptr(), dirs.data_ptr(), w.data_ptr(),
+                                                             pos.shape[0], C.byref(prm), hier_out["perm"].data_ptr(),
+                                                             hier_out["dirs"].data_ptr(), hier_out["w"].data_ptr(),
+                                                             hier_out["off"].data_ptr(), None, None, 65536,
+                                                             C.byref(nl), fs.cuda_stream))
+                src = (hier_out["dirs"], hier_out["w"], hier_out["off"][:L + 1])
+            else:
+                src = (dirs, w, off)
+            if record:
+                fe["recon"][0].record(fs)
+            npg.reconstruct_fused(ctx, model, *src, H, W, args.precision, out=tabs, stream=fs)
+            if record:
+                fe["recon"][1].record(fs)
+            npg.sample_dirs(ctx, tabs, q_leaf, q_u, out=sd, stream=fs)
+            npg.eval_pdf(ctx, tabs, q_leaf, sd[0], out=pe, stream=fs)
+
+        for _ in range(3):   # eager, captured, first replay
+            one(False)
+        fs.synchronize()
+        t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rec_ms, step_ms = [], []
+        t0e.record(fs)
+        for _ in range(steps):
+            fe["step"][0].record(fs)
+            one(True)
+            fe["step"][1].record(fs)
+            fs.synchronize()
+            rec_ms.append(fe["recon"][0].elapsed_time(fe["recon"][1]))
+            step_ms.append(fe["step"][0].elapsed_time(fe["step"][1]))
+        t1e.record(fs)
+        fs.synchronize()
+        ctx.set_option("graphs", 0)
+        if npg.sync_status(ctx, stream=fs) != 0:
+            raise RuntimeError("data-dependent error in the fused form")
+        tot = t0e.elapsed_time(t1e)
+        return {"value": L * steps / (tot / 1e3), "unit": "leaves/s", "ms_per_step": tot / steps,
+                "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
+                "reconstruct_fused_ms": float(np.mean(rec_ms)),
+                "form": "build_hierarchy_sorted -> reconstruct_fused (HIP graph replay) -> sample_dirs -> eval_pdf"
+                        if pos is not None else "reconstruct_fused (HIP graph replay) -> sample_dirs -> eval_pdf"}
+
+    fused = None
+    if not args.experts and not args.input5 and (pos is None or args.hierarchy == "octree"):
+        fused = fused_form(max(3, args.steps // 2))
+        print(f"{workload} fused form: {fused['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
     mis = mis_rates()
     locate = None
     if pos is not None and args.hierarchy == "kdgrid":
@@ -876,6 +937,7 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
                                  "1x1 softplus head"} if args.paper_net else {}),
         "samples_per_s": nq / (avg["sample"] / 1e3),
         "eval_per_s": nq / (avg["eval"] / 1e3),
+        **({"fused_form": fused} if fused else {}),
         "one_sample_mis": mis,
         **({"kdgrid_locate": locate} if locate else {}),
         "p50_ms": float(np.percentile(per_step, 50)),
@@ -983,6 +1045,7 @@ def main():
         # the uniform batch, timed the same way, as an extra key
         u = run_path(args, "uniform", with_baseline=not args.no_cpu_baseline)
         res["uniform_batch"] = {k: u[k] for k in ("value", "unit", "ms_per_step", "samples_per_s", "eval_per_s",
+                                                  "fused_form",
                                                   "p50_ms", "p99_ms", "stage_ms", "stage_roofline", "roofline",
                                                   "config", "sampling_chi2", "precision_vs_fp32", "cpu_baseline")
                                 if k in u}

@@ -259,16 +259,6 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *__r
   hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile.  vals == NULL: the value is the item index.
-// The tile is first ordered by digit in LDS (ranks from wavefront ballots,
-// waves and rounds in item order, so equal digits keep their input order),
-// then streamed out: consecutive LDS entries of one digit go to consecutive
-// global positions, so the writes form runs instead of single words.  LDS
-// holds each item's key and its index within the tile; the value and the
-// optional payload (a photon's direction and weight, moved with the
-// permutation) are read from the tile's own 4096 items when written out, so
-// those reads stay within a few L2-resident lines.  key_out == NULL: the
-// keys are not written (the last pass).
 // Between two passes the payload is one 16-byte record per photon
 // (direction, weight); the first pass reads the caller's arrays, the last
 // writes them.  Each item then costs one or two wide accesses per pass
@@ -287,113 +277,17 @@ struct Dir3 {
   float x, y, z;
 };
 
-__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *__restrict__ key,
-                                                                const uint32_t *__restrict__ vals, uint64_t n,
-                                                                int shift, uint32_t nblocks,
-                                                                const uint32_t *__restrict__ offs,
-                                                                uint32_t *__restrict__ key_out,
-                                                                uint32_t *__restrict__ val_out, Payload pl) {
-  __shared__ uint32_t cnt[RS_THREADS / 64][256];
-  __shared__ uint32_t tile_off[256];  // first LDS slot of each digit
-  __shared__ uint32_t gdst[256];      // global position of that slot
-  __shared__ uint32_t lkey[RS_TILE];
-  __shared__ uint16_t lidx[RS_TILE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int w = 0; w < RS_THREADS / 64; ++w) cnt[w][threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t tbase = (uint64_t)blockIdx.x * RS_TILE;
-  const uint64_t wbase = tbase + (uint64_t)wave * RS_WAVE_ITEMS;
-  for (int k = lane; k < RS_WAVE_ITEMS; k += 64) {
-    const uint64_t i = wbase + k;
-    if (i < n) atomicAdd(&cnt[wave][(key[i] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  {  // digit d = threadIdx.x: its tile count, then per-wave starts
-    const int d = threadIdx.x;
-    uint32_t c = 0;
-    for (int w = 0; w < RS_THREADS / 64; ++w) c += cnt[w][d];
-    // exclusive scan of the 256 digit counts
-    __shared__ uint32_t ws[RS_THREADS / 64];
-    uint32_t incl = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(incl, o);
-      if (lane >= o) incl += t;
-    }
-    if (lane == 63) ws[wave] = incl;
-    __syncthreads();
-    uint32_t run = incl - c;
-    for (int w = 0; w < wave; ++w) run += ws[w];
-    tile_off[d] = run;
-    gdst[d] = offs[(uint64_t)d * nblocks + blockIdx.x];
-    for (int w = 0; w < RS_THREADS / 64; ++w) {
-      const uint32_t cw = cnt[w][d];
-      cnt[w][d] = run;
-      run += cw;
-    }
-  }
-  __syncthreads();
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < RS_WAVE_ITEMS; r += 64) {
-    const uint64_t i = wbase + r + lane;
-    const bool act = i < n;
-    const uint32_t kk = act ? key[i] : 0u;
-    const uint32_t dg = (kk >> shift) & 255u;
-    uint64_t mask = __ballot(act);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot(((dg >> b) & 1u) != 0);
-      mask &= ((dg >> b) & 1u) ? bb : ~bb;
-    }
-    const uint32_t rank = (uint32_t)__popcll(mask & below);
-    const uint32_t tot = (uint32_t)__popcll(mask);
-    uint32_t basev = 0;
-    if (act) basev = cnt[wave][dg];
-    __builtin_amdgcn_wave_barrier();
-    if (act) {
-      const uint32_t pos = basev + rank;
-      lkey[pos] = kk;
-      lidx[pos] = (uint16_t)(i - tbase);
-      if (rank == 0) cnt[wave][dg] = basev + tot;
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  const uint32_t nt = (uint32_t)min((uint64_t)RS_TILE, n - tbase);
-  for (uint32_t j = threadIdx.x; j < nt; j += RS_THREADS) {
-    const uint32_t kk = lkey[j];
-    const uint32_t dg = (kk >> shift) & 255u;
-    const uint32_t pos = gdst[dg] + (j - tile_off[dg]);
-    const uint64_t src = tbase + lidx[j];
-    if (key_out) key_out[pos] = kk;
-    val_out[pos] = vals ? vals[src] : (uint32_t)src;
-    if (pl.on()) {
-      Dir3 d;
-      uint32_t ww;
-      if (pl.rec_in) {
-        const uint4 r = pl.rec_in[src];
-        d = Dir3{__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z)};
-        ww = r.w;
-      } else {
-        d = reinterpret_cast<const Dir3 *>(pl.dir_in)[src];
-        ww = pl.w_in[src];
-      }
-      if (pl.rec_out) {
-        pl.rec_out[pos] = make_uint4(__float_as_uint(d.x), __float_as_uint(d.y), __float_as_uint(d.z), ww);
-      } else {
-        reinterpret_cast<Dir3 *>(pl.dir_out)[pos] = d;
-        pl.w_out[pos] = ww;
-      }
-    }
-  }
-}
-
-// The octree build's scatter: as rs_scatter_kernel, but every item's value
-// and payload travel through LDS with its key, so that all global reads are
-// in item order (coalesced) and all writes are runs of one digit.  1024
-// threads (16 wavefronts of 256 items each, a 4096-item tile as in
-// rs_hist_kernel); each wavefront issues the loads of its four rounds before
-// ranking the first.  PL: the payload (direction + weight) is moved too.
+// Stable scatter of one 4096-item tile of an LSD radix pass (the tile of
+// rs_hist_kernel).  Each item's key, value (the item index when vals is
+// NULL) and payload are read in item order (coalesced), ordered by digit in
+// LDS (ranks from wavefront ballots; waves and rounds in item order, so equal
+// digits keep their input order), then streamed out: consecutive LDS
+// entries of one digit go to consecutive global positions, so the writes
+// form runs instead of single words.  1024 threads (16 wavefronts of 256
+// items each); each wavefront issues the loads of its four rounds before
+// ranking the first.  key_out == NULL: the keys are not written (the last
+// pass).  PL: the payload (a photon's direction and weight, moved with the
+// permutation) is moved too.
 constexpr int RSP_THREADS = 1024;
 constexpr int RSP_WAVES = RSP_THREADS / 64;
 constexpr int RSP_WAVE_ITEMS = RS_TILE / RSP_WAVES;  // 256
@@ -571,8 +465,8 @@ hipError_t npg_radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint
     hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, s, kin, n, 8 * p, nb, hist);
     hipError_t e = scan_u32(hist, nhist, offs, btmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(RS_THREADS), 0, s, kin, vin, n, 8 * p, nb, offs, kout,
-                       vout, Payload{});
+    hipLaunchKernelGGL(rs_scatter_pl_kernel<false>, dim3(nb), dim3(RSP_THREADS), 0, s, kin, vin, n, 8 * p, nb, offs,
+                       kout, vout, Payload{});
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     kin = kout;

@@ -6,9 +6,13 @@ One step = one pass of the whole path over one batch of synthetic input:
   -> build_cdf -> sample_dirs -> eval_pdf (of the sampled directions)
 and, for the clustered workload, build_hierarchy first.
 
-Default workload: the uniform batch -- 1024 leaves x 4096 photons, 64x64
-maps, the 4-level U-Net (16/32/64/128) in FP32, 1,048,576 guided samples.
-The leaf grouping is given by the workload, so no hierarchy is built.
+Default workload: the clustered photons -- 5e7 photons in 64 Gaussian
+clusters, an octree split while a voxel holds more than 8192 photons (depth
+<= 6, 18,595 leaves), 128x128 maps, the 4-level U-Net (16/32/64/128) in FP32
+mode (FP32 weights, FP64 activations and accumulation), 1e8 guided samples;
+the hierarchy is built inside every step. After it, the uniform batch (1024
+leaves x 4096 photons, 64x64 maps, 1,048,576 samples, leaf grouping given)
+is timed the same way and reported under "uniform_batch".
 
 Prints one JSON line (rank 0): leaves reconstructed per second over whole
 steps, guided samples per second of the sampling stage, p50/p99 step
@@ -994,6 +998,54 @@ def calibrate_counters(nbytes: int = 1 << 30, reps: int = 8):
     print(json.dumps({"calibration_copy_bytes": nbytes, "dispatches": reps}))
 
 
+def measure_peaks():
+    """What the chip delivers to library code, beside the published peaks
+    the rooflines divide by: a 4 GiB device copy (HBM), and square GEMMs
+    through torch (rocBLAS / hipBLASLt) in FP64, BF16 and, where torch has
+    it, FP8 e4m3 with FP32 output. Context for the roofline fractions; the
+    fractions themselves stay against the published peaks."""
+    import torch
+    dev = "cuda:0"
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+
+    out = {}
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    t = timed(lambda: y.copy_(x), 10)
+    out["hbm_copy_GBps"] = 2 * 4 * n / t / 1e9
+    del x, y
+    for name, dt, m in (("fp64_gemm_TFLOPs", torch.float64, 8192), ("bf16_gemm_TFLOPs", torch.bfloat16, 16384)):
+        a = torch.randn(m, m, device=dev).to(dt)
+        b = torch.randn(m, m, device=dev).to(dt)
+        t = timed(lambda: torch.matmul(a, b), 5)
+        out[name] = 2 * m ** 3 / t / 1e12
+        del a, b
+    try:
+        m = 16384
+        a = torch.randn(m, m, device=dev).to(torch.float8_e4m3fn)
+        b = torch.randn(m, m, device=dev).to(torch.float8_e4m3fn).t()
+        one = torch.ones((), device=dev)
+        t = timed(lambda: torch._scaled_mm(a, b, scale_a=one, scale_b=one, out_dtype=torch.float32), 5)
+        out["fp8_gemm_TFLOPs"] = 2 * m ** 3 / t / 1e12
+    except Exception as e:   # FP8 GEMM not offered by this torch build
+        out["fp8_gemm_TFLOPs"] = None
+        out["fp8_note"] = f"{type(e).__name__}: {e}"[:200]
+    out["published"] = {k: PEAK[k] for k in ("hbm_GBps", "fp64_mfma_TFLOPs", "bf16_mfma_TFLOPs", "fp8_mfma_TFLOPs")}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1023,9 +1075,13 @@ def main():
                          "valid-bin mask) with a masked first layer; FP32 or BF16")
     ap.add_argument("--calibrate-counters", action="store_true",
                     help="only run 8 device copies of 1 GiB (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure a 4 GiB copy and FP64/BF16/FP8 library GEMMs (context for the rooflines)")
     args = ap.parse_args()
     if args.calibrate_counters:
         return calibrate_counters()
+    if args.peaks:
+        return measure_peaks()
     if args.paper_net:
         args.input5 = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

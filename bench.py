@@ -776,6 +776,35 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
         del normal, u3, outs, pe_m
         return res_
 
+    def grouped_rates(reps=3):
+        """The same queries sorted by leaf (a stable sort outside the timed
+        region), as a caller that groups its path vertices by leaf would
+        issue them: sampling and evaluation rates on the final tables, and a
+        check that every query's result equals its result in random order."""
+        order = torch.sort(q_leaf, stable=True).indices
+        gl, gu = q_leaf[order].contiguous(), q_u[order].contiguous()
+        out = (torch.empty((nq, 3), dtype=torch.float32, device=dev), torch.empty(nq, dtype=torch.float32, device=dev))
+        pe_g = torch.empty(nq, dtype=torch.float32, device=dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        ts, te = [], []
+        for r in range(reps + 1):
+            e0.record(stream)
+            npg.sample_dirs(ctx, tabs, gl, gu, out=(out[0], out[1], None))
+            e1.record(stream)
+            npg.eval_pdf(ctx, tabs, gl, out[0], out=pe_g)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+                te.append(e1.elapsed_time(e2))
+        if npg.sync_status(ctx) != 0:
+            raise RuntimeError("data-dependent error in grouped sampling")
+        same = bool(torch.equal(out[0], sd[0][order]) and torch.equal(out[1], sd[1][order]))
+        del order, gl, gu, out, pe_g
+        return {"samples_per_s": nq / (np.mean(ts) / 1e3), "eval_per_s": nq / (np.mean(te) / 1e3),
+                "sample_ms": float(np.mean(ts)), "same_results_as_random_order": same,
+                "order": "queries stably sorted by leaf before timing"}
+
     per_step, stage_ms = [], {s: [] for s in stages}
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -861,6 +890,7 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
         fused = fused_form(max(3, args.steps // 2))
         print(f"{workload} fused form: {fused['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
     mis = mis_rates()
+    grouped = grouped_rates()
     locate = None
     if pos is not None and args.hierarchy == "kdgrid":
         # point location at render time (outside the timed steps): 2e7 points
@@ -943,6 +973,7 @@ def run_path(args, workload: str, with_baseline: bool = True) -> dict:
         "eval_per_s": nq / (avg["eval"] / 1e3),
         **({"fused_form": fused} if fused else {}),
         "one_sample_mis": mis,
+        "sampling_grouped_by_leaf": grouped,
         **({"kdgrid_locate": locate} if locate else {}),
         "p50_ms": float(np.percentile(per_step, 50)),
         "p99_ms": float(np.percentile(per_step, 99)),
@@ -1101,7 +1132,7 @@ def main():
         # the uniform batch, timed the same way, as an extra key
         u = run_path(args, "uniform", with_baseline=not args.no_cpu_baseline)
         res["uniform_batch"] = {k: u[k] for k in ("value", "unit", "ms_per_step", "samples_per_s", "eval_per_s",
-                                                  "fused_form",
+                                                  "fused_form", "sampling_grouped_by_leaf",
                                                   "p50_ms", "p99_ms", "stage_ms", "stage_roofline", "roofline",
                                                   "config", "sampling_chi2", "precision_vs_fp32", "cpu_baseline")
                                 if k in u}

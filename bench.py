@@ -289,24 +289,41 @@ def host_info() -> dict:
     return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
 
 
-def _oracle_chain(orc, b_dirs, b_w, leaf_off, H, W, model, n_queries, seed, perm=None, input5=None):
+def _oracle_chain(orc, b_dirs, b_w, leaf_off, H, W, model, n_queries, seed, perm=None, input5=None, times=None):
     """The oracle's whole step on a set of leaves: splat -> normalise ->
     network -> CDF -> n_queries guided samples -> pdf of the sampled
-    directions."""
+    directions; `times` (a dict) collects the seconds of each stage."""
+    from paper_2010_01775_amd import synth
+    t = {} if times is None else times
+    mark = [time.perf_counter()]
+
+    def lap(stage):
+        now = time.perf_counter()
+        t[stage] = t.get(stage, 0.0) + now - mark[0]
+        mark[0] = now
+
+    rc, E, P = orc.splat(b_dirs, b_w, leaf_off, H, W, perm=perm)
+    lap("splat")
     if input5 is None:
-        rc, E, P = orc.splat(b_dirs, b_w, leaf_off, H, W, perm=perm)
-        rc, dens = orc.net_forward(model, orc.normalize_input(E))
+        x = orc.normalize_input(E)
+        lap("normalise")
+        rc, dens = orc.net_forward(model, x)
     else:
-        rc, E, P = orc.splat(b_dirs, b_w, leaf_off, H, W, perm=perm)
         Ep, Pp = input5
-        rc, dens = orc.net_forward5(model, orc.input5(E, Ep, P, Pp))
+        x = orc.input5(E, Ep, P, Pp)
+        lap("normalise")
+        rc, dens = orc.net_forward5(model, x)
     assert rc == 0
+    lap("network")
     rc, pdf, marg, cond, total = orc.build_cdf(dens)
     assert rc == 0
-    from paper_2010_01775_amd import synth
+    lap("cdf")
     ql, qu = synth.queries(seed, pdf.shape[0], n_queries)
+    mark[0] = time.perf_counter()   # query generation is not the oracle's work
     rc, d, p, bins = orc.sample(pdf, marg, cond, ql, qu)
+    lap("sample")
     rc, pe = orc.eval_pdf(pdf, ql, d.astype(np.float32))
+    lap("eval")
     return pdf
 
 
@@ -330,12 +347,13 @@ def cpu_baseline_uniform(input5: bool = False, model5: bytes | None = None):
         model = model5 or synth.unet5_model(1003)
         rc, Ep, Pp = orc.splat(b.dirs, b.w, off_p, b.H, b.W, perm=perm_p)   # resident, not timed
         prev = (Ep, Pp)
-    t0 = time.perf_counter()
-    _oracle_chain(orc, b.dirs, b.w, b.leaf_off, b.H, b.W, model, L * 1024, 77, input5=prev)
-    dt = time.perf_counter() - t0
+    stages = {}
+    _oracle_chain(orc, b.dirs, b.w, b.leaf_off, b.H, b.W, model, L * 1024, 77, input5=prev, times=stages)
+    dt = sum(stages.values())
     return {"value": L / dt, "unit": "leaves/s", "cores": min(threads, L), "kind": "oracle",
             "sample": f"{L} leaves x 4096 photons (64x64, {'five-channel ' if input5 else ''}network, FP64) "
                       f"end to end plus {L * 1024} samples and their pdfs; {dt:.1f} s",
+            "stage_s_per_step": {k: v * 1024 / L for k, v in stages.items()},
             "host": host_info()}
 
 
@@ -362,19 +380,20 @@ def cpu_baseline_clustered(cp, model: bytes, L_gpu: int, n_queries: int, subset:
         sub_perm = np.concatenate([tree["perm"][off[l]:off[l + 1]] for l in pick])
         sub_off = np.concatenate([[0], np.cumsum(cnt[pick])]).astype(np.uint32)
         nq = max(1, int(round(n_queries * n_sub / L)))
-        t1 = time.perf_counter()
-        _oracle_chain(orc, cp.dirs, cp.w, sub_off, 128, 128, model, nq, 78, perm=sub_perm)
-        t_sub = time.perf_counter() - t1
+        stages = {}
+        _oracle_chain(orc, cp.dirs, cp.w, sub_off, 128, 128, model, nq, 78, perm=sub_perm, times=stages)
+        t_sub = sum(stages.values())
         t_full = t_tree + t_sub * L / n_sub
-        return L, int(cnt[pick].sum()), nq, t_tree, t_sub, t_full
+        per_step = {"hierarchy": t_tree} | {k: v * L / n_sub for k, v in stages.items()}
+        return L, int(cnt[pick].sum()), nq, t_tree, t_sub, t_full, per_step
 
     threads = _omp()
-    L, ph, nq, t_tree, t_sub, t_full = run(subset)
+    L, ph, nq, t_tree, t_sub, t_full, per_step = run(subset)
     if L != L_gpu:
         raise RuntimeError(f"oracle tree has {L} leaves, the GPU's {L_gpu}")
     _omp(1)
     try:
-        _, ph1, nq1, t_tree1, t_sub1, t_full1 = run(subset_1t)
+        _, ph1, nq1, t_tree1, t_sub1, t_full1, _ = run(subset_1t)
     finally:
         _omp(threads)
     return {"value": L / t_full, "unit": "leaves/s", "cores": threads, "kind": "oracle",
@@ -383,6 +402,7 @@ def cpu_baseline_clustered(cp, model: bytes, L_gpu: int, n_queries: int, subset:
                        f"128x128, FP64; {t_sub:.1f} s); extrapolated to all {L} leaves and 1e8 samples as "
                        f"t_tree + t_subset * {L}/{subset} = {t_full:.1f} s per step"),
             "subset_leaves_per_s": subset / t_sub,
+            "stage_s_per_step": per_step,
             "one_thread": {"value": L / t_full1, "unit": "leaves/s", "cores": 1,
                            "sample": f"octree ({t_tree1:.1f} s) + {subset_1t} stratified leaves "
                                      f"({ph1} photons, {nq1} samples; {t_sub1:.1f} s), extrapolated "

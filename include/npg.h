@@ -326,8 +326,9 @@ int npg_normalize_input(npg_ctx *ctx, const uint64_t *energy_dev, uint32_t L, in
                         float *x_dev, void *stream);
 
 /* Reconstructs the sampling density of every leaf with the network
- * (Sec. 6: S_d = F(S_e); the raw map S_e is the normalised energy map as in
- * npg_normalize_input, computed on the fly).
+ * (Sec. 6: S_d = F(S_e); the raw map S_e is the normalised energy map of
+ * npg_normalize_input, computed on the fly: kept in binary64 in NPG_FP32
+ * mode, rounded to float32 as npg_normalize_input stores it otherwise).
  *   energy_dev  [L][H][W] uint64;  count_dev: reserved for the count input
  *               channels of the paper's five-channel network, may be NULL
  *   density_dev [L][H][W] float32 out, softplus output (>= 0)

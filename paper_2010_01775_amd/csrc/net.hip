@@ -7,8 +7,9 @@
 // and sums (v_mfma_f64_16x16x4f64), softplus in binary64, float32 densities.
 // A float32 accumulation chain over K = 9*Cin terms and 15 layers loses ~3e-5
 // relative accuracy in the output pdf, and float32 activation storage alone
-// ~1e-5 on spiky leaves; with binary64 activations the only roundings left are
-// the float32 input map and output densities.  BF16 mode: bf16 activations
+// ~1e-5 on spiky leaves; with binary64 activations (and the normalised input
+// map formed in binary64 as well) the only rounding left is that of the
+// float32 output densities.  BF16 mode: bf16 activations
 // and weights, float32 accumulation (v_mfma_f32_16x16x32_bf16).
 //   M = output pixels of a tile, N = output channels, K = 9 taps x input
 //   channels.
@@ -414,10 +415,12 @@ template <class T>
 __device__ __forceinline__ double src_raw(const Src &s, int leaf, int y, int x, int c, int H, int W) {
   switch (s.mode) {
     case SRC_ENERGY: {
-      // the raw map is the float32 normalised energy (as npg_normalize_input)
+      // the normalised energy: binary64 in FP32 mode, else rounded to
+      // float32 (as npg_normalize_input stores it)
       const double t = s.tot[leaf];
       const uint64_t e = static_cast<const uint64_t *>(s.s0)[((size_t)leaf * H + y) * W + x];
-      return t > 0.0 ? (double)(float)((double)(H * W) * (double)e / t) : 0.0;
+      const double v = t > 0.0 ? (double)(H * W) * (double)e / t : 0.0;
+      return sizeof(T) == sizeof(double) ? v : (double)(float)v;
     }
     case SRC_POOL: {
       const T *p = static_cast<const T *>(s.s0);
@@ -683,9 +686,11 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint64_t *__restr
   for (int i = threadIdx.x; i < PH * PW; i += 256) {
     const int py = i / PW, px = i - py * PW;
     const int y = ty0 - 1 + py, x = tx0 - 1 + px;
-    float v = 0.0f;  // the float32 normalised energy (as npg_normalize_input)
-    if (y >= 0 && y < H && x >= 0 && x < W && tl > 0.0) v = (float)(hw * (double)e[(size_t)y * W + x] / tl);
-    xs[i] = (Acc)v;
+    // the normalised energy in the accumulation type: binary64 in FP32 mode,
+    // float32 otherwise (as npg_normalize_input stores it)
+    Acc v = (Acc)0;
+    if (y >= 0 && y < H && x >= 0 && x < W && tl > 0.0) v = (Acc)(hw * (double)e[(size_t)y * W + x] / tl);
+    xs[i] = v;
   }
   __syncthreads();
   const int m = threadIdx.x;
@@ -1147,24 +1152,24 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     // input patch with halo: batches of SB loads per thread, then the
     // stores; pooled inputs (four loads per piece) go one piece at a time
     if constexpr (MODE == 2) {
-      // normalised energy x = HW*E/total (float32, zero outside the map) on
-      // the patch plus one more pixel of border, then the first layer's 16
-      // outputs per patch pixel (zero where the pixel is outside the map:
-      // the second layer's zero padding)
+      // normalised energy x = HW*E/total (binary64 in FP32 mode, float32
+      // otherwise; zero outside the map) on the patch plus one more pixel of
+      // border, then the first layer's 16 outputs per patch pixel (zero
+      // where the pixel is outside the map: the second layer's zero padding)
       using A0 = std::conditional_t<P::F64, double, float>;
       const int EW = TW + 4, EH = TR + 4;
-      float *xt = reinterpret_cast<float *>(smem + npg_align(patch_bytes + (size_t)a.wbytes, 16));
+      A0 *xt = reinterpret_cast<A0 *>(smem + npg_align(patch_bytes + (size_t)a.wbytes, 16));
       const int ne = TL * EH * EW;
       const double hw = (double)H * (double)W;
       for (int i = tid; i < ne; i += 256) {
         const int ls = i / (EH * EW), r = i - ls * EH * EW;
         const int ey = r / EW, ex = r - ey * EW;
         const int y = ty0 - 2 + ey, x = tx0 - 2 + ex, leaf = leaf0 + ls;
-        float v = 0.0f;
+        A0 v = (A0)0;
         if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
           const double tl = a.src.tot[leaf];
           if (tl > 0.0)
-            v = (float)(hw * (double)static_cast<const uint64_t *>(a.src.s0)[((size_t)leaf * H + y) * W + x] / tl);
+            v = (A0)(hw * (double)static_cast<const uint64_t *>(a.src.s0)[((size_t)leaf * H + y) * W + x] / tl);
         }
         xt[i] = v;
       }
@@ -1176,7 +1181,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         const int y = ty0 - DIL + py, x = tx0 - DIL + px, leaf = leaf0 + ls;
         T res[KC];  // the pixel's KC channels, written as 16-byte pieces
         if (leaf < a.Lc && y >= 0 && y < H && x >= 0 && x < W) {
-          const float *xp = xt + ls * EH * EW + py * EW + px;
+          const A0 *xp = xt + ls * EH * EW + py * EW + px;
           A0 xv[9];
 #pragma unroll
           for (int k = 0; k < 9; ++k) xv[k] = (A0)xp[(k / 3) * EW + k % 3];
@@ -1547,7 +1552,7 @@ size_t conv_lds_bytes(const Tiling &t, bool first = false) {
   else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
   const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
   const size_t xt = first ? npg_align(patch + wts, 16) - patch - wts +
-                                (size_t)t.TL * (t.TR + 4) * (t.TW + 4) * sizeof(float)
+                                (size_t)t.TL * (t.TR + 4) * (t.TW + 4) * (P::F64 ? sizeof(double) : sizeof(float))
                           : 0;
   return std::max(patch + wts + xt, epi);
 }

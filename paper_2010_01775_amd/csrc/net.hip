@@ -752,7 +752,12 @@ struct F32P {
 };
 // 8-bit and 16-bit traits: a lane's A or B fragment is 8 consecutive K
 // values (channels) of one pixel or output channel; PSTR / KCP are the LDS
-// row strides (elements) of the patch and of the weight tile.
+// row strides (elements) of the patch and of the weight tile, whole 16-byte
+// slots (they are written by LDS loads slot by slot), padded where the 16
+// rows of a fragment read would otherwise share banks (a 64-byte pitch
+// does; the 16- and 32-byte pitches of the 16-channel chunks, read two taps
+// at a time, do not).  SB / SBP: global loads (pooled: windows) in flight
+// per thread where the staging goes through registers.
 struct BF16P {
   using T = uint16_t;
   using WT = uint16_t;
@@ -760,12 +765,12 @@ struct BF16P {
   using Frag = bf16x8;
   static constexpr bool F64 = false, Q8 = false, WGLB = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 1, SPX = 1;
+  static constexpr int SB = 4, SBP = 1;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 struct BF16S : BF16P {
-  static constexpr int KC = KC16S, PSTR = KC + 8, KCP = KC + 8, SPX = 2;
+  static constexpr int KC = KC16S, PSTR = KC, KCP = KC;
 };
 struct FP8P {
   using T = uint8_t;
@@ -774,12 +779,12 @@ struct FP8P {
   using Frag = fp8x8;
   static constexpr bool F64 = false, Q8 = true, WGLB = false;
   static constexpr int KC = KC8, VEC = 16, PSTR = KC + 16, KCP = KC + 16, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 2, SPX = 2;
+  static constexpr int SB = 4, SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
 };
 struct FP8S : FP8P {
-  static constexpr int KC = KC8S, PSTR = KC + 32, KCP = KC + 32, SPX = 4;
+  static constexpr int KC = KC8S, PSTR = KC, KCP = KC;
 };
 
 // n / d for 2 <= d and n * d < 2^32, as a multiply-high by m = ceil(2^32 / d).
@@ -867,6 +872,25 @@ __device__ __forceinline__ ChunkSrc<T> chunk_src(const ConvArgs &a, int leaf0, i
   return cs;
 }
 
+// 16-byte LDS slots [0, nslots) of region lds written straight from global
+// memory (buffer loads with the LDS bit): instruction k of the workgroup,
+// issued by wavefront k % 4, fills slots 64k .. 64k + 63, lane l slot 64k + l,
+// whose source is byte offset off(s) of resource rs (offsets out of range,
+// and slots past nslots, write zeros).  The region is a whole number of
+// 1 KiB blocks.  No registers hold the data, so every load of a chunk is in
+// flight at once; the caller waits on vmcnt and a barrier before reading.
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr size_t DMA_BLOCK = 1024;
+template <class F>
+__device__ __forceinline__ void dma_slots(__amdgpu_buffer_rsrc_t rs, char *lds, int nslots, int wave, int lane, F off) {
+  const int ninst = (nslots + 63) >> 6;
+  for (int k = wave; k < ninst; k += 4) {
+    const int s = k * 64 + lane;
+    const uint32_t o = s < nslots ? off(s) : 0x80000000u;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(lds + (size_t)k * DMA_BLOCK), 16, o, 0, 0, 0);
+  }
+}
+
 // Mean of four 16-byte pieces (the pooling window), rounded to storage.
 template <class P>
 __device__ __forceinline__ uint4 pool_combine(const uint4 &a, const uint4 &b, const uint4 &cc, const uint4 &d) {
@@ -946,14 +970,18 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // fragment read touches fall in different LDS banks.
   constexpr int BNP = BN + ((16 - BN) & 63);
   constexpr int KCP = P::KCP;  // 8/16-bit B tile: [tap][n][KCP]
+  static_assert(IS_F32 || (PSTR * sizeof(T) % 16 == 0 && KCP * sizeof(WT) % 16 == 0),
+                "8/16-bit LDS rows are whole 16-byte slots");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int DIL = X ? a.dil : 1, TW = a.TW, TR = a.TR, TL = a.TL, PW = TW + 2 * DIL, PH = TR + 2 * DIL;
   const int ACT = X ? a.act : ACT_RELU;
   const void *const RES = X ? a.res : nullptr;
   const int H = a.H, W = a.W;
   T *patch = reinterpret_cast<T *>(smem);
-  const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), 16);
+  // 8/16-bit tiles stage the patch and the weights by whole 1 KiB blocks
+  const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), IS_F32 ? 16 : DMA_BLOCK);
   WT *wl = reinterpret_cast<WT *>(smem + patch_bytes);
+  const int wave_u = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   const int tile = blockIdx.x;
   const int grp = tile / a.tiles_per_leaf;
@@ -1129,28 +1157,35 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     }
   }
   const int items = TL * PH * PW * G;
-  for (int ch = 0; ch < (piped ? 0 : a.nchunk); ++ch) {
+  // staging mode 2 reads the first layer's 16 channels: a single chunk, as
+  // a trip count the compiler sees (no loop carries an LDS load to the
+  // first layer's weight reads, which then stay scalar loads)
+  const int nch = piped ? 0 : MODE == 2 ? 16 / KC : a.nchunk;
+  for (int ch = 0; ch < nch; ++ch) {
     const int c0 = ch * KC;
-    // 8/16-bit weights: the first batch is loaded before the patch so that
-    // both arrive in one global round trip
     const WT *wg = static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN;
-    constexpr int WV = 16 / (int)sizeof(WT);  // weights per 16-byte piece
-    constexpr int R8 = IS_F32 ? 1 : KC / WV;
-    constexpr int WITEMS8 = NTAPW * BN * R8;
-    uint4 wv[IS_F32 ? 1 : SB];
-    if constexpr (!IS_F32) {
-#pragma unroll
-      for (int k = 0; k < SB; ++k) {
-        const int it = k * 256 + tid;
-        wv[k] = make_uint4(0, 0, 0, 0);
-        if (it < WITEMS8) {
-          const int row = it / R8, c8 = it - row * R8;
-          if (row < 9 * BN) wv[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * WV);
-        }
+    // 8/16-bit weights [tap][n][KCP] straight into LDS (row padding and the
+    // tenth tap of two-tap chunks are written as zeros), issued before the
+    // patch loads so that both arrive in one global round trip
+    auto stage_w = [&]() {
+      if constexpr (!IS_F32) {
+        constexpr int SPW = KCP * (int)sizeof(WT) / 16, RW = KC * (int)sizeof(WT) / 16;
+        const auto wrs = __builtin_amdgcn_make_buffer_rsrc(const_cast<WT *>(wg), (short)0,
+                                                           9 * BN * KC * (int)sizeof(WT), BUF_WORD3);
+        dma_slots(wrs, reinterpret_cast<char *>(wl), NTAPW * BN * SPW, wave_u, lane, [&](int s) -> uint32_t {
+          const int row = s / SPW, g = s - row * SPW;
+          return g < RW ? (uint32_t)(row * KC * (int)sizeof(WT) + g * 16) : 0x80000000u;
+        });
       }
-    }
-    // input patch with halo: batches of SB loads per thread, then the
-    // stores; pooled inputs (four loads per piece) go one piece at a time
+    };
+    // staging mode 2 issues them after the first layer: the compiler turns
+    // the first layer's weight reads into vector loads (many registers) when
+    // an LDS load precedes them
+    if constexpr (MODE != 2) stage_w();
+    // input patch with halo: straight into LDS for 8/16-bit tiles on plain
+    // or concatenated inputs; otherwise through registers, in batches of SB
+    // loads per thread, then the stores (pooled inputs, four loads per piece,
+    // one piece at a time)
     if constexpr (MODE == 2) {
       // normalised energy x = HW*E/total (binary64 in FP32 mode, float32
       // otherwise; zero outside the map) on the patch plus one more pixel of
@@ -1202,6 +1237,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         for (int v = 0; v < KC * (int)sizeof(T) / 16; ++v)
           reinterpret_cast<uint4 *>(patch + pp * PSTR)[v] = reinterpret_cast<const uint4 *>(res)[v];
       }
+      stage_w();
     } else if constexpr (MODE == 1) {
       constexpr int SBP = P::SBP;  // pooling windows (four loads each) in flight per thread
       // the full-resolution input of the tile's leaves as a buffer resource
@@ -1241,6 +1277,20 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           }
         }
       }
+    } else if constexpr (!IS_F32) {
+      // the patch straight into LDS: PSTR / (16 bytes) slots per pixel, the
+      // first G from the source, the row padding written as zeros (a chunk's
+      // channels come from one source: the concatenation boundary is a
+      // multiple of KC)
+      constexpr int SPP = PSTR * (int)sizeof(T) / 16;
+      const ChunkSrc<T> cs = chunk_src<T>(a, leaf0, c0);
+      dma_slots(cs.rs, reinterpret_cast<char *>(patch), TL * PH * PW * SPP, wave_u, lane, [&](int s) -> uint32_t {
+        const int pp = s / SPP, g = s - pp * SPP;
+        const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
+        const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
+        if (g >= G || g * VEC >= cs.cleft) return 0x80000000u;
+        return cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) + 16u * (uint32_t)g;
+      });
     } else {
       // one offset per patch pixel, then its G 16-byte pieces back to back
       // (a chunk's channels come from one source: the concatenation boundary
@@ -1295,35 +1345,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
       }
     } else {
-      constexpr int WITEMS = WITEMS8;
-#pragma unroll
-      for (int k = 0; k < SB; ++k) {
-        const int it = k * 256 + tid;
-        if (it < WITEMS) {
-          const int row = it / R8, c8 = it - row * R8;
-          *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * WV) = wv[k];
-        }
-      }
-      for (int base = 256 * SB; base < WITEMS; base += 256 * SB) {
-        uint4 v[SB];
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int it = base + k * 256 + tid;
-          v[k] = make_uint4(0, 0, 0, 0);
-          if (it < WITEMS) {
-            const int row = it / R8, c8 = it - row * R8;
-            if (row < 9 * BN) v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * KC + c8 * WV);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int it = base + k * 256 + tid;
-          if (it < WITEMS) {
-            const int row = it / R8, c8 = it - row * R8;
-            *reinterpret_cast<uint4 *>(wl + row * KCP + c8 * WV) = v[k];
-          }
-        }
-      }
+      // the LDS loads of this wavefront have landed; the barrier covers the others'
+      __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
     chunk_taps(ch, wg);
@@ -1397,7 +1420,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
       return;
     }
-    T *ol = reinterpret_cast<T *>(smem);  // [BM][BN]
+    // [BM][OP]: the row padding puts the 16 lanes of a group, which hold
+    // 16 pixels of the same channels, in different LDS banks
+    constexpr int OP = BN + 16 / (int)sizeof(T);
+    T *ol = reinterpret_cast<T *>(smem);
 #pragma unroll
     for (int ni = 0; ni < NW; ++ni) {
       AS bn[4], ws[4];
@@ -1420,7 +1446,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
             q[r] = act_fn(acc[mi][ni][r] + bn[r], ACT);
           }
         }
-        T *o = ol + m * BN + 16 * ni + 4 * lg;  // four consecutive channels: one store
+        T *o = ol + m * OP + 16 * ni + 4 * lg;  // four consecutive channels: one store
         if constexpr (sizeof(T) == 2)
           *reinterpret_cast<uint2 *>(o) = make_uint2((uint32_t)f2bf(q[0]) | ((uint32_t)f2bf(q[1]) << 16),
                                                      (uint32_t)f2bf(q[2]) | ((uint32_t)f2bf(q[3]) << 16));
@@ -1435,7 +1461,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       const int m = i / PPR, pc = i - m * PPR;
       const long g = gpix(m);
       if (g >= 0) {
-        uint4 v = *reinterpret_cast<const uint4 *>(ol + m * BN + pc * (16 / sizeof(T)));
+        uint4 v = *reinterpret_cast<const uint4 *>(ol + m * OP + pc * (16 / sizeof(T)));
         if (RES)
           v = add_res<T>(v, *reinterpret_cast<const uint4 *>(static_cast<const T *>(RES) + g * BN +
                                                              pc * (16 / sizeof(T))));
@@ -1536,7 +1562,7 @@ size_t conv_wts_bytes(const Tiling &t) {
   using WT = typename P::WT;
   const int BN = 16 * t.NW;
   if (P::F64) return P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
-  return (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
+  return npg_align((size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT), DMA_BLOCK);
 }
 
 // first: the energy tile of a fused first layer follows the weights
@@ -1544,13 +1570,12 @@ template <class P>
 size_t conv_lds_bytes(const Tiling &t, bool first = false) {
   using T = typename P::T;
   const int BN = 16 * t.NW;
-  const size_t patch =
-      npg_align((size_t)t.TL * (t.TR + 2 * t.dil) * (t.TW + 2 * t.dil) * P::PSTR * sizeof(T), 16);
-  size_t wts;
-  using WT = typename P::WT;
-  if (P::F64) wts = P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
-  else wts = (size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT);
-  const size_t epi = (size_t)64 * t.MW * BN * sizeof(T);  // output tile staging
+  // 8/16-bit tiles: patch and weights in whole blocks (their LDS loads)
+  const size_t patch = npg_align((size_t)t.TL * (t.TR + 2 * t.dil) * (t.TW + 2 * t.dil) * P::PSTR * sizeof(T),
+                                 P::F64 ? 16 : DMA_BLOCK);
+  const size_t wts = conv_wts_bytes<P>(t);
+  // output tile staging (8/16-bit rows padded by 16 bytes)
+  const size_t epi = (size_t)64 * t.MW * (BN * sizeof(T) + (P::F64 ? 0 : 16));
   const size_t xt = first ? npg_align(patch + wts, 16) - patch - wts +
                                 (size_t)t.TL * (t.TR + 4) * (t.TW + 4) * (P::F64 ? sizeof(double) : sizeof(float))
                           : 0;

@@ -749,28 +749,34 @@ struct F32P {
   // LDS then holds the patch only, which leaves room for more workgroups
   static constexpr bool WGLB = true;
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
+  __device__ static int swz(int) { return 0; }
 };
 // 8-bit and 16-bit traits: a lane's A or B fragment is 8 consecutive K
 // values (channels) of one pixel or output channel; PSTR / KCP are the LDS
 // row strides (elements) of the patch and of the weight tile, whole 16-byte
-// slots (they are written by LDS loads slot by slot), padded where the 16
-// rows of a fragment read would otherwise share banks (a 64-byte pitch
-// does; the 16- and 32-byte pitches of the 16-channel chunks, read two taps
-// at a time, do not).  SB / SBP: global loads (pooled: windows) in flight
-// per thread where the staging goes through registers.
+// slots (they are written by LDS loads slot by slot).  The 16 rows of a
+// fragment read would share LDS banks at a 64-byte pitch (32-channel BF16
+// chunks) and at a 32-byte pitch read 8 bytes at a time (32-channel FP8
+// chunks): there the 16-byte pieces of row p are stored in the order
+// piece ^ swz(p), which spreads them over the banks (the 16-channel chunks,
+// read two taps at a time, need no such order).  SB / SBP: global loads
+// (pooled: windows) in flight per thread where the staging goes through
+// registers.
 struct BF16P {
   using T = uint16_t;
   using WT = uint16_t;
   using Acc = f32x4;
   using Frag = bf16x8;
   static constexpr bool F64 = false, Q8 = false, WGLB = false;
-  static constexpr int KC = KC16, VEC = 8, PSTR = KC + 8, KCP = KC + 8, MAX_TILES = 16;
+  static constexpr int KC = KC16, VEC = 8, PSTR = KC, KCP = KC, MAX_TILES = 16;
   static constexpr int SB = 4, SBP = 1;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
+  __device__ static int swz(int p) { return (p >> 1) & 3; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 struct BF16S : BF16P {
   static constexpr int KC = KC16S, PSTR = KC, KCP = KC;
+  __device__ static int swz(int) { return 0; }
 };
 struct FP8P {
   using T = uint8_t;
@@ -778,13 +784,15 @@ struct FP8P {
   using Acc = f32x4;
   using Frag = fp8x8;
   static constexpr bool F64 = false, Q8 = true, WGLB = false;
-  static constexpr int KC = KC8, VEC = 16, PSTR = KC + 16, KCP = KC + 16, MAX_TILES = 16;
+  static constexpr int KC = KC8, VEC = 16, PSTR = KC, KCP = KC, MAX_TILES = 16;
   static constexpr int SB = 4, SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
+  __device__ static int swz(int p) { return (p >> 2) & 1; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
 };
 struct FP8S : FP8P {
   static constexpr int KC = KC8S, PSTR = KC, KCP = KC;
+  __device__ static int swz(int) { return 0; }
 };
 
 // n / d for 2 <= d and n * d < 2^32, as a multiply-high by m = ceil(2^32 / d).
@@ -1012,6 +1020,14 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = AccV{0, 0, 0, 0};
+  // 8/16-bit tiles: element offset of this lane's fragment (K values lg*8 ..
+  // lg*8 + 7) in LDS row p of the patch or weight tile, whose 16-byte pieces
+  // are stored in the order piece ^ swz(p)
+  constexpr int EPP = 16 / (int)sizeof(T);  // elements per 16-byte piece
+  auto frag_at = [&](int p, int stride) {
+    const int e = lg * 8;
+    return p * stride + (((e / EPP) ^ P::swz(p)) * EPP) + e % EPP;
+  };
 
   // the nine taps of one K chunk on the staged patch (weights wg of the
   // chunk); NT = 4: the four phase-merged taps of an upsampled chunk (mode 3)
@@ -1067,11 +1083,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         using Frag = typename P::Frag;
         Frag av[MW], bv[NW];
 #pragma unroll
-        for (int mi = 0; mi < MW; ++mi)
-          av[mi] = *reinterpret_cast<const Frag *>(patch + (bp[mi] + toff) * PSTR + lg * 8);
+        for (int mi = 0; mi < MW; ++mi) av[mi] = *reinterpret_cast<const Frag *>(patch + frag_at(bp[mi] + toff, PSTR));
 #pragma unroll
         for (int ni = 0; ni < NW; ++ni)
-          bv[ni] = *reinterpret_cast<const Frag *>(wl + (tap * BN + ni * 16 + lr) * KCP + lg * 8);
+          bv[ni] = *reinterpret_cast<const Frag *>(wl + frag_at(tap * BN + ni * 16 + lr, KCP));
 #pragma unroll
         for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
@@ -1164,9 +1179,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   for (int ch = 0; ch < nch; ++ch) {
     const int c0 = ch * KC;
     const WT *wg = static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN;
-    // 8/16-bit weights [tap][n][KCP] straight into LDS (row padding and the
-    // tenth tap of two-tap chunks are written as zeros), issued before the
-    // patch loads so that both arrive in one global round trip
+    // 8/16-bit weights [tap][n][KCP] straight into LDS (slot g of row r holds
+    // piece g ^ swz(r); the tenth tap of two-tap chunks and any row padding
+    // are written as zeros), issued before the patch loads so that both
+    // arrive in one global round trip
     auto stage_w = [&]() {
       if constexpr (!IS_F32) {
         constexpr int SPW = KCP * (int)sizeof(WT) / 16, RW = KC * (int)sizeof(WT) / 16;
@@ -1174,7 +1190,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
                                                            9 * BN * KC * (int)sizeof(WT), BUF_WORD3);
         dma_slots(wrs, reinterpret_cast<char *>(wl), NTAPW * BN * SPW, wave_u, lane, [&](int s) -> uint32_t {
           const int row = s / SPW, g = s - row * SPW;
-          return g < RW ? (uint32_t)(row * KC * (int)sizeof(WT) + g * 16) : 0x80000000u;
+          return g < RW ? (uint32_t)(row * KC * (int)sizeof(WT) + (g ^ P::swz(row)) * 16) : 0x80000000u;
         });
       }
     };
@@ -1235,7 +1251,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
 #pragma unroll
         for (int v = 0; v < KC * (int)sizeof(T) / 16; ++v)
-          reinterpret_cast<uint4 *>(patch + pp * PSTR)[v] = reinterpret_cast<const uint4 *>(res)[v];
+          reinterpret_cast<uint4 *>(patch + pp * PSTR)[v ^ P::swz(pp)] = reinterpret_cast<const uint4 *>(res)[v];
       }
       stage_w();
     } else if constexpr (MODE == 1) {
@@ -1273,23 +1289,26 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           const int it = base + k * 256 + tid;
           if (it < items) {
             const int pp = it / G, g = it - pp * G;
-            *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = pool_combine<P>(q[k][0], q[k][1], q[k][2], q[k][3]);
+            *reinterpret_cast<uint4 *>(patch + pp * PSTR + (g ^ P::swz(pp)) * VEC) =
+                pool_combine<P>(q[k][0], q[k][1], q[k][2], q[k][3]);
           }
         }
       }
     } else if constexpr (!IS_F32) {
-      // the patch straight into LDS: PSTR / (16 bytes) slots per pixel, the
-      // first G from the source, the row padding written as zeros (a chunk's
-      // channels come from one source: the concatenation boundary is a
-      // multiple of KC)
+      // the patch straight into LDS: slot g of pixel p holds the source's
+      // piece g ^ swz(p); slots past the first G of a pixel (row padding,
+      // none at present) are written as zeros.  A chunk's channels come from
+      // one source: the concatenation boundary is a multiple of KC.
       constexpr int SPP = PSTR * (int)sizeof(T) / 16;
       const ChunkSrc<T> cs = chunk_src<T>(a, leaf0, c0);
       dma_slots(cs.rs, reinterpret_cast<char *>(patch), TL * PH * PW * SPP, wave_u, lane, [&](int s) -> uint32_t {
         const int pp = s / SPP, g = s - pp * SPP;
         const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
         const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-        if (g >= G || g * VEC >= cs.cleft) return 0x80000000u;
-        return cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) + 16u * (uint32_t)g;
+        if (g >= G) return 0x80000000u;
+        const int gs = g ^ P::swz(pp);  // the source piece this slot holds
+        if (gs * VEC >= cs.cleft) return 0x80000000u;
+        return cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) + 16u * (uint32_t)gs;
       });
     } else {
       // one offset per patch pixel, then its G 16-byte pieces back to back

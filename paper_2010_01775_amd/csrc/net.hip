@@ -741,9 +741,9 @@ struct F32P {
   using Acc = f64x4;
   static constexpr bool F64 = true, Q8 = false;
   static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, KCP = 0, MAX_TILES = 8;
-  // global loads in flight per thread while staging: SB pieces (pooled: SBP
-  // windows; plain: SPX whole pixels of KC/VEC pieces)
-  static constexpr int SB = 4, SBP = 2, SPX = 1;
+  // global loads in flight per thread while staging through registers: SB
+  // pieces (pooled: SBP windows)
+  static constexpr int SB = 4, SBP = 2;
   // B fragments straight from the packed weights in global memory (L2/L1
   // resident, shared by every workgroup), one tap ahead in registers; the
   // LDS then holds the patch only, which leaves room for more workgroups
@@ -986,8 +986,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   const void *const RES = X ? a.res : nullptr;
   const int H = a.H, W = a.W;
   T *patch = reinterpret_cast<T *>(smem);
-  // 8/16-bit tiles stage the patch and the weights by whole 1 KiB blocks
-  const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), IS_F32 ? 16 : DMA_BLOCK);
+  // the patch (and the 8/16-bit weights) staged by whole 1 KiB blocks
+  const size_t patch_bytes = npg_align((size_t)TL * PH * PW * PSTR * sizeof(T), DMA_BLOCK);
   WT *wl = reinterpret_cast<WT *>(smem + patch_bytes);
   const int wave_u = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
@@ -1173,8 +1173,9 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   }
   const int items = TL * PH * PW * G;
   // staging mode 2 reads the first layer's 16 channels: a single chunk, as
-  // a trip count the compiler sees (no loop carries an LDS load to the
-  // first layer's weight reads, which then stay scalar loads)
+  // a trip count the compiler sees (with a loop around them, the LDS loads
+  // would turn the first layer's weight reads into vector loads held in
+  // many registers)
   const int nch = piped ? 0 : MODE == 2 ? 16 / KC : a.nchunk;
   for (int ch = 0; ch < nch; ++ch) {
     const int c0 = ch * KC;
@@ -1194,10 +1195,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         });
       }
     };
-    // staging mode 2 issues them after the first layer: the compiler turns
-    // the first layer's weight reads into vector loads (many registers) when
-    // an LDS load precedes them
-    if constexpr (MODE != 2) stage_w();
+    stage_w();
     // input patch with halo: straight into LDS for 8/16-bit tiles on plain
     // or concatenated inputs; otherwise through registers, in batches of SB
     // loads per thread, then the stores (pooled inputs, four loads per piece,
@@ -1208,6 +1206,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       // border, then the first layer's 16 outputs per patch pixel (zero
       // where the pixel is outside the map: the second layer's zero padding)
       using A0 = std::conditional_t<P::F64, double, float>;
+      // the first layer's weights read as constant memory: scalar loads,
+      // although the LDS loads issued above are in flight
+      using CF = const __attribute__((address_space(4))) float;
+      CF *w0 = (CF *)a.w0, *b0 = (CF *)a.b0;
       const int EW = TW + 4, EH = TR + 4;
       A0 *xt = reinterpret_cast<A0 *>(smem + npg_align(patch_bytes + (size_t)a.wbytes, 16));
       const int ne = TL * EH * EW;
@@ -1239,9 +1241,9 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
           for (int cc = 0; cc < KC; ++cc) {  // this chunk's channels c0 .. c0 + KC - 1
             const int c = c0 + cc;
-            A0 acc0 = (A0)a.b0[c];
+            A0 acc0 = (A0)b0[c];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc0 = fma((A0)a.w0[c * 9 + k], xv[k], acc0);
+            for (int k = 0; k < 9; ++k) acc0 = fma((A0)w0[c * 9 + k], xv[k], acc0);
             const A0 rl = acc0 > (A0)0 ? acc0 : (A0)0;
             res[cc] = from_d<T>(sizeof(T) == 1 ? (double)(rl * (A0)a.oinv0) : (double)rl);
           }
@@ -1253,7 +1255,6 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         for (int v = 0; v < KC * (int)sizeof(T) / 16; ++v)
           reinterpret_cast<uint4 *>(patch + pp * PSTR)[v ^ P::swz(pp)] = reinterpret_cast<const uint4 *>(res)[v];
       }
-      stage_w();
     } else if constexpr (MODE == 1) {
       constexpr int SBP = P::SBP;  // pooling windows (four loads each) in flight per thread
       // the full-resolution input of the tile's leaves as a buffer resource
@@ -1294,7 +1295,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
           }
         }
       }
-    } else if constexpr (!IS_F32) {
+    } else {
       // the patch straight into LDS: slot g of pixel p holds the source's
       // piece g ^ swz(p); slots past the first G of a pixel (row padding,
       // none at present) are written as zeros.  A chunk's channels come from
@@ -1310,36 +1311,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         if (gs * VEC >= cs.cleft) return 0x80000000u;
         return cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) + 16u * (uint32_t)gs;
       });
-    } else {
-      // one offset per patch pixel, then its G 16-byte pieces back to back
-      // (a chunk's channels come from one source: the concatenation boundary
-      // is a multiple of KC)
-      constexpr int SPX = P::SPX;  // pixels per thread per batch
-      const int npx = TL * PH * PW;
-      const ChunkSrc<T> cs = chunk_src<T>(a, leaf0, c0);
-      for (int base = 0; base < npx; base += 256 * SPX) {
-        uint4 v[SPX][G];
-#pragma unroll
-        for (int k = 0; k < SPX; ++k) {
-          const int pp = base + k * 256 + tid;
-          const int ls = (int)fdiv((uint32_t)pp, a.fPP), pr = pp - ls * PH * PW;
-          const int py = (int)fdiv((uint32_t)pr, a.fPW), px = pr - py * PW;
-          const uint32_t o = pp < npx ? cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) : 0x80000000u;
-#pragma unroll
-          for (int g = 0; g < G; ++g) v[k][g] = g * VEC < cs.cleft ? cs.load(o + 16 * g) : make_uint4(0, 0, 0, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < SPX; ++k) {
-          const int pp = base + k * 256 + tid;
-          if (pp < npx) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) *reinterpret_cast<uint4 *>(patch + pp * PSTR + g * VEC) = v[k][g];
-          }
-        }
-      }
     }
     // weights of this chunk
     if constexpr (WGLB) {
+      __builtin_amdgcn_s_waitcnt(0);  // the patch's LDS loads of this wavefront
     } else if (IS_F32) {
       constexpr int R4 = BN / 4;  // float4 per row
       constexpr int WITEMS = 9 * KC * R4;
@@ -1589,9 +1564,9 @@ template <class P>
 size_t conv_lds_bytes(const Tiling &t, bool first = false) {
   using T = typename P::T;
   const int BN = 16 * t.NW;
-  // 8/16-bit tiles: patch and weights in whole blocks (their LDS loads)
+  // patch (and 8/16-bit weights) in whole blocks (their LDS loads)
   const size_t patch = npg_align((size_t)t.TL * (t.TR + 2 * t.dil) * (t.TW + 2 * t.dil) * P::PSTR * sizeof(T),
-                                 P::F64 ? 16 : DMA_BLOCK);
+                                 DMA_BLOCK);
   const size_t wts = conv_wts_bytes<P>(t);
   // output tile staging (8/16-bit rows padded by 16 bytes)
   const size_t epi = (size_t)64 * t.MW * (BN * sizeof(T) + (P::F64 ? 0 : 16));

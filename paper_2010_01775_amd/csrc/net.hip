@@ -826,6 +826,10 @@ struct ConvArgs {
   int dil = 1;           // tap spacing (dilated convolutions); the patch halo is dil pixels
   int act = 0;           // ACT_RELU or ACT_ELU (8/16-bit and FP64 tiles without a fused head)
   const void *res = nullptr;  // residual added after the activation, same layout as out
+  // non-null (plain tile order, no residual, even TR and TW): also store the
+  // 2x2 means of the stored tile, [leaf][H/2][W/2][Cout], the next level's
+  // pooled input, with the pooled staging's arithmetic
+  void *pool_out = nullptr;
 };
 
 // The input channels of one K chunk (plain or upsampled + concatenated
@@ -957,6 +961,29 @@ __device__ __forceinline__ uint4 add_res(uint4 v, uint4 r) {
   for (int i = 0; i < N; ++i) x[i] = from_d<T>(to_d<T>(x[i]) + to_d<T>(y[i]));
   __builtin_memcpy(&v, x, 16);
   return v;
+}
+
+// The 2x2 means of a stored output tile staged in LDS (rows of op elements,
+// tile pixel m = leaf * TR * TW + row * TW + column): pool_combine of the
+// four stored 16-byte pieces, exactly what the pooled staging of the next
+// layer would compute from them, stored [leaf][H/2][W/2][BN].
+template <class P, int BN>
+__device__ __forceinline__ void store_pooled(const ConvArgs &a, const typename P::T *ol, int op, int leaf0, int ty0,
+                                             int tx0) {
+  using T = typename P::T;
+  constexpr int EPP = 16 / (int)sizeof(T), PPR = BN / EPP;
+  const int TW2 = a.TW >> 1, Q = (a.TR >> 1) * TW2, TPX = a.TR * a.TW;
+  T *po = static_cast<T *>(a.pool_out);
+  for (int i = threadIdx.x; i < a.TL * Q * PPR; i += 256) {
+    const int q = i / PPR, pc = i - q * PPR;
+    const int ls = q / Q, r = q - ls * Q, qy = r / TW2, qx = r - qy * TW2;
+    if (leaf0 + ls >= a.Lc) continue;
+    const int m = ls * TPX + 2 * qy * a.TW + 2 * qx;
+    auto at = [&](int mm) { return *reinterpret_cast<const uint4 *>(ol + mm * op + pc * EPP); };
+    const uint4 v = pool_combine<P>(at(m), at(m + 1), at(m + a.TW), at(m + a.TW + 1));
+    const long g = ((long)(leaf0 + ls) * (a.H >> 1) + (ty0 >> 1) + qy) * (a.W >> 1) + (tx0 >> 1) + qx;
+    *reinterpret_cast<uint4 *>(po + g * BN + pc * EPP) = v;
+  }
 }
 
 // X: the extended form (dilation, ELU, residual link); without it the
@@ -1462,6 +1489,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) = v;
       }
     }
+    if constexpr (MODE != 3)
+      if (a.pool_out) store_pooled<P, BN>(a, ol, OP, leaf0, ty0, tx0);
     return;
   }
   if (a.head_w) {
@@ -1542,6 +1571,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       *reinterpret_cast<uint4 *>(out + g * BN + pc * (16 / sizeof(T))) = v;
     }
   }
+  if constexpr (MODE != 3)
+    if (a.pool_out) store_pooled<P, BN>(a, ol, BN, leaf0, ty0, tx0);
 }
 
 // Tiling of a layer: returns false if the MFMA kernel does not fit it.
@@ -1701,6 +1732,7 @@ struct Runner {
   int fuse_first = 1;                        // first layer inside the second layer's staging
   unsigned *amax = nullptr;                  // calibration: per-call max of the stored output
                                              // (float bits); the head is then not fused
+  bool pooled = false;                       // the last conv also stored its output's 2x2 means
 
   int cap() const {
     int c = mw_all;
@@ -1750,7 +1782,8 @@ struct Runner {
   }
 
   int conv_first_fused(const LayerDev &l0, const LayerDev &l1, const Src &energy, int Lc, int H, int W,
-                       void *out) {
+                       void *out, void *pool_out = nullptr) {
+    pooled = false;
     if (ev) {
       if (hipEventRecord((*ev)[2 * call], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
     }
@@ -1782,6 +1815,10 @@ struct Runner {
     a.b0 = l0.b;
     a.oinv0 = prec == NPG_FP8 ? 1.0f / l0.a8 : 1.0f;
     a.out = out;
+    if (pool_out && t.TR % 2 == 0 && t.TW % 2 == 0) {
+      a.pool_out = pool_out;
+      pooled = true;
+    }
     const unsigned tiles = (unsigned)((Lc + t.TL - 1) / t.TL) * a.tiles_per_leaf;
     // layer 1 on the matrix cores; layer 0 recomputed on the vector ALUs for
     // every patch pixel (the tile and its one-pixel halo)
@@ -1808,12 +1845,24 @@ struct Runner {
 
   // res: a tensor of the output's layout added after the activation (a
   // residual link), or null
+  // the pooled output of a plain-order tile (no phase order, head or
+  // residual) with even TR and TW
+  void set_pool(ConvArgs &a, const Tiling &t, void *pool_out) {
+    if (pool_out && !a.wpp && !a.head_w && !a.res && t.TR % 2 == 0 && t.TW % 2 == 0) {
+      a.pool_out = pool_out;
+      pooled = true;
+    }
+  }
+  // pool_out: where to store the 2x2 means of the output as well (the next
+  // level's pooled input), if the layer's tiles can; `pooled` tells whether
+  // they did
   int conv(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
-           int act, const void *res = nullptr) {
+           int act, const void *res = nullptr, void *pool_out = nullptr) {
+    pooled = false;
     if (ev) {
       if (hipEventRecord((*ev)[2 * call], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
     }
-    int rc = conv_impl(y, src, Lc, H, W, out, head, act, res);
+    int rc = conv_impl(y, src, Lc, H, W, out, head, act, res, pool_out);
     if (ev && !rc) {
       if (hipEventRecord((*ev)[2 * call + 1], s) != hipSuccess) return npg_fail(ctx, NPG_E_HIP, "event record");
     }
@@ -1833,7 +1882,7 @@ struct Runner {
 
   // One 3x3 conv (+ReLU / ELU, + residual) or the last layer (+head / softplus).
   int conv_impl(const LayerDev &y, const Src &src, int Lc, int H, int W, void *out, const LayerDev *head,
-                int act, const void *res) {
+                int act, const void *res, void *pool_out) {
     if ((act == ACT_ELU || res || y.dil != 1) && (prec == NPG_FP8 || head))
       return npg_fail(ctx, NPG_E_ARG, "internal: ELU, residual and dilated layers run in FP32 or BF16, unfused");
     Tiling t;
@@ -1881,26 +1930,31 @@ struct Runner {
           taps_x_cin = 4.0 * src.C0 + 9.0 * src.C1;
         }
         ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
+        set_pool(a, t, pool_out);
         e = launch_mfma<F32P>(a, t, tiles, s);
       } else if (prec == NPG_FP8 && y.cin % KC8 == 0) {
         ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = y.cin / KC8;
         a.wpk = y.pk8;
+        set_pool(a, t, pool_out);
         e = launch_mfma<FP8P>(a, t, tiles, s);
       } else if (prec == NPG_FP8) {
         ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = (y.cin + KC8S - 1) / KC8S;
         a.wpk = y.pk8s;
+        set_pool(a, t, pool_out);
         e = launch_mfma<FP8S>(a, t, tiles, s);
       } else if (y.cin % KC16 == 0) {
         ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = y.cin / KC16;
         a.wpk = y.pk16;
+        set_pool(a, t, pool_out);
         e = launch_mfma<BF16P>(a, t, tiles, s);
       } else {
         ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;
         a.nchunk = (y.cin + KC16S - 1) / KC16S;
         a.wpk = y.pk16s;
+        set_pool(a, t, pool_out);
         e = launch_mfma<BF16S>(a, t, tiles, s);
       }
       if (head) ctx->conv_flops[1] += 2.0 * px * head->cin;  // 1x1 head in the epilogue
@@ -2024,6 +2078,7 @@ struct NetPlan {
   size_t per_leaf = 0;              // bytes
   std::vector<size_t> skip_elems;   // U-Net skip tensors (elements per leaf)
   size_t tmp_elems = 0;             // each of the two ping-pong buffers
+  bool pool = false;                // U-Net: the skip tensors' 2x2 means too (a quarter each)
 };
 
 NetPlan plan_net(const npg_model *m, int H, int W, size_t esz) {
@@ -2040,25 +2095,29 @@ NetPlan plan_net(const npg_model *m, int H, int W, size_t esz) {
     p.tmp_elems = std::max(p.tmp_elems, e);
     if (d < D - 1) p.skip_elems.push_back(e);
   }
-  for (size_t e : p.skip_elems) p.per_leaf += npg_align(e * esz, 64);
+  p.pool = m->arch == 2;
+  for (size_t e : p.skip_elems) p.per_leaf += npg_align(e * esz, 64) + (p.pool ? npg_align(e / 4 * esz, 64) : 0);
   p.per_leaf += 2 * npg_align(p.tmp_elems * esz, 64);
   return p;
 }
 
 struct NetBufs {
   std::vector<char *> skip;
+  std::vector<char *> pool;  // 2x2 means of each skip tensor (U-Net), or empty
   char *tA = nullptr, *tB = nullptr;
 };
 
 size_t net_bufs_bytes(const NetPlan &p, size_t chunk, size_t esz) {
   size_t b = 0;
-  for (size_t e : p.skip_elems) b += npg_align(chunk * e * esz);
+  for (size_t e : p.skip_elems) b += npg_align(chunk * e * esz) + (p.pool ? npg_align(chunk * (e / 4) * esz) : 0);
   return b + 2 * npg_align(chunk * p.tmp_elems * esz);
 }
 
 NetBufs carve_net(Carver &cv, const NetPlan &p, size_t chunk, size_t esz) {
   NetBufs B;
   for (size_t e : p.skip_elems) B.skip.push_back(cv.take<char>(chunk * e * esz));
+  if (p.pool)
+    for (size_t e : p.skip_elems) B.pool.push_back(cv.take<char>(chunk * (e / 4) * esz));
   B.tA = cv.take<char>(chunk * p.tmp_elems * esz);
   B.tB = cv.take<char>(chunk * p.tmp_elems * esz);
   return B;
@@ -2157,25 +2216,29 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
   const void *prev = nullptr;
   int prevC = 0;
   float prevQ = 1.0f;
+  bool have_pool = false;  // the level above stored its output's 2x2 means
   for (int d = 0; d < D; ++d) {  // encoder
     const LayerDev &la = m->layer[2 * d], &lb = m->layer[2 * d + 1];
     Src sa = in;
     if (d > 0) {
       h /= 2;
       w /= 2;
-      sa = pooled(prev, prevC, prevQ);
+      sa = have_pool ? plain(B.pool[d - 1], prevC, prevQ) : pooled(prev, prevC, prevQ);
     }
     void *ob = d < D - 1 ? (void *)B.skip[d] : (void *)B.tB;
+    // the level's output tile also stores its 2x2 means, the next level's input
+    void *po = d < D - 1 && !B.pool.empty() ? (void *)B.pool[d] : nullptr;
     Tiling tf;
     if (d == 0 && R.first_fusable(la, lb, h, w, &tf)) {
-      rc = R.conv_first_fused(la, lb, sa, Lc, h, w, ob);
+      rc = R.conv_first_fused(la, lb, sa, Lc, h, w, ob, po);
       if (rc) return rc;
     } else {
       rc = R.conv(la, sa, Lc, h, w, B.tA, nullptr, ACT_RELU);
       if (rc) return rc;
-      rc = R.conv(lb, plain(B.tA, la.cout, dq(la)), Lc, h, w, ob, nullptr, ACT_RELU);
+      rc = R.conv(lb, plain(B.tA, la.cout, dq(la)), Lc, h, w, ob, nullptr, ACT_RELU, nullptr, po);
       if (rc) return rc;
     }
+    have_pool = po && R.pooled;
     prev = ob;
     prevC = lb.cout;
     prevQ = dq(lb);

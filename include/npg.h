@@ -124,6 +124,10 @@ void npg_conv_flops(npg_ctx *ctx, double *matrix, double *vector, int reset);
  *   "fuse_first"   0: store the first layer's activations instead of
  *                  computing them inside the second layer's input staging
  *                  (default 1; the results are identical)
+ *   "pool_outputs" 0: each U-Net encoder level pools the level above's
+ *                  stored output while staging it, instead of reading the
+ *                  2x2 means that level stored beside its output (default
+ *                  1; the results are identical)
  *   "upsample_taps9" 1: FP32-mode decoder convolutions take all nine taps on
  *                  their nearest-upsampled channels instead of four
  *                  phase-merged taps per output phase (testing; default 0;

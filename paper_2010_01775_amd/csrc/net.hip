@@ -1730,6 +1730,7 @@ struct Runner {
   std::vector<hipEvent_t> *ev = nullptr;     // per-call begin/end events (autotuner)
   int call = 0;                              // conv call index within a chunk
   int fuse_first = 1;                        // first layer inside the second layer's staging
+  int pool_outputs = 1;                      // U-Net levels store their output's 2x2 means too
   unsigned *amax = nullptr;                  // calibration: per-call max of the stored output
                                              // (float bits); the head is then not fused
   bool pooled = false;                       // the last conv also stored its output's 2x2 means
@@ -2227,7 +2228,7 @@ int net_chunk(Runner &R, const Src &in, int Lc, int H, int W, float *dens, const
     }
     void *ob = d < D - 1 ? (void *)B.skip[d] : (void *)B.tB;
     // the level's output tile also stores its 2x2 means, the next level's input
-    void *po = d < D - 1 && !B.pool.empty() ? (void *)B.pool[d] : nullptr;
+    void *po = d < D - 1 && R.pool_outputs && !B.pool.empty() ? (void *)B.pool[d] : nullptr;
     Tiling tf;
     if (d == 0 && R.first_fusable(la, lb, h, w, &tf)) {
       rc = R.conv_first_fused(la, lb, sa, Lc, h, w, ob, po);
@@ -2312,6 +2313,7 @@ Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStre
   R.force_direct = (int)ctx->opt("force_direct", 0);
   R.upsample_taps9 = (int)ctx->opt("upsample_taps9", 0);
   R.fuse_first = ctx->opt("fuse_first", 1) ? 1 : 0;
+  R.pool_outputs = ctx->opt("pool_outputs", 1) ? 1 : 0;
   return R;
 }
 

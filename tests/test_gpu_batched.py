@@ -176,3 +176,27 @@ def test_fused_first_layer_equals_separate(ctx, npg, prec, H, L, arch):
     assert npg.sync_status(ctx) == 0
     assert torch.equal(ref, got)
     m.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("H,L", [(64, 37), (16, 21), (128, 5), (8, 13)])
+def test_pooled_outputs_equal_pooled_staging(ctx, npg, prec, H, L):
+    """The 2x2 means an encoder level stores beside its output give the next
+    level the same bits as pooling that output while staging it (ragged last
+    tile, an empty leaf, maps small enough for whole-leaf tiles and for the
+    direct path at the deepest levels)."""
+    m = npg.Model(ctx, synth.unet_model(23, random_bias=True))
+    b = synth.uniform_batch(seed=41 + H, L=L, per_leaf=3000, H=H, W=H, n_queries=8, model=b"")
+    e, _ = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), H, H, want_count=False)
+    e[L // 3].zero_()
+    if prec == "fp8":
+        m.calibrate_fp8(e)
+    ctx.set_option("pool_outputs", 0)
+    try:
+        ref = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    finally:
+        ctx.set_option("pool_outputs", 1)
+    got = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    assert npg.sync_status(ctx) == 0
+    assert torch.equal(ref, got)
+    m.free()

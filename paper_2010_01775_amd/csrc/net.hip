@@ -1613,6 +1613,7 @@ template <class P>
 bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4, int dil = 1) {
   if (Cout % 16 || Cout > 128) return false;
   const int NW = Cout / 16;
+  if (NW & (NW - 1)) return false;  // 1, 2, 4 or 8 tiles of 16 output channels (the launched forms)
   if (NW > P::MAX_TILES) return false;
   const int HW = H * W;
   for (int MW = 8; MW >= 1; MW >>= 1) {

@@ -741,9 +741,9 @@ struct F32P {
   using Acc = f64x4;
   static constexpr bool F64 = true, Q8 = false;
   static constexpr int KC = KC32, VEC = 2, PSTR = KC + 2, KCP = 0, MAX_TILES = 8;
-  // global loads in flight per thread while staging through registers: SB
-  // pieces (pooled: SBP windows)
-  static constexpr int SB = 4, SBP = 2;
+  // pooling windows (four loads each) in flight per thread in the pooled
+  // staging, the one staging that goes through registers
+  static constexpr int SBP = 2;
   // B fragments straight from the packed weights in global memory (L2/L1
   // resident, shared by every workgroup), one tap ahead in registers; the
   // LDS then holds the patch only, which leaves room for more workgroups
@@ -759,9 +759,8 @@ struct F32P {
 // chunks) and at a 32-byte pitch read 8 bytes at a time (32-channel FP8
 // chunks): there the 16-byte pieces of row p are stored in the order
 // piece ^ swz(p), which spreads them over the banks (the 16-channel chunks,
-// read two taps at a time, need no such order).  SB / SBP: global loads
-// (pooled: windows) in flight per thread where the staging goes through
-// registers.
+// read two taps at a time, need no such order).  SBP: pooling windows in
+// flight per thread in the pooled staging, which goes through registers.
 struct BF16P {
   using T = uint16_t;
   using WT = uint16_t;
@@ -769,7 +768,7 @@ struct BF16P {
   using Frag = bf16x8;
   static constexpr bool F64 = false, Q8 = false, WGLB = false;
   static constexpr int KC = KC16, VEC = 8, PSTR = KC, KCP = KC, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 1;
+  static constexpr int SBP = 1;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static int swz(int p) { return (p >> 1) & 3; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
@@ -785,7 +784,7 @@ struct FP8P {
   using Frag = fp8x8;
   static constexpr bool F64 = false, Q8 = true, WGLB = false;
   static constexpr int KC = KC8, VEC = 16, PSTR = KC, KCP = KC, MAX_TILES = 16;
-  static constexpr int SB = 4, SBP = 2;
+  static constexpr int SBP = 2;
   __device__ static int row(int lg, int r) { return 4 * lg + r; }
   __device__ static int swz(int p) { return (p >> 2) & 1; }
   __device__ static Acc mma(Frag a, Frag b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
@@ -994,16 +993,13 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   using AccV = typename P::Acc;
   using AS = std::remove_cv_t<std::remove_reference_t<decltype(AccV{}[0])>>;
   constexpr int KC = P::KC, VEC = P::VEC, PSTR = P::PSTR, G = KC / VEC;
-  constexpr int SB = P::SB;  // global loads in flight per thread while staging
   constexpr int BN = 16 * NW;
   using WT = typename P::WT;
   constexpr bool IS_F32 = P::F64;                // FP32 weights, FP64 activations and sums
   constexpr bool WGLB = P::WGLB;                 // B fragments from global memory
+  static_assert(WGLB == IS_F32, "FP64 tiles read their weights from global memory, 8/16-bit tiles from LDS");
   constexpr bool TWO_TAP = !IS_F32 && KC == 16;  // K slice = 2 taps x 16 channels
   constexpr int NTAPW = TWO_TAP ? 10 : 9;        // weight taps in LDS (10th = zeros)
-  // FP32 B tile: [tap][kc][BNP], row stride chosen so the four k-rows a
-  // fragment read touches fall in different LDS banks.
-  constexpr int BNP = BN + ((16 - BN) & 63);
   constexpr int KCP = P::KCP;  // 8/16-bit B tile: [tap][n][KCP]
   static_assert(IS_F32 || (PSTR * sizeof(T) % 16 == 0 && KCP * sizeof(WT) % 16 == 0),
                 "8/16-bit LDS rows are whole 16-byte slots");
@@ -1098,8 +1094,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
             av[mi] = (double)patch[(bp[mi] + toff) * PSTR + ks * 4 + lg];
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni)
-            bv[ni] = WGLB ? (double)wcur[WGLB ? ks : 0][WGLB ? ni : 0]
-                          : (double)wl[(tap * KC + ks * 4 + lg) * BNP + ni * 16 + lr];
+            bv[ni] = (double)wcur[WGLB ? ks : 0][WGLB ? ni : 0];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
@@ -1339,36 +1334,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         return cs.off(ls, ty0 - DIL + py, tx0 - DIL + px, H, W) + 16u * (uint32_t)gs;
       });
     }
-    // weights of this chunk
-    if constexpr (WGLB) {
-      __builtin_amdgcn_s_waitcnt(0);  // the patch's LDS loads of this wavefront
-    } else if (IS_F32) {
-      constexpr int R4 = BN / 4;  // float4 per row
-      constexpr int WITEMS = 9 * KC * R4;
-      for (int base = 0; base < WITEMS; base += 256 * SB) {
-        uint4 v[SB];
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int it = base + k * 256 + tid;
-          v[k] = make_uint4(0, 0, 0, 0);
-          if (it < WITEMS) {
-            const int row = it / R4, c4 = it - row * R4;
-            v[k] = *reinterpret_cast<const uint4 *>(wg + (size_t)row * BN + c4 * 4);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int it = base + k * 256 + tid;
-          if (it < WITEMS) {
-            const int row = it / R4, c4 = it - row * R4;
-            *reinterpret_cast<uint4 *>(wl + row * BNP + c4 * 4) = v[k];
-          }
-        }
-      }
-    } else {
-      // the LDS loads of this wavefront have landed; the barrier covers the others'
-      __builtin_amdgcn_s_waitcnt(0);
-    }
+    // the LDS loads of this wavefront have landed; the barrier covers the others'
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     chunk_taps(ch, wg);
     __syncthreads();
@@ -1586,7 +1553,7 @@ template <class P>
 size_t conv_wts_bytes(const Tiling &t) {
   using WT = typename P::WT;
   const int BN = 16 * t.NW;
-  if (P::F64) return P::WGLB ? 0 : (size_t)9 * P::KC * (BN + ((16 - BN) & 63)) * sizeof(WT);
+  if (P::F64) return 0;  // FP64 tiles read their weights from global memory
   return npg_align((size_t)(P::KC == 16 ? 10 : 9) * BN * P::KCP * sizeof(WT), DMA_BLOCK);
 }
 

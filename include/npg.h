@@ -402,7 +402,10 @@ int npg_reconstruct_experts(npg_ctx *ctx, const npg_model *const *models, int n_
                             uint32_t L, int H, int W, npg_precision precision, float *density_dev,
                             uint32_t *counts_out, void *stream);
 
-/* The batched form of the path: splat -> normalise -> network -> CDF for a
+/* The batched form of the path (Sec. 7.2, sampling map reconstruction: after
+ * an iteration's photons are traced, every valid voxel that received new
+ * photons gets its map reconstructed by the network, as one batch): splat ->
+ * normalise -> network -> CDF for a
  * batch of leaves of uneven photon counts, processed in chunks whose energy
  * maps and densities live only in library scratch (the per-leaf maps of the
  * whole batch are never written).  Arguments as in npg_splat_histograms,
@@ -515,7 +518,10 @@ int npg_eval_pdf_mis(npg_ctx *ctx, const npg_tables *tables, const float *alpha_
 /* ---------------------------------------------------------------- serving */
 
 /* A server takes reconstruction and sampling requests as a render loop emits
- * them and runs them with continuous batching: a scheduler thread owns
+ * them (Algorithm 1 and Sec. 7: each iteration traces photons, reconstructs
+ * the maps of the voxels they reached, then guides the iteration's paths by
+ * sampling those maps, Sec. 7.3) and runs them with continuous batching: a
+ * scheduler thread owns
  * n_slots device streams; whenever one is free it launches the oldest
  * waiting request, merged with every later waiting reconstruction of the
  * same map size (up to max_batch_leaves leaves, as long as their tables fit

@@ -540,12 +540,10 @@ static int build_hierarchy(npg_ctx *ctx, const float *pos_dev, uint64_t n, const
                        lds_hist ? nullptr : cnt, ctx->err_dev);
   NPG_HIP_CHECK(ctx, hipGetLastError());
   if (n && lds_hist) {
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<uint64_t> attr{0};
+    if (npg_first_on_device(attr))
       NPG_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cell_hist_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, HIST_RANGE * 4));
-      attr = true;
-    }
     // about 1024 workgroups; slices of at least 16k photons, multiples of 4
     const uint64_t slices = std::max<uint64_t>(1, std::min<uint64_t>(1024 / nranges, (n + 16383) / 16384));
     const uint64_t per_slice = ((n + slices - 1) / slices + 3) & ~(uint64_t)3;

@@ -1617,12 +1617,11 @@ bool pick_tiling(int Cout, int H, int W, Tiling *t, int mw_max = 4, int dil = 1)
 
 template <class P, int MW, int NW, int MODE, bool X>
 hipError_t launch_mfma_kx(const ConvArgs &a, size_t lds, unsigned tiles, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
+  static std::atomic<uint64_t> attr{0};
+  if (npg_first_on_device(attr)) {
     hipError_t e = hipFuncSetAttribute((const void *)conv_mfma_kernel<P, MW, NW, MODE, X>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   hipLaunchKernelGGL((conv_mfma_kernel<P, MW, NW, MODE, X>), dim3(tiles), dim3(256), lds, s, a);
   return hipGetLastError();

@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <set>
 #include <string>
@@ -67,6 +68,16 @@ int npg_set_device(npg_ctx *ctx);
 int npg_noalloc_setup(npg_ctx *ctx);
 
 __host__ __device__ static inline size_t npg_align(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// A kernel's LDS limit is raised on every device it runs on: true the first
+// time the calling thread's current device (0..63) meets `done`, which then
+// records it (a caller whose attribute call fails returns that error).
+static inline bool npg_first_on_device(std::atomic<uint64_t> &done) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return true;
+  const uint64_t bit = 1ull << (dev & 63);
+  return !(done.fetch_or(bit) & bit);
+}
 
 // Carves consecutive 256-byte aligned pieces out of one scratch buffer.
 struct Carver {

@@ -135,13 +135,12 @@ template <int BPT, int NT, class LS>
 hipError_t launch_splat_t(const float2 *bnd, const LS &src, uint32_t L, int H, int W, int band_rows,
                           uint64_t *energy, uint32_t *count, int accumulate, uint32_t *err, hipStream_t s) {
   const size_t lds = sizeof(unsigned long long) * (size_t)band_rows * W;
-  static bool attr = false;
-  if (!attr) {
+  static std::atomic<uint64_t> attr{0};
+  if (npg_first_on_device(attr)) {
     hipError_t e = hipFuncSetAttribute((const void *)splat_kernel<BPT, NT, LS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        SPLAT_MAX_BINS * sizeof(unsigned long long));
     if (e != hipSuccess) return e;
-    attr = true;
   }
   dim3 grid(L, H / band_rows);
   hipLaunchKernelGGL((splat_kernel<BPT, NT, LS>), grid, dim3(NT), lds, s, bnd, src, H, W, band_rows,

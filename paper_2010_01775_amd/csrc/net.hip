@@ -745,8 +745,8 @@ struct F32P {
   // staging, the one staging that goes through registers
   static constexpr int SBP = 2;
   // B fragments straight from the packed weights in global memory (L2/L1
-  // resident, shared by every workgroup), one tap ahead in registers; the
-  // LDS then holds the patch only, which leaves room for more workgroups
+  // resident, shared by every workgroup), a few K steps ahead in registers;
+  // the LDS then holds the patch only, which leaves room for more workgroups
   static constexpr bool WGLB = true;
   __device__ static int row(int lg, int r) { return 4 * r + lg; }
   __device__ static int swz(int) { return 0; }
@@ -985,6 +985,11 @@ __device__ __forceinline__ void store_pooled(const ConvArgs &a, const typename P
   }
 }
 
+// no work to run late in a chunk's taps
+struct NoLate {
+  __device__ void operator()() const {}
+};
+
 // X: the extended form (dilation, ELU, residual link); without it the
 // layer is a plain 3x3 conv + ReLU and none of that code is compiled in.
 template <class P, int MW, int NW, int MODE, bool X = false>
@@ -1052,49 +1057,79 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     return p * stride + (((e / EPP) ^ P::swz(p)) * EPP) + e % EPP;
   };
 
-  // the nine taps of one K chunk on the staged patch (weights wg of the
-  // chunk); NT = 4: the four phase-merged taps of an upsampled chunk (mode 3)
-  auto taps = [&](const WT *wg, int NT) {
-    // WGLB: this lane's B values of a tap, [k step][n tile]; mode 3 reads
-    // binary64 weights (its phase-merged taps are binary64 sums)
-    using WR = std::conditional_t<MODE == 3, double, float>;
-    WR wcur[WGLB ? KC / 4 : 1][WGLB ? NW : 1], wnxt[WGLB ? KC / 4 : 1][WGLB ? NW : 1];
-    auto wld = [&](int i) -> WR {
-      if constexpr (MODE == 3) return reinterpret_cast<const double *>(wg)[i];
-      return wg[i];
-    };
+  // WGLB: this lane's B values (mode 3 reads binary64 weights: its
+  // phase-merged taps are binary64 sums) for the next R K steps (a K step
+  // is 4 channels of one tap) in a ring of R slots: step s sits in slot
+  // s % R until its matrix products are issued, then the slot is reloaded
+  // with step s + R.  R divides the K steps of a tap, so every slot is
+  // known at compile time and no register copies (which would wait for the
+  // loads in flight) are needed.  A chunk's first R steps (wfirst) are
+  // loaded before its patch is staged, so they arrive with it.
+  using WR = std::conditional_t<MODE == 3, double, float>;
+  constexpr int KS = KC / 4;
+  constexpr int R = NW >= 4 ? 2 : KS;
+  static_assert(KS % R == 0, "ring slots repeat every tap");
+  WR wr[WGLB ? R : 1][WGLB ? NW : 1];
+  auto wfetch = [&](const WT *wg, int step, WR (&dst)[WGLB ? NW : 1]) {
+#pragma unroll
+    for (int ni = 0; ni < NW; ++ni) {
+      const int i = (4 * step + lg) * BN + ni * 16 + lr;
+      if constexpr (MODE == 3)
+        dst[ni] = reinterpret_cast<const double *>(wg)[i];
+      else
+        dst[ni] = wg[i];
+    }
+  };
+  auto wfirst = [&](const WT *wg) {
     if constexpr (WGLB) {
 #pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-        for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wld((ks * 4 + lg) * BN + ni * 16 + lr);
+      for (int r = 0; r < R; ++r) wfetch(wg, r, wr[r]);
     }
-#pragma unroll 1
-    for (int tap = 0; tap < NT; ++tap) {
+  };
+  // the weights and the number of taps of chunk ch: phase-merged taps for
+  // upsampled channels in mode 3
+  struct ChunkW {
+    const WT *wg;
+    int nt;
+  };
+  auto chunk_w = [&](int ch) -> ChunkW {
+    if constexpr (MODE == 3) {
+      const bool up = ch * KC < a.src.C0;
+      return {reinterpret_cast<const WT *>(up ? static_cast<const double *>(a.wpp) + ((size_t)ch * 4 + wave) * 4 * KC * BN
+                                              : static_cast<const double *>(a.wpk64) + (size_t)ch * 9 * KC * BN),
+              up ? 4 : 9};
+    }
+    return {static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN, 9};
+  };
+
+  // the nine taps of one K chunk on the staged patch (weights wg of the
+  // chunk, its first R steps already in the ring); NT = 4: the four
+  // phase-merged taps of an upsampled chunk (mode 3).  late() runs once per
+  // chunk, right after the loads of its last step: vector loads retire in
+  // order, so a load issued there holds up no weight of the chunk
+  auto taps = [&](const WT *wg, int NT, auto &&late) {
+    constexpr int LKS = R < KS ? KS - 1 - R : KS - 1;  // K step and tap (from the end)
+    constexpr int LT = R < KS ? 1 : 2;                 // after which late() runs
+    auto one_tap = [&](int tap, auto has_late) {
       int toff;
       if constexpr (MODE == 3)
         toff = NT == 4 ? (tap >> 1) * PW + (tap & 1) + (wave >> 1) * PW + (wave & 1) : (tap / 3) * PW + (tap % 3);
       else
         toff = ((tap / 3) * PW + (tap % 3)) * DIL;
-      if constexpr (WGLB) {
-        if (tap + 1 < NT) {
-#pragma unroll
-          for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-            for (int ni = 0; ni < NW; ++ni)
-              wnxt[ks][ni] = wld(((tap + 1) * KC + ks * 4 + lg) * BN + ni * 16 + lr);
-        }
-      }
       if constexpr (IS_F32) {
 #pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks) {
+        for (int ks = 0; ks < KS; ++ks) {
           double av[MW], bv[NW];
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
             av[mi] = (double)patch[(bp[mi] + toff) * PSTR + ks * 4 + lg];
 #pragma unroll
-          for (int ni = 0; ni < NW; ++ni)
-            bv[ni] = (double)wcur[WGLB ? ks : 0][WGLB ? ni : 0];
+          for (int ni = 0; ni < NW; ++ni) bv[ni] = (double)wr[ks % R][ni];
+          // the step R ahead into the slot just read (steps past the chunk's
+          // last are not loaded)
+          if (ks + R < KS || tap + 1 < NT) wfetch(wg, tap * KS + ks + R, wr[ks % R]);
+          if constexpr (decltype(has_late)::value)
+            if (ks == LKS) late();
 #pragma unroll
           for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
@@ -1114,7 +1149,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
       } else {
-        if (tap & 1) continue;  // taps handled in pairs (tap, tap + 1)
+        if (tap & 1) return;  // taps handled in pairs (tap, tap + 1)
         // lanes 0-31 read tap `tap`, lanes 32-63 tap `tap + 1` (the tenth
         // tap has zero weights; its patch reads stay inside the patch)
         const int tl = tap + (lg >> 1);
@@ -1133,31 +1168,33 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
           for (int ni = 0; ni < NW; ++ni) acc[mi][ni] = P::mma(bv[ni], av[mi], acc[mi][ni]);
       }
-      if constexpr (WGLB) {
-#pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-          for (int ni = 0; ni < NW; ++ni) wcur[ks][ni] = wnxt[ks][ni];
-      }
+    };
+    // with a late() to run, the last LT taps are peeled off the loop, so the
+    // loads it issues are not pending (for the compiler's waits) at the top
+    // of the loop
+    constexpr bool HAS_LATE = !std::is_same_v<std::decay_t<decltype(late)>, NoLate>;
+    if constexpr (IS_F32 && HAS_LATE) {
+#pragma unroll 1
+      for (int tap = 0; tap < NT - LT; ++tap) one_tap(tap, std::false_type{});
+      if constexpr (LT == 2) one_tap(NT - 2, std::true_type{});
+      one_tap(NT - 1, std::bool_constant<LT == 1>{});
+    } else {
+#pragma unroll 1
+      for (int tap = 0; tap < NT; ++tap) one_tap(tap, std::false_type{});
     }
   };
 
-  // the taps of chunk ch: phase-merged for upsampled channels in mode 3
-  auto chunk_taps = [&](int ch, const WT *wg) {
-    int nt = 9;
-    if constexpr (MODE == 3) {
-      const bool up = ch * KC < a.src.C0;
-      nt = up ? 4 : 9;
-      wg = reinterpret_cast<const WT *>(up ? static_cast<const double *>(a.wpp) + ((size_t)ch * 4 + wave) * 4 * KC * BN
-                                           : static_cast<const double *>(a.wpk64) + (size_t)ch * 9 * KC * BN);
-    }
-    taps(wg, nt);  // one call site: one copy of the tap loop
+  auto chunk_taps = [&](int ch, auto &&late) {
+    const ChunkW c = chunk_w(ch);
+    taps(c.wg, c.nt, late);  // one call site: one copy of the tap loop
   };
 
   // FP64 tiles on plain or concatenated inputs whose patch has at most one
   // pixel per thread: the next chunk's pixel is loaded into registers while
-  // the matrix cores work on the current chunk (their weights come straight
-  // from global memory, so the patch is all there is to stage)
+  // the matrix cores work on the last two taps of the current chunk (their
+  // weights come straight from global memory, so the patch is all there is
+  // to stage; issued at the start of the chunk, the load would hold up the
+  // first tap's weights behind it)
   bool piped = false;
   if constexpr (WGLB && (MODE == 0 || MODE == 3)) {
     const int npx = TL * PH * PW;
@@ -1179,12 +1216,16 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
         }
       };
       uint4 nv[G];
+      wfirst(chunk_w(0).wg);
       load_px(0, nv);
       store_px(nv);
       __syncthreads();
       for (int ch = 0; ch < a.nchunk; ++ch) {
-        if (ch + 1 < a.nchunk) load_px(ch + 1, nv);
-        chunk_taps(ch, static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN);
+        chunk_taps(ch, [&] {
+          if (ch + 1 < a.nchunk) load_px(ch + 1, nv);
+        });
+        // the next chunk's first weights, in flight across the barriers
+        if (ch + 1 < a.nchunk) wfirst(chunk_w(ch + 1).wg);
         __syncthreads();
         if (ch + 1 < a.nchunk) {
           store_px(nv);
@@ -1218,6 +1259,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
       }
     };
     stage_w();
+    wfirst(chunk_w(ch).wg);
     // input patch with halo: straight into LDS for 8/16-bit tiles on plain
     // or concatenated inputs; otherwise through registers, in batches of SB
     // loads per thread, then the stores (pooled inputs, four loads per piece,
@@ -1337,7 +1379,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     // the LDS loads of this wavefront have landed; the barrier covers the others'
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    chunk_taps(ch, wg);
+    chunk_taps(ch, NoLate{});
     __syncthreads();
   }
 

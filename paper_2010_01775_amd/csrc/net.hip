@@ -55,7 +55,7 @@ struct LayerDev {
   float *pk32 = nullptr;       // [chunk][tap][kc16][cout]
   double *pkp = nullptr;       // [chunk][phase][tap 2x2][kc16][cout]: weights of a 3x3 conv on a
                                // nearest-upsampled input, merged per output phase (exact sums)
-  double *pk64 = nullptr;      // pk32 in binary64 (the concatenated chunks of such a conv)
+  double *pk64 = nullptr;      // pk32 in binary64 (read by some FP64 tiles)
   uint16_t *pk16 = nullptr;    // [chunk][tap][cout][kc32] (bf16 bits)
   uint16_t *pk16s = nullptr;   // [chunk][tap][cout][kc16] (bf16 bits)
   // FP8 (after calibration): e4m3 weights with the input channels' activation
@@ -312,9 +312,10 @@ extern "C" int npg_model_load(npg_ctx *ctx, const void *host_bytes, size_t n_byt
                 pp[((((size_t)c32 * 4 + ph) * 4 + t) * KC32 + k32) * y.cout + co] = v;
               }
         offs[i].pp = put(pp.data(), 8 * pp.size());
-        const std::vector<double> p64(p32.begin(), p32.end());
-        offs[i].p64 = put(p64.data(), 8 * p64.size());
       }
+      // binary64 copy (exact), read by the FP64 tiles that take binary64 weights
+      const std::vector<double> p64(p32.begin(), p32.end());
+      offs[i].p64 = put(p64.data(), 8 * p64.size());
       offs[i].p16 = put(p16.data(), 2 * p16.size());
       offs[i].p16s = put(p16s.data(), 2 * p16s.size());
     }
@@ -810,7 +811,7 @@ struct ConvArgs {
   int tiles_x, tiles_per_leaf;
   const void *wpk;
   const void *wpp = nullptr;   // phase-merged weights (upsampled chunks, staging mode 3)
-  const void *wpk64 = nullptr; // binary64 weights of the concatenated chunks (mode 3)
+  const void *wpk64 = nullptr; // binary64 packed weights (FP64 tiles: mode 3, 64 output channels)
   const float *bias;
   const float *head_w;   // non-null: fuse the 1x1 head + softplus (Cout == 16)
   float head_b;
@@ -1057,30 +1058,29 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
     return p * stride + (((e / EPP) ^ P::swz(p)) * EPP) + e % EPP;
   };
 
-  // WGLB: this lane's B values (mode 3 reads binary64 weights: its
-  // phase-merged taps are binary64 sums) for the next R K steps (a K step
+  // WGLB: this lane's B values for the next R K steps (a K step
   // is 4 channels of one tap) in a ring of R slots: step s sits in slot
   // s % R until its matrix products are issued, then the slot is reloaded
   // with step s + R.  R divides the K steps of a tap, so every slot is
   // known at compile time and no register copies (which would wait for the
   // loads in flight) are needed.  A chunk's first R steps (wfirst) are
-  // loaded before its patch is staged, so they arrive with it.
-  using WR = std::conditional_t<MODE == 3, double, float>;
+  // loaded before its patch is staged, so they arrive with it.  Mode 3
+  // reads binary64 weights (its phase-merged taps are binary64 sums); so do
+  // the 64-channel tiles (binary64 copies of the float32 weights), which
+  // spares them a conversion on the vector ALUs per weight (every vector
+  // instruction delays the FP64 matrix products of its SIMD) at no cost in
+  // wavefronts per SIMD; the other tiles would lose a wavefront to the
+  // wider registers and keep float32.
+  using WR = std::conditional_t<MODE == 3 || NW == 4, double, float>;
   constexpr int KS = KC / 4;
   constexpr int R = NW >= 4 ? 2 : KS;
   static_assert(KS % R == 0, "ring slots repeat every tap");
   WR wr[WGLB ? R : 1][WGLB ? NW : 1];
-  auto wfetch = [&](const WT *wg, int step, WR (&dst)[WGLB ? NW : 1]) {
+  auto wfetch = [&](const WR *wg, int step, WR (&dst)[WGLB ? NW : 1]) {
 #pragma unroll
-    for (int ni = 0; ni < NW; ++ni) {
-      const int i = (4 * step + lg) * BN + ni * 16 + lr;
-      if constexpr (MODE == 3)
-        dst[ni] = reinterpret_cast<const double *>(wg)[i];
-      else
-        dst[ni] = wg[i];
-    }
+    for (int ni = 0; ni < NW; ++ni) dst[ni] = wg[(4 * step + lg) * BN + ni * 16 + lr];
   };
-  auto wfirst = [&](const WT *wg) {
+  auto wfirst = [&](const WR *wg) {
     if constexpr (WGLB) {
 #pragma unroll
       for (int r = 0; r < R; ++r) wfetch(wg, r, wr[r]);
@@ -1089,17 +1089,18 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // the weights and the number of taps of chunk ch: phase-merged taps for
   // upsampled channels in mode 3
   struct ChunkW {
-    const WT *wg;
+    const WR *wg;
     int nt;
   };
   auto chunk_w = [&](int ch) -> ChunkW {
-    if constexpr (MODE == 3) {
-      const bool up = ch * KC < a.src.C0;
-      return {reinterpret_cast<const WT *>(up ? static_cast<const double *>(a.wpp) + ((size_t)ch * 4 + wave) * 4 * KC * BN
-                                              : static_cast<const double *>(a.wpk64) + (size_t)ch * 9 * KC * BN),
-              up ? 4 : 9};
+    if constexpr (std::is_same_v<WR, double>) {
+      if constexpr (MODE == 3) {
+        if (ch * KC < a.src.C0) return {static_cast<const double *>(a.wpp) + ((size_t)ch * 4 + wave) * 4 * KC * BN, 4};
+      }
+      return {static_cast<const double *>(a.wpk64) + (size_t)ch * 9 * KC * BN, 9};
+    } else {
+      return {static_cast<const float *>(a.wpk) + (size_t)ch * 9 * KC * BN, 9};
     }
-    return {static_cast<const WT *>(a.wpk) + (size_t)ch * 9 * KC * BN, 9};
   };
 
   // the nine taps of one K chunk on the staged patch (weights wg of the
@@ -1107,7 +1108,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // phase-merged taps of an upsampled chunk (mode 3).  late() runs once per
   // chunk, right after the loads of its last step: vector loads retire in
   // order, so a load issued there holds up no weight of the chunk
-  auto taps = [&](const WT *wg, int NT, auto &&late) {
+  auto taps = [&](const WR *wg, int NT, auto &&late) {
     constexpr int LKS = R < KS ? KS - 1 - R : KS - 1;  // K step and tap (from the end)
     constexpr int LT = R < KS ? 1 : 2;                 // after which late() runs
     auto one_tap = [&](int tap, auto has_late) {
@@ -1699,6 +1700,7 @@ hipError_t launch_mfma(const ConvArgs &a0, const Tiling &t, unsigned tiles, hipS
   const bool first = a0.src.mode == SRC_ENERGY;
   const size_t lds = conv_lds_bytes<P>(t, first);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (P::F64 && !a0.wpk64) return hipErrorInvalidValue;  // the FP64 tiles read the binary64 weights
   ConvArgs a = a0;
   a.wbytes = (int)conv_wts_bytes<P>(t);
   switch (t.NW * 10 + t.MW) {
@@ -1837,6 +1839,7 @@ struct Runner {
     hipError_t e;
     if (prec == NPG_FP32) {
       a.wpk = l1.pk32;
+      a.wpk64 = l1.pk64;
       e = launch_mfma<F32P>(a, t, tiles, s);
     } else if (prec == NPG_FP8) {
       a.wpk = l1.pk8s;
@@ -1932,11 +1935,11 @@ struct Runner {
       if (prec == NPG_FP32) {
         a.nchunk = (y.cin + KC32 - 1) / KC32;
         a.wpk = y.pk32;
+        a.wpk64 = y.pk64;
         // upsampled channels by phase (every tile here has even TR and TW)
-        if (src.mode == SRC_UPCAT && !head && y.dil == 1 && y.pkp && y.pk64 && !upsample_taps9 && t.TR % 2 == 0 &&
+        if (src.mode == SRC_UPCAT && !head && y.dil == 1 && y.pkp && !upsample_taps9 && t.TR % 2 == 0 &&
             t.TW % 2 == 0 && t.TL * t.TR * t.TW == 64 * t.MW) {
           a.wpp = y.pkp;
-          a.wpk64 = y.pk64;
           taps_x_cin = 4.0 * src.C0 + 9.0 * src.C1;
         }
         ctx->conv_flops[0] += 2.0 * px * y.cout * taps_x_cin;

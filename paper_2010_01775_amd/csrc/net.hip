@@ -1192,10 +1192,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
 
   // FP64 tiles on plain or concatenated inputs whose patch has at most one
   // pixel per thread: the next chunk's pixel is loaded into registers while
-  // the matrix cores work on the last two taps of the current chunk (their
-  // weights come straight from global memory, so the patch is all there is
-  // to stage; issued at the start of the chunk, the load would hold up the
-  // first tap's weights behind it)
+  // the matrix cores work on the current chunk's last K steps, after its
+  // last weight loads (the weights come straight from global memory, so the
+  // patch is all there is to stage; issued at the start of the chunk, the
+  // load would hold up the first tap's weights behind it)
   bool piped = false;
   if constexpr (WGLB && (MODE == 0 || MODE == 3)) {
     const int npx = TL * PH * PW;

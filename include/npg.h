@@ -132,6 +132,10 @@ void npg_conv_flops(npg_ctx *ctx, double *matrix, double *vector, int reset);
  *                  their nearest-upsampled channels instead of four
  *                  phase-merged taps per output phase (testing; default 0;
  *                  the results agree to rounding)
+ *   "tile_cap"     largest matrix-core tile, in units of 64 output pixels:
+ *                  1, 2, 4 or 8 (a value in between rounds down; default 4;
+ *                  a tuned table caps each layer further; testing: every
+ *                  tile shape gives identical results)
  * NPG_E_ARG for an unknown name or a negative value. */
 int npg_set_option(npg_ctx *ctx, const char *name, int64_t value);
 

@@ -121,7 +121,7 @@ int npg_set_option(npg_ctx *ctx, const char *name, int64_t value) {
   if (!ctx || !name) return NPG_E_ARG;
   const std::string n(name);
   if (n != "graphs" && n != "chunk_leaves" && n != "force_direct" && n != "fuse_first" &&
-      n != "upsample_taps9" && n != "pool_outputs")
+      n != "upsample_taps9" && n != "pool_outputs" && n != "tile_cap")
     return npg_fail(ctx, NPG_E_ARG, "unknown option '%s'", name);
   if (value < 0) return npg_fail(ctx, NPG_E_ARG, "option '%s' must be >= 0", name);
   ctx->opts[n] = value;

@@ -2326,6 +2326,8 @@ Runner make_runner(npg_ctx *ctx, const npg_model *m, npg_precision prec, hipStre
   R.upsample_taps9 = (int)ctx->opt("upsample_taps9", 0);
   R.fuse_first = ctx->opt("fuse_first", 1) ? 1 : 0;
   R.pool_outputs = ctx->opt("pool_outputs", 1) ? 1 : 0;
+  const long long cap = ctx->opt("tile_cap", 4);  // testing: pixel tiles of at most 64 * cap
+  R.mw_all = cap >= 8 ? 8 : cap >= 4 ? 4 : cap >= 2 ? 2 : 1;
   return R;
 }
 
@@ -2354,6 +2356,7 @@ void apply_tune(npg_ctx *ctx, Runner &R, int H, int W, std::vector<int> *hold) {
   if (it != ctx->tune.end() && it->second.size() > 1) {
     hold->assign(it->second.begin() + 1, it->second.end());
     R.mw_cap = hold;
+    R.mw_all = 8;  // the table's picks (up to 8, as probed) cap each call
   }
 }
 

@@ -200,3 +200,30 @@ def test_pooled_outputs_equal_pooled_staging(ctx, npg, prec, H, L):
     assert npg.sync_status(ctx) == 0
     assert torch.equal(ref, got)
     m.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("H,L", [(128, 5), (64, 23), (16, 21)])
+def test_every_tile_width_gives_same_bits(ctx, npg, prec, H, L):
+    """Every matrix-core tile width (option "tile_cap": at most 64, 128, 256
+    or 512 output pixels) gives the bits of the default tiles: in FP32 mode
+    the weight ring of 2 or 4 K steps with its peeled last taps, the patch
+    staged through registers (one pixel per thread) or straight into LDS,
+    the phase-merged decoder tiles and the fused first layer; ragged last
+    tile and an empty leaf."""
+    m = npg.Model(ctx, synth.unet_model(24, random_bias=True))
+    b = synth.uniform_batch(seed=51 + H, L=L, per_leaf=3000, H=H, W=H, n_queries=8, model=b"")
+    e, _ = npg.splat_histograms(ctx, tf(b.dirs), t32(b.w), t32(b.leaf_off), H, H, want_count=False)
+    e[L // 2].zero_()
+    if prec == "fp8":
+        m.calibrate_fp8(e)
+    ref = npg.reconstruct_density(ctx, m, e, prec).cpu()
+    try:
+        for cap in (1, 2, 8):
+            ctx.set_option("tile_cap", cap)
+            got = npg.reconstruct_density(ctx, m, e, prec).cpu()
+            assert npg.sync_status(ctx) == 0
+            assert torch.equal(ref, got), cap
+    finally:
+        ctx.set_option("tile_cap", 4)
+    m.free()

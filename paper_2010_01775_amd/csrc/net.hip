@@ -1071,7 +1071,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(ConvArgs a) {
   // instruction delays the FP64 matrix products of its SIMD) at no cost in
   // wavefronts per SIMD; the other tiles would lose a wavefront to the
   // wider registers and keep float32.
-  using WR = std::conditional_t<MODE == 3 || NW == 4, double, float>;
+  using WR = std::conditional_t<WGLB && (MODE == 3 || NW == 4), double, float>;
   constexpr int KS = KC / 4;
   constexpr int R = NW >= 4 ? 2 : KS;
   static_assert(KS % R == 0, "ring slots repeat every tap");

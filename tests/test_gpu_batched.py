@@ -227,3 +227,15 @@ def test_every_tile_width_gives_same_bits(ctx, npg, prec, H, L):
     finally:
         ctx.set_option("tile_cap", 4)
     m.free()
+
+
+def test_options_checked(ctx, npg):
+    """Context tunables: every documented name is accepted; an unknown name
+    or a negative value is an argument error."""
+    for name, value in (("graphs", 0), ("chunk_leaves", 0), ("force_direct", 0), ("fuse_first", 1),
+                        ("upsample_taps9", 0), ("pool_outputs", 1), ("tile_cap", 4)):
+        ctx.set_option(name, value)
+    for name, value in (("tile_size", 4), ("tile_cap", -1), ("", 1)):
+        with pytest.raises(npg.NpgError) as ei:
+            ctx.set_option(name, value)
+        assert ei.value.code == npg.E_ARG, (name, value)

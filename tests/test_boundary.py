@@ -50,3 +50,18 @@ def test_no_oracle_in_product():
                 txt = open(os.path.join(dp, f)).read()
                 for pat in (r"import\s+oracle", r"from\s+oracle", r"npg_oracle", r"\bor_(splat|build_cdf|sample|eval_pdf|net_forward|build_tree|bin_dirs)\b"):
                     assert not re.search(pat, txt), (os.path.join(dp, f), pat)
+
+
+def test_every_option_documented():
+    """Each name npg_set_option accepts is described in the header's list of
+    context tunables, and the header describes no name it rejects."""
+    api = open(os.path.join(ROOT, "paper_2010_01775_amd", "csrc", "api.hip")).read()
+    body = api[api.index("int npg_set_option("):]
+    body = body[:body.index("unknown option")]
+    accepted = set(re.findall(r'n != "([a-z_0-9]+)"', body))
+    assert {"graphs", "chunk_leaves", "tile_cap"} <= accepted
+    hdr = open(os.path.join(ROOT, "include", "npg.h")).read()
+    block = hdr[hdr.index("/* Context tunables"):]
+    block = block[:block.index("*/")]
+    documented = set(re.findall(r'^ \*   "([a-z_0-9]+)"', block, re.M))
+    assert accepted == documented, (accepted ^ documented)
